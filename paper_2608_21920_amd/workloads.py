@@ -1,0 +1,64 @@
+"""Seeded synthetic workloads: the input parameters of each benchmark case.
+
+This module holds inputs only (grid sizes, physical parameters, seeds).  It
+contains none of the method's arithmetic, so both the HIP path and the CPU
+oracle can be driven from it.  The physical inputs follow the statement of the
+problem in Sects. 2-3 and 6.1 of the paper: a 1D gap of N cells with Courant
+number 0.45 and H = 0.8 L, driven by alpha * j_co, with curvature QED set by
+B/B_Q and the curvature radius.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Shared defaults (dx in skin depths d = c/omega_p,co).
+BASE = dict(dx=0.25, cfl=0.45, period_s=1.0, h_gap_frac=0.8, ppc_ref=16, x_thr=2.0, xc_floor=1e-2,
+            lambda_c_scale=1.0, r_curv_scale=1.0, inj_rate=0.0, inj_weight=1.0, u_init=0.0,
+            merge_frac=0.9, nsub_max=64, merge_every=64, seed=0, flags=0)
+
+# Tiny gap: 1024 cells, 16 e- + 16 e+ per cell at rest, alpha = 1.5, b = 0.1,
+# R_curv = 1e7 cm.  The Compton wavelength and the curvature radius are
+# rescaled (lambda~ = 4.84e-6 d, R~ = 103 d) so that the energy-scale
+# hierarchy of Sect. 4 (gamma_thr ~ 300 < gamma_rad ~ 3e3) fits in 500 steps
+# and pairs appear after about 100 steps.
+TINY = dict(BASE, n_cells=1024, init_kind=1, ppc_init=16, alpha=1.5, b=0.1, r_curv_cm=1e7,
+            r_curv_scale=1.4e-5, lambda_c_scale=1.7e5, seed=0, steps=500,
+            cap_leptons=4 << 20, cap_photons=4 << 20)
+
+# Production gap: 65536 cells, vacuum below H and e- at n_co above (16 per
+# cell), cold e- injected at the surface at 0.1 n_co dx per step, physical QED
+# (b = 0.1, R_curv = 1e7 cm), merging above 0.9 of the 5e7 cap.
+PRODUCTION = dict(BASE, n_cells=65536, init_kind=0, ppc_init=16, alpha=1.5, b=0.1, r_curv_cm=1e7,
+                  inj_rate=0.1, seed=0, steps=100000, cap_leptons=50_000_000, cap_photons=50_000_000,
+                  merge=True)
+
+# Full-scale gap: 262144 cells, b = 0.2, caps 2e8.
+FULL = dict(BASE, n_cells=262144, init_kind=0, ppc_init=16, alpha=1.5, b=0.2, r_curv_cm=1e7,
+            inj_rate=0.1, seed=0, steps=200000, cap_leptons=200_000_000, cap_photons=200_000_000,
+            merge=True)
+
+# Differentiable window: 16384 cells, 122 e- + 122 e+ per cell (4.0e6
+# leptons), rescaled QED as TINY, injection on, 2000 steps, checkpoints / 100.
+ADJOINT = dict(BASE, n_cells=16384, init_kind=1, ppc_init=122, ppc_ref=16, alpha=1.5, b=0.1,
+               r_curv_cm=1e7, r_curv_scale=1.4e-5, lambda_c_scale=1.7e5, inj_rate=0.1, seed=0,
+               steps=2000, ckpt_every=100, cap_leptons=16_000_000, cap_photons=16_000_000)
+
+
+def batched_tubes(n_tubes: int = 256, seed: int = 1) -> list[dict]:
+    """Independent flux tubes of uneven size (the batched ensemble).
+
+    Cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q
+    log-uniform in [0.01, 0.3], initial particles per cell per species
+    uniform in [4, 64]; drawn with numpy's generator from ``seed``.  Each
+    tube starts from uniform e+- at rest with physical QED (R_curv = 1e7 cm)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n_tubes):
+        n = int(rng.integers(2048, 16385))
+        alpha = float(rng.uniform(-1.0, 2.0))
+        b = float(np.exp(rng.uniform(np.log(0.01), np.log(0.3))))
+        ppc = int(rng.integers(4, 65))
+        out.append(dict(BASE, n_cells=n, init_kind=1, ppc_init=ppc, alpha=alpha, b=b, r_curv_cm=1e7,
+                        seed=int(seed) * 100003 + t, steps=20000,
+                        cap_leptons=max(4 * 2 * ppc * n, 1 << 16), cap_photons=max(2 * ppc * n, 1 << 16)))
+    return out
