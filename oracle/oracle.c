@@ -149,6 +149,9 @@ static void draw(uint64_t seed, uint64_t id, int64_t step, uint32_t tag, uint32_
 /* 24-bit uniform on the open interval (0,1): midpoint of the k-th bin. */
 static double u24(uint32_t r) { return ((double)(r >> 8) + 0.5) / 16777216.0; }
 
+/* Positions drawn at random sit on the 2^-24 grid of a cell: xi = k 2^-24. */
+static double xi24(uint32_t r) { return (double)(r >> 8) / 16777216.0; }
+
 static uint64_t child_id(uint64_t seed, uint64_t parent, int64_t step, uint32_t j) {
   uint32_t r[4];
   draw(seed, parent, step, TAG_CHILD, j, r);
@@ -295,7 +298,9 @@ static int64_t wt_fixed(double w) { return (int64_t)llrint(fabs(w) * ORC_FP_ONE)
 
 static void deposit_one(orc_sim* s, int32_t k, double xi, double w) {
   int64_t T = wt_fixed(w);
-  int64_t A = (int64_t)floor((double)T * xi + 0.5);
+  /* round(T xi), half up; long double keeps T xi exact when xi is on the
+   * 2^-24 grid and |w| < 2^16 */
+  int64_t A = (int64_t)floorl((long double)T * (long double)xi + 0.5L);
   int64_t sg = w < 0 ? -1 : 1;
   int32_t k1 = k + 1;
   if ((s->p.flags & ORC_PERIODIC) && k1 == s->N) k1 = 0;
@@ -365,7 +370,7 @@ static void init_particles(orc_sim* s) {
       for (int j = 0; j < p->ppc_init; ++j, ++id) {
         uint32_t r[4];
         draw(p->seed, id, 0, TAG_INIT, 0, r);
-        olep l = {k, u24(r[0]), p->u_init, sign[sp], id};
+        olep l = {k, xi24(r[0]), p->u_init, sign[sp], id};
         push_lep(s, l);
       }
 }
@@ -545,7 +550,7 @@ static void step_once(orc_sim* s) {
       uint64_t id = INJ_ID_BASE + s->inj_count++;
       uint32_t r[4];
       draw(p->seed, id, n, TAG_INJ, 0, r);
-      olep l = {0, u24(r[0]), 0.0, -p->inj_weight, id};
+      olep l = {0, xi24(r[0]), 0.0, -p->inj_weight, id};
       if (push_lep(s, l)) s->dq += wt_fixed(p->inj_weight);   /* E_s -= Q_inj, Q_inj < 0 */
     }
   }
