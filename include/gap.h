@@ -1,0 +1,189 @@
+/*
+ * gap.h -- C ABI of libgap: the per-step particle loop of the 1D radiative
+ * PIC of a pulsar polar-cap pair discharge (Nattila & Salmi), on one
+ * MI355X (gfx950) GPU.
+ *
+ * One step of a flux tube (Sects. 2.2, 3, 4 and 6.1 of the paper):
+ *   1. inject cold electrons at the stellar surface (atmosphere supply, Sect. 2.3);
+ *   2. gather E_parallel and kick every lepton, du/dt = q E (Sect. 4, beads on a wire);
+ *   3. curvature emission by Monte Carlo with recoil (Sect. 3.1 eqs. tau_syn,
+ *      P_curv, x_curv; QED only below H_gap, Sect. 6.1);
+ *   4. drift, absorption at h = 0, free outflow at h = L;
+ *   5. charge-conserving fixed-point deposit (first-order shape, Sect. 6.1);
+ *   6. photon free streaming and one-photon pair creation (Sect. 3.2 eq. tau_bw,
+ *      accumulated angle sin(psi) = |sin(s/R_curv)|, Sect. 6.1);
+ *   7. new pairs and photons compacted into the particle stores;
+ *   8. field: Ampere drive alpha j_co and surface flux enter the surface field
+ *      E_s, then Gauss's law dE/dh = rho - eta_co (Sect. 2.2) by an integer scan.
+ *
+ * Units: lengths in d = c/omega_p,co, times in 1/omega_p,co, c = 1,
+ * u = gamma beta, E in m_e c omega_p,co / e, charge density in e n_co,
+ * omega_p,co^2 = Omega omega_B with Omega = 2 pi / period (Sect. 2.2).
+ *
+ * Conventions for every entry point:
+ *  - return 0 on success, a negative GAP_E* code otherwise; no exceptions
+ *    cross the ABI;
+ *  - device work is enqueued on the HIP stream given to gap_init and runs
+ *    asynchronously; errors raised on the device are sticky and reported by
+ *    the next call that synchronises (gap_sync, gap_diag, gap_set_state);
+ *  - one handle must not be used from two host threads at once.
+ */
+#ifndef GAP_H
+#define GAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define GAP_OK        0
+#define GAP_EINVAL   (-1)  /* invalid argument or parameter                          */
+#define GAP_ENOMEM   (-2)  /* device or host allocation failed                       */
+#define GAP_ECAP     (-3)  /* a particle store overflowed: particles were dropped    */
+#define GAP_ETILE    (-4)  /* a particle left its tile window (rebucket too rare)    */
+#define GAP_ENAN     (-5)  /* non-finite field                                       */
+#define GAP_EDEVICE  (-6)  /* HIP runtime error                                      */
+#define GAP_ESTATE   (-7)  /* call not valid in the current state                    */
+
+/* flags (gap_params.flags) */
+#define GAP_QED_OFF      1u     /* no emission, no conversion                          */
+#define GAP_ETA_CO_OFF   2u     /* no co-rotation background charge in Gauss's law     */
+#define GAP_FIELD_FROZEN 4u     /* E is not updated (set with gap_set_state)           */
+#define GAP_RECOIL_OFF   8u     /* emission leaves the lepton momentum unchanged      */
+#define GAP_PERIODIC     16u    /* periodic box; mean field advanced by Ampere's law   */
+#define GAP_MERGE_ON     32u    /* weight-doubling merge above merge_frac * cap        */
+#define GAP_TRACK_ALL    64u    /* store every emitted photon, also below x_thr        */
+#define GAP_ANTI_ALIGNED 128u   /* eta_co = +e n_co instead of -e n_co                 */
+#define GAP_CONV_OFF     1024u  /* photons never convert                               */
+#define GAP_EMIT_OFF     2048u  /* leptons never emit                                  */
+
+/* initial states (gap_params.init_kind) */
+#define GAP_INIT_GAP      0  /* vacuum below H, electrons at ppc_init per cell above H  */
+#define GAP_INIT_UNIFORM  1  /* ppc_init electrons and ppc_init positrons in every cell */
+#define GAP_INIT_EMPTY    2  /* no particles                                            */
+#define GAP_INIT_ELECTRON 3  /* ppc_init electrons in every cell                        */
+
+/* Physical inputs of one flux tube (the statement of the problem in Sects.
+ * 2-3 and 6.1: grid, alpha, B/B_Q, curvature radius, injection, QED knobs). */
+typedef struct gap_params {
+  int32_t n_cells;        /* N >= 2                                                    */
+  int32_t init_kind;      /* GAP_INIT_*                                                */
+  int32_t ppc_init;       /* initial macro-particles per cell per species              */
+  int32_t ppc_ref;        /* macro-particles per cell at n_co; w0 = dx / ppc_ref       */
+  double dx;              /* cell size in skin depths                                  */
+  double cfl;             /* c dt / dx, 0 < cfl < 1                                    */
+  double alpha;           /* j_m / j_co                                                */
+  double b;               /* B / B_Q                                                   */
+  double r_curv_cm;       /* curvature radius of the field line [cm]                   */
+  double period_s;        /* rotation period [s] (sets n_co)                           */
+  double lambda_c_scale;  /* multiplies lambda_C / d (1 = physical)                    */
+  double r_curv_scale;    /* multiplies R_curv / d (1 = physical)                      */
+  double h_gap_frac;      /* H = h_gap_frac * N * dx; QED only below H                 */
+  double inj_rate;        /* injected charge per step in units of n_co dx              */
+  double inj_weight;      /* weight of one injected macro-electron (units of w0)       */
+  double x_thr;           /* photons below this energy (m_e c^2) are not stored         */
+  double xc_floor;        /* emission is evaluated only where x_c(gamma) >= xc_floor   */
+  double u_init;          /* momentum of the initial particles                         */
+  double merge_frac;      /* merge when a store holds more than merge_frac * cap       */
+  uint64_t seed;          /* Philox key                                                */
+  int64_t cap_leptons;    /* capacity of the lepton store (live particles)             */
+  int64_t cap_photons;    /* capacity of the photon store                              */
+  uint32_t flags;         /* GAP_* flags                                               */
+  int32_t nsub_max;       /* cap on Monte Carlo sub-steps per step (>= 1)               */
+  int32_t merge_every;    /* steps between merge checks                                */
+  int32_t rebucket_every; /* steps between re-sorts of the stores (0 = automatic)       */
+} gap_params;
+
+/* Optional device allocator (e.g. backed by torch's caching allocator). */
+typedef struct gap_allocator {
+  void* (*alloc)(size_t bytes, void* ctx);   /* returns device memory or NULL */
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} gap_allocator;
+
+typedef struct gap_t gap_t;
+
+/* Create n_tubes >= 1 independent flux tubes described by p[0..n_tubes-1]
+ * (host array, read during the call), place the initial particles and solve
+ * the initial field.  stream: a hipStream_t (NULL = the null stream); all
+ * device work of the handle is enqueued on it.  alloc: NULL = hipMalloc.
+ * The handle owns all device buffers.  On success *out receives the handle. */
+int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_allocator* alloc, gap_t** out);
+
+/* Advance every tube by n_steps >= 0 steps (asynchronous, on the stream). */
+int gap_step(gap_t* g, int64_t n_steps);
+
+/* Capture the next n_steps of gap_step into a HIP graph and replay it; same
+ * result as gap_step(g, n_steps).  Graph replays are reused while
+ * n_steps stays the same. */
+int gap_step_graph(gap_t* g, int64_t n_steps);
+
+/* Wait for all queued work; return the sticky device error (or 0). */
+int gap_sync(gap_t* g);
+
+/* diagnostic kinds for gap_diag (layout of host_buf) */
+#define GAP_DIAG_COUNTS   0  /* int64[32]: see GAP_C_* below                              */
+#define GAP_DIAG_FIELD    1  /* float[N]: E at cell centres k+1/2                          */
+#define GAP_DIAG_ES       2  /* double[1]: surface field (periodic: mean field)             */
+#define GAP_DIAG_RHO      3  /* int64[N+1]: node charge of the last deposit (2^-24 w0 units) */
+#define GAP_DIAG_LEPTONS  4  /* n x {int32 cell, uint32 frac24, float u, float w, uint64 id}  */
+#define GAP_DIAG_PHOTONS  5  /* n x {int32 cell, uint32 frac24, float x, float w, int32 n0,
+                                     int32 pad, uint64 id}                                 */
+#define GAP_DIAG_NODE_E   6  /* float[N+1]: node field used by the gather                   */
+#define GAP_DIAG_DERIVED  7  /* double[8]: d_cm, lambda~, R~, dt, H, w0, s_co, N            */
+
+/* indices of GAP_DIAG_COUNTS */
+#define GAP_C_LEPTONS     0   /* live leptons                      */
+#define GAP_C_PHOTONS     1   /* live photons                      */
+#define GAP_C_STEP        2   /* steps taken                       */
+#define GAP_C_EMIT        3   /* emission events                   */
+#define GAP_C_PHO_BORN    4   /* photons stored                    */
+#define GAP_C_CONV        5   /* conversions                       */
+#define GAP_C_ABSORBED    6   /* leptons absorbed at h = 0         */
+#define GAP_C_OUTFLOW     7   /* leptons leaving at h = L          */
+#define GAP_C_PHO_EXIT    8   /* photons leaving the QED zone      */
+#define GAP_C_DROPPED     9   /* particles dropped (store full)    */
+#define GAP_C_MERGED      10  /* merge events                      */
+#define GAP_C_ERR         11  /* sticky error code                 */
+#define GAP_C_INJECTED    12  /* injected electrons                */
+#define GAP_C_EMIT_EVAL   13  /* lepton-steps that evaluated emission (read the id) */
+#define GAP_C_CONV_EVAL   14  /* photon-steps that evaluated conversion (read id, w) */
+#define GAP_C_LEP_STEPS   15  /* lepton-steps taken                */
+#define GAP_C_PHO_STEPS   16  /* photon-steps taken                */
+#define GAP_C_REBUCKETS   17  /* re-sorts of the stores            */
+
+/* Copy a diagnostic of tube `tube` into host_buf (buf_bytes long); waits for
+ * queued work.  *bytes_written receives the size used.  GAP_EINVAL if the
+ * buffer is too small (then *bytes_written holds the size needed). */
+int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_bytes, size_t* bytes_written);
+
+/* state kinds for gap_set_state */
+#define GAP_STATE_PARTICLES 0  /* host_buf: int64 nl, int64 np, then nl lepton records and np
+                                  photon records in the GAP_DIAG_LEPTONS / PHOTONS layouts     */
+#define GAP_STATE_ES_STEP   1  /* double E_s, then int64 step                                  */
+#define GAP_STATE_FIELD     2  /* float E[N] then double E_s (for GAP_FIELD_FROZEN runs)       */
+#define GAP_STATE_INJECTION 3  /* double accumulator, then uint64 injected count              */
+
+/* Replace part of the state of tube `tube` (only valid when n_tubes == 1).
+ * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
+ * the field from the current E_s.  Waits for queued work. */
+int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);
+
+/* Release the handle and every buffer it owns (waits for queued work). */
+void gap_free(gap_t* g);
+
+/* Static description of an error code. */
+const char* gap_strerror(int code);
+
+/* Host utility: invert the cumulative classical synchrotron photon-number
+ * spectrum with the library's own table (the sampler the device uses):
+ * xi[i] = C^-1(r[i]) for r in (0,1).  Host pointers; no device work. */
+int gap_sync_inverse_host(const float* r, float* xi, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAP_H */

@@ -1,0 +1,909 @@
+// gap.hip -- host side of libgap: parameter derivation, device state, the
+// step sequence, re-sorting of the particle stores, diagnostics and the C ABI
+// declared in include/gap.h.
+#include "gap.h"
+#include "gap_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace gap;
+
+namespace {
+
+// ---------------------------------------------------------------- constants
+// CGS values (CODATA); the unit system follows Sect. 2.2 of the paper:
+// omega_p,co^2 = Omega omega_B, d = c / omega_p,co.
+constexpr double kC = 2.99792458e10;
+constexpr double kEoverMC = 1.75882001076e7;
+constexpr double kLambdaC = 3.8615926796e-11;
+constexpr double kBQ = 4.41400e13;
+constexpr double kAlphaEM = 1.0 / 137.035999084;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwo24 = 16777216.0;
+
+constexpr int kGrid = 2048;        // workgroups of the particle passes (multiple of 8)
+
+// ---------------------------------------------------------------- spectrum table
+// Cumulative classical synchrotron photon-number spectrum C(xi) =
+// (3/(5 pi)) int_0^xi dxi' int_xi'^inf K_{5/3}.  From the integral
+// representation of K_nu, 1 - C(xi) = (3/(5 pi)) int_0^inf exp(-xi cosh s)
+// cosh(5s/3) / cosh^2 s ds, evaluated here with Simpson's rule.
+struct SyncQuad {
+  std::vector<double> wg, ch;
+  SyncQuad() {
+    const double h = 1.0 / 32.0;
+    const int n = 48 * 32;  // s in [0, 48], n even
+    wg.resize(n + 1);
+    ch.resize(n + 1);
+    for (int i = 0; i <= n; ++i) {
+      const double s = i * h;
+      const double c = std::cosh(s);
+      const double simpson = (i == 0 || i == n) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+      ch[i] = c;
+      wg[i] = simpson * h / 3.0 * std::cosh(5.0 * s / 3.0) / (c * c) * 3.0 / (5.0 * kPi);
+    }
+  }
+  // tail = 1 - C(xi); dens = -d tail / d xi = dC/dxi
+  void eval(double xi, double* tail, double* dens) const {
+    double t = 0.0, d = 0.0;
+    for (size_t i = 0; i < wg.size(); ++i) {
+      const double a = xi * ch[i];
+      if (a > 700.0) break;
+      const double e = std::exp(-a) * wg[i];
+      t += e;
+      d += e * ch[i];
+    }
+    *tail = t;
+    *dens = d;
+  }
+};
+
+// Solve tail(xi) = target (target in (0,1)) for log(xi), Newton with a bracket.
+double solve_tail(const SyncQuad& q, double target, bool use_cdf) {
+  double lo = -110.0, hi = 6.0;
+  double y = use_cdf ? 3.0 * std::log(std::max(1.0 - target, 1e-300) / 1.2316) : std::log(std::max(-std::log(target), 1e-3));
+  if (!(y > lo && y < hi)) y = 0.5 * (lo + hi);
+  for (int it = 0; it < 300; ++it) {
+    double t, d;
+    const double xi = std::exp(y);
+    q.eval(xi, &t, &d);
+    // g(y) = log tail - log target, decreasing in y
+    double g, dg;
+    if (use_cdf) {           // for small C compare C = 1 - tail directly
+      g = (1.0 - target) - (1.0 - t);   // C_target - C(xi): decreasing in y
+      dg = -d * xi;
+    } else {
+      g = std::log(t) - std::log(target);
+      dg = -d * xi / t;
+    }
+    if (g > 0) lo = y; else hi = y;
+    double yn = y - g / dg;
+    if (!(yn > lo && yn < hi) || !std::isfinite(yn)) yn = 0.5 * (lo + hi);
+    if (std::fabs(yn - y) < 1e-13 || hi - lo < 1e-13) return std::exp(yn);
+    y = yn;
+  }
+  return std::exp(y);
+}
+
+const std::vector<float>& sync_table() {
+  static std::vector<float> tab;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    SyncQuad q;
+    tab.assign(2 * (NTAB + 1), 0.0f);
+    for (int i = 1; i <= NTAB; ++i) {
+      const double r = 0.5 * i / NTAB;                         // C(xi) = r
+      tab[i] = (float)std::cbrt(solve_tail(q, 1.0 - r, true));
+    }
+    for (int i = 0; i <= NTAB; ++i) {
+      const double y = TAB_YLO + (double)i * (TAB_YHI - TAB_YLO) / NTAB;   // tail = e^-y
+      tab[NTAB + 1 + i] = (float)solve_tail(q, std::exp(-y), false);
+    }
+  });
+  return tab;
+}
+
+// host copy of the device sampler (same table, same interpolation)
+float sync_sample_host(float r, const float* tab) {
+  if (r <= 0.5f) {
+    float t = r * (2.0f * NTAB);
+    int i = std::min((int)t, NTAB - 1);
+    float f = t - (float)i;
+    float v = tab[i] + f * (tab[i + 1] - tab[i]);
+    return v * v * v;
+  }
+  float y = -std::log(1.0f - r);
+  float t = (y - TAB_YLO) * ((float)NTAB / (TAB_YHI - TAB_YLO));
+  t = std::fmin(std::fmax(t, 0.0f), (float)NTAB - 1e-3f);
+  int i = (int)t;
+  float f = t - (float)i;
+  const float* h = tab + NTAB + 1;
+  return h[i] + f * (h[i + 1] - h[i]);
+}
+
+// ---------------------------------------------------------------- state
+struct Store {
+  Ctl* ctl = nullptr;
+  int cur = 0;
+  uint32_t* pos[2] = {nullptr, nullptr};
+  float* a[2] = {nullptr, nullptr};      // u (leptons) or x (photons)
+  float* w[2] = {nullptr, nullptr};
+  int32_t* n0[2] = {nullptr, nullptr};   // photons only
+  uint64_t* id[2] = {nullptr, nullptr};
+  int32_t* tt = nullptr;
+  int32_t* chunk[2] = {nullptr, nullptr};
+  int32_t* tcount = nullptr;
+  int32_t* tcursor = nullptr;
+  long long* tchunk = nullptr;
+  int64_t capacity = 0, limit = 0, cap_live = 0;
+  LepBuf lep(int b) const { return LepBuf{pos[b], a[b], w[b], id[b]}; }
+  PhoBuf pho(int b) const { return PhoBuf{pos[b], a[b], w[b], n0[b], id[b]}; }
+};
+
+struct Derived { double d_cm, lam, rc, dt, H, w0, s_co; int N; };
+
+}  // namespace
+
+struct gap_t {
+  int n_tubes = 0;
+  hipStream_t s = nullptr;
+  gap_allocator al{};
+  bool custom_alloc = false;
+  std::vector<void*> owned;
+  std::vector<gap_params> P;
+  std::vector<Derived> D;
+  std::vector<Tube> th;
+  std::vector<Tile> tiles_h;
+  std::vector<FBlk> fb_h;
+  Tube* tubes = nullptr;
+  Tile* tiles = nullptr;
+  int n_tiles = 0;
+  long long total_nodes = 0, total_cells = 0;
+  long long* rho = nullptr;
+  long long* rho_last = nullptr;
+  float* E = nullptr;
+  float* ebar = nullptr;
+  FBlk* fb = nullptr;
+  int n_fb = 0;
+  long long* part = nullptr;
+  long long* part2 = nullptr;
+  float* tab = nullptr;
+  int* err = nullptr;
+  long long* live = nullptr;
+  Store lep, pho;
+  int R = 64;
+  int64_t since_rb = 0;
+  bool any_periodic = false;
+  int sticky = 0;
+  // graph: replay is valid from the recorded start state and leaves the end state
+  hipGraphExec_t gexec = nullptr;
+  int64_t gsteps = -1;
+  int gs_l = -1, gs_p = -1, ge_l = -1, ge_p = -1;
+  int64_t gs_since = -1, ge_since = -1;
+};
+
+namespace {
+
+int from_hip(hipError_t e) { return e == hipSuccess ? GAP_OK : GAP_EDEVICE; }
+#define HIPCHK(x) do { hipError_t _e = (x); if (_e != hipSuccess) return GAP_EDEVICE; } while (0)
+
+void* dalloc(gap_t* g, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (g->custom_alloc) p = g->al.alloc(bytes, g->al.ctx);
+  else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  if (p) {
+    g->owned.push_back(p);
+    (void)hipMemsetAsync(p, 0, bytes, g->s);
+  }
+  return p;
+}
+
+void release(gap_t* g) {
+  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
+  if (g->s) (void)hipStreamSynchronize(g->s);
+  for (void* p : g->owned) {
+    if (g->custom_alloc) g->al.free(p, g->al.ctx);
+    else (void)hipFree(p);
+  }
+  g->owned.clear();
+}
+
+int validate(const gap_params& p) {
+  if (p.n_cells < 2 || p.n_cells > (1 << 26)) return GAP_EINVAL;
+  if (!(p.dx > 0) || !(p.cfl > 0 && p.cfl < 1.0)) return GAP_EINVAL;
+  if (p.ppc_ref < 1 || p.ppc_init < 0) return GAP_EINVAL;
+  if (!(p.b > 0) || !(p.r_curv_cm > 0) || !(p.period_s > 0)) return GAP_EINVAL;
+  if (!(p.lambda_c_scale > 0) || !(p.r_curv_scale > 0)) return GAP_EINVAL;
+  if (!(p.h_gap_frac >= 0)) return GAP_EINVAL;
+  if (p.init_kind < 0 || p.init_kind > 3) return GAP_EINVAL;
+  if (!(p.inj_rate >= 0) || !(p.inj_weight > 0) || p.inj_weight >= 65536.0) return GAP_EINVAL;
+  if (p.cap_leptons < 1 || p.cap_photons < 1) return GAP_EINVAL;
+  if (p.nsub_max < 1 || p.nsub_max > 64) return GAP_EINVAL;
+  if (p.rebucket_every < 0) return GAP_EINVAL;
+  if (!(p.merge_frac > 0)) return GAP_EINVAL;
+  return GAP_OK;
+}
+
+Derived derive(const gap_params& p) {
+  Derived d{};
+  const double omega = 2.0 * kPi / p.period_s;
+  const double omega_b = kEoverMC * p.b * kBQ;
+  d.d_cm = kC / std::sqrt(omega * omega_b);
+  d.lam = kLambdaC / d.d_cm * p.lambda_c_scale;
+  d.rc = p.r_curv_cm / d.d_cm * p.r_curv_scale;
+  d.dt = p.cfl * p.dx;
+  d.H = p.h_gap_frac * p.n_cells * p.dx;
+  d.w0 = p.dx / p.ppc_ref;
+  d.s_co = (p.flags & GAP_ANTI_ALIGNED) ? 1.0 : -1.0;
+  d.N = p.n_cells;
+  return d;
+}
+
+int64_t init_k_lo(const gap_params& p, const Derived& d) {
+  if (p.init_kind == GAP_INIT_GAP) return (int64_t)std::ceil(d.H / p.dx - 1e-9);
+  return 0;
+}
+
+int64_t init_count(const gap_params& p, const Derived& d) {
+  const int64_t ncell = std::max<int64_t>(0, p.n_cells - init_k_lo(p, d));
+  switch (p.init_kind) {
+    case GAP_INIT_GAP: return ncell * p.ppc_init;
+    case GAP_INIT_UNIFORM: return 2 * ncell * p.ppc_init;
+    case GAP_INIT_ELECTRON: return ncell * p.ppc_init;
+    default: return 0;
+  }
+}
+
+Ctx make_ctx(gap_t* g) {
+  Ctx c;
+  c.tubes = g->tubes;
+  c.tiles = g->tiles;
+  c.L = g->lep.lep(g->lep.cur);
+  c.lc = g->lep.ctl;
+  c.lchunk = g->lep.chunk[g->lep.cur];
+  c.ltt = g->lep.tt;
+  c.P = g->pho.pho(g->pho.cur);
+  c.pc = g->pho.ctl;
+  c.pchunk = g->pho.chunk[g->pho.cur];
+  c.ptt = g->pho.tt;
+  c.rho = g->rho;
+  c.ebar = g->ebar;
+  c.tab = g->tab;
+  c.err = g->err;
+  return c;
+}
+
+FieldCtx make_fctx(gap_t* g, int mode) {
+  FieldCtx f;
+  f.tubes = g->tubes;
+  f.fb = g->fb;
+  f.rho = g->rho;
+  f.rho_last = g->rho_last;
+  f.E = g->E;
+  f.ebar = g->ebar;
+  f.part = g->part;
+  f.part2 = g->part2;
+  f.err = g->err;
+  f.mode = mode;
+  return f;
+}
+
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i64(long long* p, long long n, long long v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <class B>
+void rebucket_t(gap_t* g, Store& st, B src, B dst) {
+  RbCtx<B> cx;
+  cx.tubes = g->tubes;
+  cx.tiles = g->tiles;
+  cx.src = src;
+  cx.dst = dst;
+  cx.ctl = st.ctl;
+  cx.chunk_old = st.chunk[st.cur];
+  cx.chunk_new = st.chunk[st.cur ^ 1];
+  cx.tt = st.tt;
+  cx.tcount = st.tcount;
+  cx.tcursor = st.tcursor;
+  cx.tchunk = st.tchunk;
+  cx.n_tiles = g->n_tiles;
+  const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
+  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
+  k_rb_count<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_rb_scan<B><<<1, 1024, 0, g->s>>>(cx);
+  k_rb_chunks<B><<<kGrid, 256, 0, g->s>>>(cx);
+  k_rb_scatter<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_rb_pad<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_rb_finish<B><<<1, 1, 0, g->s>>>(cx);
+  st.cur ^= 1;
+}
+
+void rebucket_all(gap_t* g) {
+  rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1));
+  rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1));
+}
+
+void field_pass(gap_t* g, int mode) {
+  FieldCtx f = make_fctx(g, mode);
+  k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+  k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+  if (g->any_periodic) k_field_periodic_ends<<<(g->n_tubes + 63) / 64, 64, 0, g->s>>>(f, g->n_tubes);
+}
+
+// Node charge and field from the current particles and E_s (no drive).
+void rebuild_field(gap_t* g) {
+  const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
+  k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
+  k_deposit_all<<<kGrid, CHUNK, 0, g->s>>>(make_ctx(g));
+  field_pass(g, 1);
+}
+
+void enqueue_step(gap_t* g) {
+  Ctx cx = make_ctx(g);
+  k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
+  k_leptons<<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_photons<<<kGrid, CHUNK, 0, g->s>>>(cx);
+  field_pass(g, 0);
+  if (++g->since_rb >= g->R) {
+    rebucket_all(g);
+    g->since_rb = 0;
+  }
+}
+
+int read_err(gap_t* g) {
+  int e = 0;
+  if (hipMemcpy(&e, g->err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return GAP_EDEVICE;
+  if (e & E_TILE) g->sticky = GAP_ETILE;
+  else if (e & E_NAN) g->sticky = GAP_ENAN;
+  else if (e & E_CAP) g->sticky = GAP_ECAP;
+  return g->sticky;
+}
+
+int sync_and_err(gap_t* g) {
+  if (hipStreamSynchronize(g->s) != hipSuccess) return GAP_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return GAP_EDEVICE;
+  return read_err(g);
+}
+
+Ctl read_ctl(const Store& st) {
+  Ctl c{};
+  (void)hipMemcpy(&c, st.ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+  return c;
+}
+
+int alloc_store(gap_t* g, Store& st, int64_t cap, bool photon) {
+  st.cap_live = cap;
+  st.capacity = cap + 2LL * g->n_tiles * CHUNK + CHUNK;
+  st.limit = st.capacity - (int64_t)g->n_tiles * CHUNK;
+  const size_t n = (size_t)st.capacity;
+  for (int b = 0; b < 2; ++b) {
+    st.pos[b] = (uint32_t*)dalloc(g, n * 4);
+    st.a[b] = (float*)dalloc(g, n * 4);
+    st.w[b] = (float*)dalloc(g, n * 4);
+    st.id[b] = (uint64_t*)dalloc(g, n * 8);
+    if (photon) st.n0[b] = (int32_t*)dalloc(g, n * 4);
+    st.chunk[b] = (int32_t*)dalloc(g, (n / CHUNK + 1) * 4);
+    if (!st.pos[b] || !st.a[b] || !st.w[b] || !st.id[b] || (photon && !st.n0[b]) || !st.chunk[b]) return GAP_ENOMEM;
+  }
+  st.tt = (int32_t*)dalloc(g, n * 4);
+  st.tcount = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+  st.tcursor = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+  st.tchunk = (long long*)dalloc(g, ((size_t)g->n_tiles + 1) * 8);
+  st.ctl = (Ctl*)dalloc(g, sizeof(Ctl));
+  if (!st.tt || !st.tcount || !st.tcursor || !st.tchunk || !st.ctl) return GAP_ENOMEM;
+  Ctl c{};
+  c.capacity = st.capacity;
+  c.limit = st.limit;
+  c.cap_live = cap;
+  if (hipMemcpyAsync(st.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, g->s) != hipSuccess) return GAP_EDEVICE;
+  return GAP_OK;
+}
+
+int upload_tubes(gap_t* g) {
+  return from_hip(hipMemcpy(g->tubes, g->th.data(), sizeof(Tube) * g->n_tubes, hipMemcpyHostToDevice));
+}
+int download_tubes(gap_t* g) {
+  return from_hip(hipMemcpy(g->th.data(), g->tubes, sizeof(Tube) * g->n_tubes, hipMemcpyDeviceToHost));
+}
+
+int build(gap_t* g, const gap_params* p, int n_tubes) {
+  g->n_tubes = n_tubes;
+  g->P.assign(p, p + n_tubes);
+  g->D.resize(n_tubes);
+  g->th.assign(n_tubes, Tube{});
+  int64_t cap_l = 0, cap_p = 0;
+  int rmin = 1 << 30;
+  for (int t = 0; t < n_tubes; ++t) {
+    const gap_params& q = g->P[t];
+    const Derived d = derive(q);
+    g->D[t] = d;
+    Tube& T = g->th[t];
+    std::memset(&T, 0, sizeof(Tube));
+    T.N = q.n_cells;
+    T.node_off = (int32_t)g->total_nodes;
+    T.cell_off = (int32_t)g->total_cells;
+    T.tile_first = g->n_tiles;
+    T.n_tiles = (q.n_cells + TILE - 1) / TILE;
+    T.flags = q.flags;
+    T.nsub_max = q.nsub_max;
+    T.dt = (float)d.dt;
+    T.cfl24 = (float)(q.cfl * kTwo24);
+    T.lr = (float)(d.lam / d.rc);
+    T.inv_rc = (float)(1.0 / d.rc);
+    T.b = (float)q.b;
+    T.b_over_lam = (float)(q.b / d.lam);
+    T.xc_floor = (float)q.xc_floor;
+    T.x_thr = (float)q.x_thr;
+    T.emit_k = (float)(kAlphaEM * d.dt / d.rc);
+    T.conv_k = (float)(kAlphaEM * d.dt * q.b / d.lam);
+    T.dpho = (int32_t)std::llrint(q.cfl * kTwo24);
+    T.dtd = d.dt;
+    T.scale = d.w0 / kTwo24;
+    T.drive = q.alpha * d.s_co * d.dt;
+    T.inj_per_step = q.inj_rate * q.ppc_ref / q.inj_weight;
+    T.inv_len_scale = d.w0 / ((double)q.n_cells * kTwo24 * kTwo24);
+    T.bg_unit = (q.flags & GAP_ETA_CO_OFF) ? 0 : (int64_t)std::llrint(-d.s_co) * q.ppc_ref * (int64_t)kTwo24;
+    T.hfix = (int64_t)std::ceil(q.h_gap_frac * q.n_cells * kTwo24);
+    T.inj_w = (float)q.inj_weight;
+    T.inj_T = std::llrint((double)T.inj_w * kTwo24);
+    T.seed = q.seed;
+    for (int j = 0; j < T.n_tiles; ++j) {
+      Tile tl;
+      tl.tube = t;
+      tl.first = j * TILE;
+      tl.base = tl.first - MARGIN;
+      tl.ncell = std::min(TILE, q.n_cells - tl.first);
+      g->tiles_h.push_back(tl);
+    }
+    const int nb = (q.n_cells + FB_NODES - 1) / FB_NODES;
+    const int first = (int)g->fb_h.size();
+    for (int j = 0; j < nb; ++j) g->fb_h.push_back(FBlk{t, j * FB_NODES, first, nb});
+    g->n_tiles += T.n_tiles;
+    g->total_nodes += q.n_cells + 1;
+    g->total_cells += q.n_cells;
+    cap_l += q.cap_leptons;
+    cap_p += q.cap_photons;
+    if (q.flags & GAP_PERIODIC) g->any_periodic = true;
+    const int rmax = std::max(1, (int)std::floor((MARGIN - 2) / q.cfl) - 1);
+    rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : std::min(64, rmax));
+  }
+  g->R = rmin;
+  g->n_fb = (int)g->fb_h.size();
+  if (g->total_nodes > (1LL << 30)) return GAP_EINVAL;
+
+  g->tubes = (Tube*)dalloc(g, sizeof(Tube) * n_tubes);
+  g->tiles = (Tile*)dalloc(g, sizeof(Tile) * g->n_tiles);
+  g->rho = (long long*)dalloc(g, sizeof(long long) * g->total_nodes);
+  g->rho_last = (long long*)dalloc(g, sizeof(long long) * g->total_nodes);
+  g->E = (float*)dalloc(g, sizeof(float) * g->total_cells);
+  g->ebar = (float*)dalloc(g, sizeof(float) * g->total_nodes);
+  g->fb = (FBlk*)dalloc(g, sizeof(FBlk) * g->n_fb);
+  g->part = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
+  g->part2 = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
+  g->tab = (float*)dalloc(g, sizeof(float) * 2 * (NTAB + 1));
+  g->err = (int*)dalloc(g, sizeof(int));
+  g->live = (long long*)dalloc(g, sizeof(long long) * n_tubes);
+  if (!g->tubes || !g->tiles || !g->rho || !g->rho_last || !g->E || !g->ebar || !g->fb || !g->part || !g->part2 ||
+      !g->tab || !g->err || !g->live)
+    return GAP_ENOMEM;
+  int e;
+  if ((e = alloc_store(g, g->lep, cap_l, false))) return e;
+  if ((e = alloc_store(g, g->pho, cap_p, true))) return e;
+  HIPCHK(hipStreamSynchronize(g->s));
+  if ((e = upload_tubes(g))) return e;
+  HIPCHK(hipMemcpy(g->tiles, g->tiles_h.data(), sizeof(Tile) * g->n_tiles, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(g->fb, g->fb_h.data(), sizeof(FBlk) * g->n_fb, hipMemcpyHostToDevice));
+  const std::vector<float>& tab = sync_table();
+  HIPCHK(hipMemcpy(g->tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+
+  // initial particles into the lepton tail, then sort and solve the field
+  std::vector<long long> off(n_tubes + 1, 0);
+  std::vector<int32_t> kind(n_tubes), ppc(n_tubes), klo(n_tubes);
+  std::vector<float> u0(n_tubes);
+  for (int t = 0; t < n_tubes; ++t) {
+    off[t + 1] = off[t] + init_count(g->P[t], g->D[t]);
+    kind[t] = g->P[t].init_kind;
+    ppc[t] = std::max(1, g->P[t].ppc_init);
+    klo[t] = (int32_t)init_k_lo(g->P[t], g->D[t]);
+    u0[t] = (float)g->P[t].u_init;
+    if (init_count(g->P[t], g->D[t]) > g->P[t].cap_leptons) return GAP_ECAP;
+  }
+  const long long total = off[n_tubes];
+  if (total > g->lep.limit) return GAP_ECAP;
+  if (total > 0) {
+    long long* d_off = (long long*)dalloc(g, sizeof(long long) * (n_tubes + 1));
+    int32_t* d_kind = (int32_t*)dalloc(g, 4 * n_tubes);
+    int32_t* d_ppc = (int32_t*)dalloc(g, 4 * n_tubes);
+    int32_t* d_klo = (int32_t*)dalloc(g, 4 * n_tubes);
+    float* d_u0 = (float*)dalloc(g, 4 * n_tubes);
+    if (!d_off || !d_kind || !d_ppc || !d_klo || !d_u0) return GAP_ENOMEM;
+    HIPCHK(hipStreamSynchronize(g->s));
+    HIPCHK(hipMemcpy(d_off, off.data(), sizeof(long long) * (n_tubes + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_kind, kind.data(), 4 * n_tubes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_ppc, ppc.data(), 4 * n_tubes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_klo, klo.data(), 4 * n_tubes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d_u0, u0.data(), 4 * n_tubes, hipMemcpyHostToDevice));
+    InitCtx ic;
+    ic.tubes = g->tubes;
+    ic.tiles = g->tiles;
+    ic.L = g->lep.lep(g->lep.cur);
+    ic.ltt = g->lep.tt;
+    ic.base_slot = 0;
+    ic.tube_off = d_off;
+    ic.kind = d_kind;
+    ic.ppc = d_ppc;
+    ic.k_lo = d_klo;
+    ic.u0 = d_u0;
+    ic.n_tubes = n_tubes;
+    k_init_particles<<<kGrid, 256, 0, g->s>>>(ic);
+    Ctl c{};
+    c.capacity = g->lep.capacity;
+    c.limit = g->lep.limit;
+    c.cap_live = g->lep.cap_live;
+    c.tail = total;
+    HIPCHK(hipMemcpyAsync(g->lep.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
+  }
+  rebucket_all(g);
+  rebuild_field(g);
+  return sync_and_err(g);
+}
+
+// Copy a store to the host and decode the live records of tube `tube`.
+struct HostRec { int32_t cell; uint32_t frac; float a; float w; int32_t n0; uint64_t id; };
+
+int export_store(gap_t* g, const Store& st, bool photon, int tube, std::vector<HostRec>& out) {
+  const Ctl c = read_ctl(st);
+  const long long S = c.n_sorted_chunks * CHUNK, n = S + c.tail;
+  std::vector<uint32_t> pos(n);
+  std::vector<float> a(n), w(n);
+  std::vector<int32_t> n0(photon ? n : 0), chunk(c.n_sorted_chunks), tt(n);
+  std::vector<uint64_t> id(n);
+  const int b = st.cur;
+  if (n > 0) {
+    HIPCHK(hipMemcpy(pos.data(), st.pos[b], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(a.data(), st.a[b], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(w.data(), st.w[b], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(id.data(), st.id[b], 8 * n, hipMemcpyDeviceToHost));
+    if (photon) HIPCHK(hipMemcpy(n0.data(), st.n0[b], 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(tt.data(), st.tt, 4 * n, hipMemcpyDeviceToHost));
+  }
+  if (c.n_sorted_chunks > 0) HIPCHK(hipMemcpy(chunk.data(), st.chunk[b], 4 * c.n_sorted_chunks, hipMemcpyDeviceToHost));
+  out.clear();
+  for (long long i = 0; i < n; ++i) {
+    const int tile = i < S ? chunk[i / CHUNK] : tt[i];
+    if (tile < 0 || tile >= g->n_tiles) continue;
+    const bool alive = photon ? (a[i] != 0.0f) : (w[i] != 0.0f);
+    if (!alive) continue;
+    const Tile& tl = g->tiles_h[tile];
+    if (tl.tube != tube) continue;
+    int cell = tl.base + (int)(pos[i] >> FRAC);
+    const int N = g->P[tube].n_cells;
+    if (g->P[tube].flags & GAP_PERIODIC) cell = cell < 0 ? cell + N : (cell >= N ? cell - N : cell);
+    out.push_back(HostRec{cell, pos[i] & 0xFFFFFFu, a[i], w[i], photon ? n0[i] : 0, id[i]});
+  }
+  return GAP_OK;
+}
+
+int graph_capture(gap_t* g, int64_t n) {
+  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
+  g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_since = g->since_rb;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal));
+  for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  hipError_t e = hipStreamEndCapture(g->s, &graph);
+  g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_since = g->since_rb;
+  // nothing ran yet: back to the start state
+  g->lep.cur = g->gs_l; g->pho.cur = g->gs_p; g->since_rb = g->gs_since;
+  if (e != hipSuccess) return GAP_EDEVICE;
+  e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) { g->gexec = nullptr; return GAP_EDEVICE; }
+  g->gsteps = n;
+  return GAP_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_allocator* alloc, gap_t** out) {
+  if (!p || !out || n_tubes < 1) return GAP_EINVAL;
+  *out = nullptr;
+  for (int t = 0; t < n_tubes; ++t) {
+    int e = validate(p[t]);
+    if (e) return e;
+  }
+  if (alloc && (!alloc->alloc || !alloc->free)) return GAP_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GAP_EDEVICE;
+  gap_t* g = new gap_t();
+  g->s = (hipStream_t)stream;
+  if (alloc) { g->al = *alloc; g->custom_alloc = true; }
+  int e = build(g, p, n_tubes);
+  if (e) {
+    release(g);
+    delete g;
+    return e;
+  }
+  *out = g;
+  return GAP_OK;
+}
+
+int gap_step(gap_t* g, int64_t n_steps) {
+  if (!g || n_steps < 0) return GAP_EINVAL;
+  for (int64_t i = 0; i < n_steps; ++i) enqueue_step(g);
+  if (hipGetLastError() != hipSuccess) return GAP_EDEVICE;
+  return g->sticky;
+}
+
+int gap_step_graph(gap_t* g, int64_t n_steps) {
+  if (!g || n_steps < 0) return GAP_EINVAL;
+  if (n_steps == 0) return g->sticky;
+  if (g->s == nullptr) return GAP_ESTATE;   // stream capture needs a non-default stream
+  const bool valid = g->gexec && g->gsteps == n_steps && g->lep.cur == g->gs_l && g->pho.cur == g->gs_p &&
+                     g->since_rb == g->gs_since;
+  if (!valid) {
+    int e = graph_capture(g, n_steps);
+    if (e) return e;
+  }
+  HIPCHK(hipGraphLaunch(g->gexec, g->s));
+  g->lep.cur = g->ge_l; g->pho.cur = g->ge_p; g->since_rb = g->ge_since;
+  return g->sticky;
+}
+
+int gap_sync(gap_t* g) {
+  if (!g) return GAP_EINVAL;
+  return sync_and_err(g);
+}
+
+int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_bytes, size_t* bytes_written) {
+  if (!g || tube < 0 || tube >= g->n_tubes || (!host_buf && buf_bytes)) return GAP_EINVAL;
+  int e = sync_and_err(g);
+  if (e == GAP_EDEVICE) return e;
+  const Tube& Th = g->th[tube];
+  const int N = g->P[tube].n_cells;
+  size_t need = 0;
+  auto fits = [&](size_t n) {
+    need = n;
+    if (bytes_written) *bytes_written = n;
+    return n <= buf_bytes;
+  };
+  switch (kind) {
+    case GAP_DIAG_COUNTS: {
+      if (!fits(sizeof(int64_t) * 32)) return GAP_EINVAL;
+      if ((e = download_tubes(g))) return e;
+      int64_t* o = (int64_t*)host_buf;
+      for (int i = 0; i < 32; ++i) o[i] = g->th[tube].cnt[i];
+      long long lv[2] = {0, 0};
+      const int grid = kGrid;
+      k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
+      { const Ctl* c = g->lep.ctl;
+        k_count_live<LepBuf><<<grid, CHUNK, 0, g->s>>>(g->lep.lep(g->lep.cur), c, g->lep.chunk[g->lep.cur], g->lep.tt, g->tiles, g->live); }
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(&lv[0], g->live + tube, 8, hipMemcpyDeviceToHost));
+      k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
+      { const Ctl* c = g->pho.ctl;
+        k_count_live<PhoBuf><<<grid, CHUNK, 0, g->s>>>(g->pho.pho(g->pho.cur), c, g->pho.chunk[g->pho.cur], g->pho.tt, g->tiles, g->live); }
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(&lv[1], g->live + tube, 8, hipMemcpyDeviceToHost));
+      o[GAP_C_LEPTONS] = lv[0];
+      o[GAP_C_PHOTONS] = lv[1];
+      o[GAP_C_STEP] = g->th[tube].step;
+      o[GAP_C_ERR] = g->sticky;
+      return GAP_OK;
+    }
+    case GAP_DIAG_FIELD:
+      if (!fits(sizeof(float) * N)) return GAP_EINVAL;
+      HIPCHK(hipMemcpy(host_buf, g->E + Th.cell_off, sizeof(float) * N, hipMemcpyDeviceToHost));
+      return GAP_OK;
+    case GAP_DIAG_NODE_E:
+      if (!fits(sizeof(float) * (N + 1))) return GAP_EINVAL;
+      HIPCHK(hipMemcpy(host_buf, g->ebar + Th.node_off, sizeof(float) * (N + 1), hipMemcpyDeviceToHost));
+      return GAP_OK;
+    case GAP_DIAG_RHO:
+      if (!fits(sizeof(int64_t) * (N + 1))) return GAP_EINVAL;
+      HIPCHK(hipMemcpy(host_buf, g->rho_last + Th.node_off, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost));
+      return GAP_OK;
+    case GAP_DIAG_ES: {
+      if (!fits(sizeof(double))) return GAP_EINVAL;
+      if ((e = download_tubes(g))) return e;
+      std::memcpy(host_buf, &g->th[tube].Es, sizeof(double));
+      return GAP_OK;
+    }
+    case GAP_DIAG_DERIVED: {
+      if (!fits(sizeof(double) * 8)) return GAP_EINVAL;
+      const Derived& d = g->D[tube];
+      double v[8] = {d.d_cm, d.lam, d.rc, d.dt, d.H, d.w0, d.s_co, (double)d.N};
+      std::memcpy(host_buf, v, sizeof(v));
+      return GAP_OK;
+    }
+    case GAP_DIAG_LEPTONS:
+    case GAP_DIAG_PHOTONS: {
+      const bool ph = kind == GAP_DIAG_PHOTONS;
+      std::vector<HostRec> recs;
+      if ((e = export_store(g, ph ? g->pho : g->lep, ph, tube, recs))) return e;
+      const size_t rs = ph ? 32 : 24;
+      if (!fits(rs * recs.size())) return GAP_EINVAL;
+      char* o = (char*)host_buf;
+      for (const HostRec& r : recs) {
+        std::memcpy(o, &r.cell, 4);
+        std::memcpy(o + 4, &r.frac, 4);
+        std::memcpy(o + 8, &r.a, 4);
+        std::memcpy(o + 12, &r.w, 4);
+        if (ph) {
+          int32_t pad = 0;
+          std::memcpy(o + 16, &r.n0, 4);
+          std::memcpy(o + 20, &pad, 4);
+          std::memcpy(o + 24, &r.id, 8);
+        } else {
+          std::memcpy(o + 16, &r.id, 8);
+        }
+        o += rs;
+      }
+      return GAP_OK;
+    }
+    default:
+      (void)need;
+      return GAP_EINVAL;
+  }
+}
+
+int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes) {
+  if (!g || !host_buf || tube < 0 || tube >= g->n_tubes) return GAP_EINVAL;
+  if (g->n_tubes != 1) return GAP_ESTATE;
+  int e = sync_and_err(g);
+  if (e == GAP_EDEVICE) return e;
+  if ((e = download_tubes(g))) return e;
+  Tube& T = g->th[0];
+  const gap_params& q = g->P[0];
+  const int N = q.n_cells;
+  const bool frozen = (q.flags & GAP_FIELD_FROZEN) != 0;
+  const char* b = (const char*)host_buf;
+  switch (kind) {
+    case GAP_STATE_PARTICLES: {
+      if (bytes < 16) return GAP_EINVAL;
+      int64_t nl, np;
+      std::memcpy(&nl, b, 8);
+      std::memcpy(&np, b + 8, 8);
+      if (nl < 0 || np < 0 || bytes < 16 + (size_t)nl * 24 + (size_t)np * 32) return GAP_EINVAL;
+      if (nl > g->lep.limit || np > g->pho.limit) return GAP_ECAP;
+      for (int sp = 0; sp < 2; ++sp) {
+        const bool ph = sp == 1;
+        Store& st = ph ? g->pho : g->lep;
+        const int64_t n = ph ? np : nl;
+        const char* r = ph ? b + 16 + nl * 24 : b + 16;
+        const size_t rs = ph ? 32 : 24;
+        std::vector<uint32_t> pos(n);
+        std::vector<float> a(n), w(n);
+        std::vector<int32_t> n0(n), tt(n);
+        std::vector<uint64_t> id(n);
+        for (int64_t i = 0; i < n; ++i, r += rs) {
+          int32_t cell; uint32_t frac;
+          std::memcpy(&cell, r, 4);
+          std::memcpy(&frac, r + 4, 4);
+          std::memcpy(&a[i], r + 8, 4);
+          std::memcpy(&w[i], r + 12, 4);
+          if (ph) { std::memcpy(&n0[i], r + 16, 4); std::memcpy(&id[i], r + 24, 8); }
+          else std::memcpy(&id[i], r + 16, 8);
+          if (cell < 0 || cell >= N || frac >= (1u << FRAC)) return GAP_EINVAL;
+          if (ph ? a[i] == 0.0f : w[i] == 0.0f) return GAP_EINVAL;
+          const int tile = T.tile_first + cell / TILE;
+          tt[i] = tile;
+          pos[i] = ((uint32_t)(cell - g->tiles_h[tile].base) << FRAC) | frac;
+        }
+        const int c = st.cur;
+        if (n > 0) {
+          HIPCHK(hipMemcpy(st.pos[c], pos.data(), 4 * n, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(st.a[c], a.data(), 4 * n, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(st.w[c], w.data(), 4 * n, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(st.id[c], id.data(), 8 * n, hipMemcpyHostToDevice));
+          if (ph) HIPCHK(hipMemcpy(st.n0[c], n0.data(), 4 * n, hipMemcpyHostToDevice));
+          HIPCHK(hipMemcpy(st.tt, tt.data(), 4 * n, hipMemcpyHostToDevice));
+        }
+        Ctl cc = read_ctl(st);
+        cc.n_sorted_chunks = 0;
+        cc.tail = n;
+        cc.tail_snap = 0;
+        HIPCHK(hipMemcpy(st.ctl, &cc, sizeof(Ctl), hipMemcpyHostToDevice));
+      }
+      T.dq = 0;
+      T.dcur = 0;
+      if ((e = upload_tubes(g))) return e;
+      rebucket_all(g);
+      g->since_rb = 0;
+      if (frozen) {
+        const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
+        k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
+        k_deposit_all<<<kGrid, CHUNK, 0, g->s>>>(make_ctx(g));
+        // keep E: only record the node charge
+        FieldCtx f = make_fctx(g, 1);
+        k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+        k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+      } else {
+        rebuild_field(g);
+      }
+      return sync_and_err(g);
+    }
+    case GAP_STATE_ES_STEP: {
+      if (bytes < 16) return GAP_EINVAL;
+      std::memcpy(&T.Es, b, 8);
+      std::memcpy(&T.step, b + 8, 8);
+      if ((e = upload_tubes(g))) return e;
+      if (!frozen) rebuild_field(g);
+      return sync_and_err(g);
+    }
+    case GAP_STATE_FIELD: {
+      if (bytes < sizeof(float) * N + 8) return GAP_EINVAL;
+      std::vector<float> E(N);
+      std::memcpy(E.data(), b, sizeof(float) * N);
+      std::memcpy(&T.Es, b + sizeof(float) * N, 8);
+      std::vector<float> eb(N + 1);
+      if (q.flags & GAP_PERIODIC) {
+        for (int i = 0; i < N; ++i) eb[i] = (float)(0.5 * ((double)E[(i + N - 1) % N] + (double)E[i]));
+        eb[N] = eb[0];
+      } else {
+        eb[0] = (float)(0.5 * (T.Es + (double)E[0]));
+        for (int i = 1; i < N; ++i) eb[i] = (float)(0.5 * ((double)E[i - 1] + (double)E[i]));
+        eb[N] = E[N - 1];
+      }
+      HIPCHK(hipMemcpy(g->E + T.cell_off, E.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(g->ebar + T.node_off, eb.data(), sizeof(float) * (N + 1), hipMemcpyHostToDevice));
+      if ((e = upload_tubes(g))) return e;
+      return sync_and_err(g);
+    }
+    case GAP_STATE_INJECTION: {
+      if (bytes < 16) return GAP_EINVAL;
+      std::memcpy(&T.inj_acc, b, 8);
+      std::memcpy(&T.inj_count, b + 8, 8);
+      if ((e = upload_tubes(g))) return e;
+      return sync_and_err(g);
+    }
+    default:
+      return GAP_EINVAL;
+  }
+}
+
+void gap_free(gap_t* g) {
+  if (!g) return;
+  release(g);
+  delete g;
+}
+
+const char* gap_strerror(int code) {
+  switch (code) {
+    case GAP_OK: return "ok";
+    case GAP_EINVAL: return "invalid argument";
+    case GAP_ENOMEM: return "out of device memory";
+    case GAP_ECAP: return "particle store full: particles were dropped";
+    case GAP_ETILE: return "a particle left its tile window";
+    case GAP_ENAN: return "non-finite field";
+    case GAP_EDEVICE: return "HIP runtime error";
+    case GAP_ESTATE: return "call not valid in the current state";
+    default: return "unknown error";
+  }
+}
+
+int gap_sync_inverse_host(const float* r, float* xi, int64_t n) {
+  if (n < 0 || (n > 0 && (!r || !xi))) return GAP_EINVAL;
+  const std::vector<float>& tab = sync_table();
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(r[i] > 0.0f && r[i] < 1.0f)) return GAP_EINVAL;
+    xi[i] = sync_sample_host(r[i], tab.data());
+  }
+  return GAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// gap_device.hpp -- device-side building blocks of libgap (gfx950, wave64):
+// the state layout, Philox4x32-10, the QED rate fits and the photon-energy
+// sampler.  Written for this library; shares nothing with the CPU oracle.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gap {
+
+// ---------------------------------------------------------------- layout
+// Particles live in per-species stores of fixed capacity, split into
+//  * a sorted region: chunks of CHUNK slots, each chunk belonging to one tile
+//    of TILE cells, padded with dead slots;
+//  * a tail: particles appended since the last re-sort (births, injection),
+//    each carrying its tile index in `tt`.
+// A position is a 32-bit fixed-point offset from the tile's window base
+// (first cell - MARGIN): top 8 bits = cell offset, low 24 bits = fraction.
+constexpr int TILE = 128;       // cells per tile
+constexpr int MARGIN = 64;      // cells of slack on each side of a tile
+constexpr int WIN = 256;        // cells addressable from a tile base
+constexpr int CHUNK = 256;      // slots per chunk = threads per workgroup
+constexpr int FRAC = 24;        // fractional bits of a position
+constexpr int WAVE = 64;
+
+constexpr int NTAB = 4096;      // photon-spectrum table segments
+constexpr float TAB_YLO = 0.69314718055994531f;  // ln 2
+constexpr float TAB_YHI = 17.5f;
+
+// counters (mirrors the GAP_C_* indices of the ABI)
+enum : int {
+  C_LEPTONS = 0, C_PHOTONS = 1, C_STEP = 2, C_EMIT = 3, C_PHO_BORN = 4, C_CONV = 5, C_ABSORBED = 6,
+  C_OUTFLOW = 7, C_PHO_EXIT = 8, C_DROPPED = 9, C_MERGED = 10, C_ERR = 11, C_INJECTED = 12,
+  C_EMIT_EVAL = 13, C_CONV_EVAL = 14, C_LEP_STEPS = 15, C_PHO_STEPS = 16, C_REBUCKETS = 17, C_N = 32
+};
+
+enum : uint32_t {
+  F_QED_OFF = 1u, F_ETA_CO_OFF = 2u, F_FIELD_FROZEN = 4u, F_RECOIL_OFF = 8u, F_PERIODIC = 16u,
+  F_MERGE_ON = 32u, F_TRACK_ALL = 64u, F_ANTI_ALIGNED = 128u, F_CONV_OFF = 1024u, F_EMIT_OFF = 2048u
+};
+
+// sticky device error bits
+enum : int { E_CAP = 1, E_TILE = 2, E_NAN = 4 };
+
+// Per-tube constants and mutable scalars (device memory).
+struct Tube {
+  // grid
+  int32_t N, node_off, cell_off, tile_first;
+  int32_t n_tiles, flags, nsub_max, pad0;
+  // float constants of the push
+  float dt, cfl24;          // dt; cfl * 2^24 (displacement of a beta = 1 particle, fixed point)
+  float lr, inv_rc;         // lambda~/R~, 1/R~
+  float b, b_over_lam;      // B/B_Q, b/lambda~
+  float xc_floor, x_thr;
+  float emit_k;             // alpha_em * dt / R~
+  float conv_k;             // alpha_em * dt * b / lambda~
+  float dtf_unused0, dtf_unused1;
+  int32_t dpho;             // photon displacement per step: rint(cfl 2^24)
+  int32_t pad1;
+  // double constants of the field
+  double dtd, scale;        // dt; w0 / 2^24
+  double drive;             // alpha * s_co * dt
+  double inj_per_step;      // macro-electrons injected per step
+  double inv_len_scale;     // periodic: w0 dx / (2^24 2^24 L)
+  int64_t bg_unit;          // -s_co ppc_ref 2^24 (0 with ETA_CO_OFF)
+  int64_t hfix;             // ceil(H/dx 2^24): QED zone is cell*2^24 + frac < hfix
+  int64_t inj_T;            // fixed-point charge of one injected electron
+  float inj_w;              // weight of one injected electron (positive)
+  float pad2;
+  uint64_t seed;
+  // mutable
+  double Es, inj_acc;
+  int64_t dq, dcur, step;
+  uint64_t inj_count;
+  int64_t cnt[C_N];
+};
+
+struct Tile {
+  int32_t tube, first, base, ncell;   // base = first - MARGIN (tube-local cells)
+};
+
+struct Ctl {                  // control block of one store
+  int64_t n_sorted_chunks;    // sorted region = slots [0, CHUNK * n_sorted_chunks)
+  int64_t tail;               // tail length (slots after the sorted region)
+  int64_t tail_snap;          // tail length at the start of the step's pass
+  int64_t capacity;           // slots
+  int64_t limit;              // appends stop at this slot (keeps room for re-sort padding)
+  int64_t total_chunks_new;   // written by the re-sort scan
+  int64_t cap_live;           // live-particle cap (merge threshold reference)
+  int64_t pad;
+};
+
+struct LepBuf { uint32_t* pos; float* u; float* w; uint64_t* id; };
+struct PhoBuf { uint32_t* pos; float* x; float* w; int32_t* n0; uint64_t* id; };
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds; each round multiplies
+// words 0 and 2 by fixed 32-bit constants, swaps the high halves across and
+// xors in the key, which is bumped by a Weyl increment between rounds.
+struct u4 { uint32_t a, b, c, d; };
+
+__device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+    uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// counter = (id lo, id hi, step, tag << 16 | sub), key = seed
+__device__ __forceinline__ u4 draw(uint64_t seed, uint64_t id, int64_t step, uint32_t tag, uint32_t sub) {
+  return philox((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, (tag << 16) | (sub & 0xFFFFu),
+                (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+enum : uint32_t { T_INIT = 1, T_EMIT = 2, T_CONV = 3, T_INJ = 4, T_MERGE = 5, T_CHILD = 6 };
+
+// Bernoulli decision u < p with u = (k + 1/2) 2^-24, k = top 24 bits of r,
+// taken exactly: 2k + 1 < p 2^25 (FP64 compare of exact values).
+__device__ __forceinline__ bool bern(uint32_t r, float p) {
+  return (double)(2u * (r >> 8) + 1u) < (double)p * 33554432.0;
+}
+__device__ __forceinline__ float unif(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 5.9604645e-8f; }
+
+__device__ __forceinline__ uint64_t child_id(uint64_t seed, uint64_t parent, int64_t step, uint32_t j) {
+  u4 r = draw(seed, parent, step, T_CHILD, j);
+  return (uint64_t)r.a | ((uint64_t)r.b << 32);
+}
+
+// ---------------------------------------------------------------- QED fits
+// emission-rate function of Sect. 3.1 (fit quoted with eq. tau_syn)
+__device__ __forceinline__ float t_syn(float chi) {
+  return 1.4433756729740644f * powf(1.0f + 5.5425625842204074f * chi + 1.1f * chi * chi, -1.0f / 6.0f);
+}
+// pair-creation function of Sect. 3.2 (fit quoted with eq. tau_bw)
+__device__ __forceinline__ float t_bw(float chi) {
+  if (!(chi > 0.0f)) return 0.0f;
+  return 0.23f * expf(-8.0f / (3.0f * chi)) * powf(1.0f + 0.22f * chi, -1.0f / 3.0f);
+}
+
+// Classical synchrotron number spectrum: xi = C^-1(r) from the table.
+//  r <= 1/2: tab[i] = xi^(1/3) at r = i / (2 NTAB), linear in r near 0;
+//  r > 1/2 : tab[NTAB+1+i] = xi at y = -ln(1-r) on [ln 2, TAB_YHI].
+__device__ __forceinline__ float sync_sample(float r, const float* __restrict__ tab) {
+  if (r <= 0.5f) {
+    float t = r * (2.0f * NTAB);
+    int i = min((int)t, NTAB - 1);
+    float f = t - (float)i;
+    float v = tab[i] + f * (tab[i + 1] - tab[i]);
+    return v * v * v;
+  }
+  float y = -logf(1.0f - r);
+  float t = (y - TAB_YLO) * ((float)NTAB / (TAB_YHI - TAB_YLO));
+  t = fminf(fmaxf(t, 0.0f), (float)NTAB - 1e-3f);
+  int i = (int)t;
+  float f = t - (float)i;
+  const float* h = tab + NTAB + 1;
+  return h[i] + f * (h[i + 1] - h[i]);
+}
+
+// ---------------------------------------------------------------- wave utils
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+
+// Wave-aggregated counter increment: one atomic per wave.
+__device__ __forceinline__ void wave_count(int64_t* p, bool pred) {
+  uint64_t m = __ballot(pred);
+  if (m && lane_id() == __ffsll((long long)m) - 1) atomic_add_i64(p, (int64_t)__popcll(m));
+}
+
+}  // namespace gap

@@ -1,0 +1,855 @@
+// gap_kernels.hpp -- the per-step kernels of libgap (gfx950, wave64).
+#pragma once
+#include "gap_device.hpp"
+
+namespace gap {
+
+// Everything a step kernel needs; passed by value.
+struct Ctx {
+  Tube* tubes;
+  const Tile* tiles;
+  // lepton store (current buffers)
+  LepBuf L;
+  Ctl* lc;
+  const int32_t* lchunk;  // chunk -> tile (sorted region)
+  int32_t* ltt;           // slot -> tile (tail)
+  // photon store
+  PhoBuf P;
+  Ctl* pc;
+  const int32_t* pchunk;
+  int32_t* ptt;
+  // grid
+  long long* rho;         // node charge accumulator, sum_t (N_t + 1)
+  const float* ebar;      // node field, sum_t (N_t + 1)
+  const float* tab;       // photon spectrum table
+  int* err;
+};
+
+__device__ __forceinline__ int wrap_cell(int c, int N) { return c < 0 ? c + N : (c >= N ? c - N : c); }
+
+// Add `v` to counter `idx` of the tube `t` of each lane (t < 0: no-op), one
+// atomic per distinct tube in the wave.
+__device__ __forceinline__ void count_by_tube(Tube* tubes, int t, int idx, int64_t v) {
+  while (true) {
+    uint64_t m = __ballot(t >= 0);
+    if (!m) break;
+    int lead = __ffsll((long long)m) - 1;
+    int k = __shfl(t, lead);
+    long long s = (t == k) ? (long long)v : 0ll;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane_id() == lead && s != 0) atomic_add_i64(&tubes[k].cnt[idx], (int64_t)s);
+    if (t == k) t = -1;
+  }
+}
+
+// Exclusive prefix sum of `v` over the wave; returns the exclusive value and
+// writes the wave total to *total.
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    int o = __shfl_up(incl, d);
+    if (lane_id() >= d) incl += o;
+  }
+  *total = __shfl(incl, WAVE - 1);
+  return incl - v;
+}
+
+// Reserve `n` tail slots of a store (one atomic per wave); returns the first
+// slot index for this lane's records (or -1 with nothing reserved).
+__device__ __forceinline__ long long reserve_tail(Ctl* c, int n, int* dropped) {
+  int total;
+  int ex = wave_excl_scan(n, &total);
+  long long base = 0;
+  if (lane_id() == WAVE - 1 && total > 0) base = (long long)atomicAdd((unsigned long long*)&c->tail, (unsigned long long)total);
+  base = __shfl(base, WAVE - 1);
+  long long first = c->n_sorted_chunks * CHUNK + base + ex;
+  // appends beyond the limit are dropped (the tail never grows past it)
+  long long lim = c->limit;
+  *dropped = 0;
+  if (n > 0 && first + n > lim) {
+    long long ok = lim - first;
+    if (ok < 0) ok = 0;
+    *dropped = n - (int)ok;
+  }
+  return first;
+}
+
+// ------------------------------------------------------------------ prologue
+// Surface injection (cold electrons in cell 0 at a deterministic rate) and
+// the snapshots of the tails that this step's passes will process.
+__global__ void k_pre(Ctx cx, int n_tubes) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int t = 0; t < n_tubes; ++t) {
+    Tube& T = cx.tubes[t];
+    if (T.inj_per_step <= 0.0 || (T.flags & F_PERIODIC)) continue;
+    T.inj_acc += T.inj_per_step;
+    double fl = floor(T.inj_acc);
+    T.inj_acc -= fl;
+    int m = (int)fl;
+    const Tile& tl = cx.tiles[T.tile_first];
+    for (int j = 0; j < m; ++j) {
+      long long slot = cx.lc->n_sorted_chunks * CHUNK + cx.lc->tail;
+      if (slot >= cx.lc->limit) { T.cnt[C_DROPPED]++; atomicOr(cx.err, E_CAP); continue; }
+      cx.lc->tail++;
+      uint64_t id = (1ull << 62) + T.inj_count++;
+      u4 r = draw(T.seed, id, T.step, T_INJ, 0);
+      cx.L.pos[slot] = ((uint32_t)(0 - tl.base) << FRAC) | (r.a >> 8);
+      cx.L.u[slot] = 0.0f;
+      cx.L.w[slot] = -T.inj_w;
+      cx.L.id[slot] = id;
+      cx.ltt[slot] = T.tile_first;
+      T.dq += T.inj_T;               // E_s -= q w0 of the injected electron (q < 0)
+      T.cnt[C_INJECTED]++;
+    }
+  }
+  cx.lc->tail_snap = cx.lc->tail;
+  cx.pc->tail_snap = cx.pc->tail;
+}
+
+// ------------------------------------------------------------------ leptons
+// Flush the LDS node-charge window of tile `tile` into the global accumulator.
+__device__ void flush_window(const Ctx& cx, int tile, long long* s_rho) {
+  __syncthreads();
+  const Tile tl = cx.tiles[tile];
+  const Tube& T = cx.tubes[tl.tube];
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  for (int j = threadIdx.x; j <= WIN; j += blockDim.x) {
+    long long v = s_rho[j];
+    if (v != 0) {
+      int node = tl.base + j;
+      if (per) node = wrap_cell(node, T.N);
+      atomicAdd((unsigned long long*)&cx.rho[T.node_off + node], (unsigned long long)v);
+      s_rho[j] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
+// boundaries, deposit, photon births.  `tile` < 0: no particle in this lane.
+__device__ void lepton_one(const Ctx& cx, long long slot, int tile, bool lds, long long* s_rho) {
+  float w = 0.0f;
+  if (tile >= 0) w = cx.L.w[slot];
+  const bool alive = tile >= 0 && w != 0.0f;
+  int tube = -1;
+  Tile tl{0, 0, 0, 0};
+  const Tube* Tp = cx.tubes;
+  uint32_t pos = 0;
+  float u = 0.0f;
+  if (alive) {
+    tl = cx.tiles[tile];
+    tube = tl.tube;
+    Tp = cx.tubes + tube;
+    pos = cx.L.pos[slot];
+    u = cx.L.u[slot];
+  }
+  const Tube& T = *Tp;
+  const int N = T.N;
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  const int64_t step = T.step;
+
+  // gather (node field, first-order shape) and kick
+  const int cell = tl.base + (int)(pos >> FRAC);
+  const uint32_t frac = pos & 0xFFFFFFu;
+  const int cg = per ? wrap_cell(cell, N) : cell;
+  const float xi = (float)frac * 5.9604645e-8f;
+  float e0 = 0.0f, e1 = 0.0f;
+  if (alive) { e0 = cx.ebar[T.node_off + cg]; e1 = cx.ebar[T.node_off + cg + 1]; }
+  const float sg = w < 0.0f ? -1.0f : 1.0f;
+  u += sg * ((1.0f - xi) * e0 + xi * e1) * T.dt;
+
+  // curvature emission: rate alpha_em gamma/R~ T_syn(chi), chi = gamma^2 lambda~/R~,
+  // photon energy xi_s x_c with x_c = 1.5 gamma chi, QED zone h < H
+  const float upk = u;
+  uint64_t evmask = 0;
+  uint64_t id = 0;
+  float xc = 0.0f;
+  int ncand = 0, nev = 0;
+  bool eval = false;
+  if (alive && !(T.flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < T.hfix) {
+    const float g = sqrtf(1.0f + u * u);
+    const float chi = g * g * T.lr;
+    xc = 1.5f * g * chi;
+    if (xc >= T.xc_floor) {
+      eval = true;
+      id = cx.L.id[slot];
+      const float dtau = T.emit_k * g * t_syn(chi);
+      int nsub = (int)ceilf(dtau * 10.0f);
+      nsub = max(1, min(nsub, T.nsub_max));
+      const float p = -expm1f(-dtau / (float)nsub);
+      float au = fabsf(u);
+      for (int j = 0; j < nsub; ++j) {
+        u4 r = draw(T.seed, id, step, T_EMIT, (uint32_t)j);
+        if (bern(r.a, p)) {
+          float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+          au -= x;
+          evmask |= 1ull << j;
+          ++nev;
+          if (x >= T.x_thr || (T.flags & F_TRACK_ALL)) ++ncand;
+        }
+      }
+      if (!(T.flags & F_RECOIL_OFF)) u = copysignf(au, upk);
+    }
+  }
+
+  // drift: dh/dt = u / gamma, in fixed point
+  const float g2 = sqrtf(1.0f + u * u);
+  const int dfix = __float2int_rn(u / g2 * T.cfl24);
+  const long long np = (long long)pos + dfix;
+  const int noff = (int)(np >> FRAC);
+  const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
+  bool dead = false;
+  int ncell = tl.base + noff;
+  if (alive && (np < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
+  int64_t Tw = 0;
+  if (alive) Tw = __float2ll_rn(fabsf(w) * 16777216.0f);
+  bool absorbed = false, outflow = false;
+  if (alive && !dead && !per) {
+    if (ncell < 0) { absorbed = true; dead = true; }
+    else if (ncell >= N) { outflow = true; dead = true; }
+  }
+  if (alive) {
+    if (dead) cx.L.w[slot] = 0.0f;
+    else { cx.L.pos[slot] = (uint32_t)np; cx.L.u[slot] = u; }
+  }
+  if (absorbed) atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
+  if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
+
+  // deposit at the new position: node k gets s (T - A), node k+1 gets s A,
+  // A = round(T xi) (half up), exact integers
+  const int ncg = per ? wrap_cell(ncell, N) : ncell;
+  if (alive && !dead) {
+    const unsigned long long A = ((unsigned long long)Tw * nfrac + (1ull << 23)) >> FRAC;
+    const long long a = sg > 0 ? (long long)A : -(long long)A;
+    const long long ta = sg > 0 ? (long long)(Tw - (int64_t)A) : -(long long)(Tw - (int64_t)A);
+    if (lds) {
+      atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)ta);
+      atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)a);
+    } else {
+      int n1 = ncg + 1;
+      if (per && n1 == N) n1 = 0;
+      atomicAdd((unsigned long long*)&cx.rho[T.node_off + ncg], (unsigned long long)ta);
+      atomicAdd((unsigned long long*)&cx.rho[T.node_off + n1], (unsigned long long)a);
+    }
+  }
+
+  // photon births at the post-drift position, inside the QED zone
+  const bool keep = alive && !dead && (((int64_t)ncg << FRAC) + nfrac < T.hfix);
+  const int nst = keep ? ncand : 0;
+  if (__ballot(nst > 0)) {
+    int dropped = 0;
+    long long first = reserve_tail(cx.pc, nst, &dropped);
+    if (nst > 0) {
+      const long long lim = cx.pc->limit;
+      float au = fabsf(upk);
+      const float dir = upk >= 0.0f ? 1.0f : -1.0f;
+      const float aw = fabsf(w);
+      long long k = first;
+      uint64_t m = evmask;
+      while (m) {
+        int j = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        u4 r = draw(T.seed, id, step, T_EMIT, (uint32_t)j);
+        float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+        au -= x;
+        if (x >= T.x_thr || (T.flags & F_TRACK_ALL)) {
+          if (k < lim) {
+            cx.P.pos[k] = (uint32_t)np;
+            cx.P.x[k] = dir * x;
+            cx.P.w[k] = aw;
+            cx.P.n0[k] = (int32_t)(step + 1);
+            cx.P.id[k] = child_id(T.seed, id, step, 2u + (uint32_t)j);
+            cx.ptt[k] = tile;
+          }
+          ++k;
+        }
+      }
+    }
+    if (dropped) atomicOr(cx.err, E_CAP);
+    count_by_tube(cx.tubes, nst > 0 ? tube : -1, C_PHO_BORN, nst - dropped);
+    count_by_tube(cx.tubes, dropped > 0 ? tube : -1, C_DROPPED, dropped);
+  }
+
+  // counters (one atomic per wave and tube)
+  count_by_tube(cx.tubes, alive ? tube : -1, C_LEP_STEPS, 1);
+  if (__ballot(eval)) {
+    count_by_tube(cx.tubes, eval ? tube : -1, C_EMIT_EVAL, 1);
+    count_by_tube(cx.tubes, nev > 0 ? tube : -1, C_EMIT, nev);
+  }
+  if (__ballot(dead)) {
+    count_by_tube(cx.tubes, absorbed ? tube : -1, C_ABSORBED, 1);
+    count_by_tube(cx.tubes, outflow ? tube : -1, C_OUTFLOW, 1);
+  }
+}
+
+// Lepton pass.  Each workgroup takes a contiguous range of chunks (XCD-aware:
+// consecutive ranges go to the same XCD); sorted chunks deposit through an
+// LDS window of their tile, tail chunks with global atomics.
+__global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
+  __shared__ long long s_rho[WIN + 2];
+  for (int j = threadIdx.x; j < WIN + 2; j += blockDim.x) s_rho[j] = 0;
+  __syncthreads();
+  const long long nsc = cx.lc->n_sorted_chunks;
+  const long long S = nsc * CHUNK;
+  const long long tail = cx.lc->tail_snap;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  const int G = gridDim.x, bx = blockIdx.x;
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  const long long c0 = nch * r / G, c1 = nch * (r + 1) / G;
+  int held = -1;
+  for (long long c = c0; c < c1; ++c) {
+    if (c < nsc) {
+      const int tile = cx.lchunk[c];
+      if (tile != held) {
+        if (held >= 0) flush_window(cx, held, s_rho);
+        held = tile;
+      }
+      lepton_one(cx, c * CHUNK + threadIdx.x, tile, true, s_rho);
+    } else {
+      if (held >= 0) { flush_window(cx, held, s_rho); held = -1; }
+      const long long slot = S + (c - nsc) * CHUNK + threadIdx.x;
+      const int tile = slot < S + tail ? cx.ltt[slot] : -1;
+      lepton_one(cx, slot, tile, false, s_rho);
+    }
+  }
+  if (held >= 0) flush_window(cx, held, s_rho);
+}
+
+// ------------------------------------------------------------------ photons
+// One photon: free streaming at c, exit above H, conversion with
+// rate alpha_em (b/lambda~) sin(psi) T_BW(x b sin psi), sin(psi) = |sin(s/R~)|.
+__device__ void photon_one(const Ctx& cx, long long slot, int tile) {
+  float x = 0.0f;
+  if (tile >= 0) x = cx.P.x[slot];
+  const bool alive = tile >= 0 && x != 0.0f;
+  int tube = -1;
+  Tile tl{0, 0, 0, 0};
+  const Tube* Tp = cx.tubes;
+  uint32_t pos = 0;
+  int32_t n0 = 0;
+  if (alive) {
+    tl = cx.tiles[tile];
+    tube = tl.tube;
+    Tp = cx.tubes + tube;
+    pos = cx.P.pos[slot];
+    n0 = cx.P.n0[slot];
+  }
+  const Tube& T = *Tp;
+  const int N = T.N;
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  const int64_t step = T.step;
+  const float dir = x >= 0.0f ? 1.0f : -1.0f;
+  const long long np = (long long)pos + (x >= 0.0f ? T.dpho : -T.dpho);
+  const int noff = (int)(np >> FRAC);
+  const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
+  const int ncell = tl.base + noff;
+  bool dead = false;
+  if (alive && (np < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
+  const int ncg = per ? wrap_cell(ncell, N) : ncell;
+  bool exited = false;
+  if (alive && !dead) {
+    if ((!per && (ncell < 0 || ncell >= N)) || (((int64_t)ncg << FRAC) + nfrac >= T.hfix)) { exited = true; dead = true; }
+  }
+  bool eval = false, conv = false;
+  float w = 0.0f;
+  uint64_t id = 0;
+  if (alive && !dead && !(T.flags & (F_QED_OFF | F_CONV_OFF))) {
+    const float s = (float)(step + 1 - (int64_t)n0) * T.dt;
+    const float sp = fabsf(sinf(s * T.inv_rc));
+    const float chi = fabsf(x) * T.b * sp;
+    const float p = -expm1f(-T.conv_k * sp * t_bw(chi));
+    if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
+      eval = true;
+      id = cx.P.id[slot];
+      u4 r = draw(T.seed, id, step, T_CONV, 0);
+      conv = bern(r.a, p);
+      if (conv) w = cx.P.w[slot];
+    }
+  }
+  if (alive) {
+    if (dead || conv) cx.P.x[slot] = 0.0f;
+    else cx.P.pos[slot] = (uint32_t)np;
+  }
+  // pair births: e- and e+ at the photon position, gamma = x/2 each, along the photon
+  if (__ballot(conv)) {
+    int dropped = 0;
+    long long first = reserve_tail(cx.lc, conv ? 2 : 0, &dropped);
+    if (conv) {
+      const long long lim = cx.lc->limit;
+      const float gm = 0.5f * fabsf(x);
+      const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+      for (int k = 0; k < 2; ++k) {
+        long long sl = first + k;
+        if (sl < lim) {
+          cx.L.pos[sl] = (uint32_t)np;
+          cx.L.u[sl] = up;
+          cx.L.w[sl] = k == 0 ? -w : w;
+          cx.L.id[sl] = child_id(T.seed, id, step, (uint32_t)k);
+          cx.ltt[sl] = tile;
+        }
+      }
+    }
+    if (dropped) atomicOr(cx.err, E_CAP);
+    count_by_tube(cx.tubes, conv ? tube : -1, C_CONV, 1);
+    count_by_tube(cx.tubes, dropped > 0 ? tube : -1, C_DROPPED, dropped);
+  }
+  count_by_tube(cx.tubes, alive ? tube : -1, C_PHO_STEPS, 1);
+  if (__ballot(eval)) count_by_tube(cx.tubes, eval ? tube : -1, C_CONV_EVAL, 1);
+  if (__ballot(exited)) count_by_tube(cx.tubes, exited ? tube : -1, C_PHO_EXIT, 1);
+}
+
+__global__ __launch_bounds__(CHUNK) void k_photons(Ctx cx) {
+  const long long nsc = cx.pc->n_sorted_chunks;
+  const long long S = nsc * CHUNK;
+  const long long tail = cx.pc->tail_snap;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  const int G = gridDim.x, bx = blockIdx.x;
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  const long long c0 = nch * r / G, c1 = nch * (r + 1) / G;
+  for (long long c = c0; c < c1; ++c) {
+    long long slot;
+    int tile;
+    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = cx.pchunk[c]; }
+    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? cx.ptt[slot] : -1; }
+    photon_one(cx, slot, tile);
+  }
+}
+
+// ------------------------------------------------------------------ field
+// Blocks of FB_NODES cells of one tube.  Pass A: block sums of the node
+// charge (and, periodic, sum rho_i (N - i)), and the surface-field update
+//   E_s += dq w0 2^-24 + alpha s_co dt     (Ampere at the surface)
+// Pass B: inclusive scan (Gauss) and conversion to E and the node field.
+constexpr int FB_THREADS = 1024;
+constexpr int FB_PER = 4;
+constexpr int FB_NODES = FB_THREADS * FB_PER;
+
+struct FBlk { int32_t tube, k0, first_blk, nblk; };
+
+struct FieldCtx {
+  Tube* tubes;
+  const FBlk* fb;
+  long long* rho;
+  long long* rho_last;
+  float* E;
+  float* ebar;
+  long long* part;    // per block: sum rho
+  long long* part2;   // per block: sum rho_i (N - i)
+  int* err;
+  int mode;           // 0: step (surface update, step += 1); 1: rebuild E only
+};
+
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  long long t = 0;
+  if (threadIdx.x < WAVE) {
+    t = threadIdx.x < (int)(blockDim.x / WAVE) ? sh[threadIdx.x] : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d);
+  }
+  if (threadIdx.x == 0) sh[0] = t;
+  __syncthreads();
+  t = sh[0];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_field_a(FieldCtx f) {
+  __shared__ long long sh[FB_THREADS / WAVE];
+  const FBlk b = f.fb[blockIdx.x];
+  Tube& T = f.tubes[b.tube];
+  const int N = T.N;
+  long long s1 = 0, s2 = 0;
+  const int k = b.k0 + threadIdx.x * FB_PER;
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    if (k + i < N) {
+      long long r = f.rho[T.node_off + k + i];
+      s1 += r;
+      s2 += r * (long long)(N - (k + i));
+    }
+  }
+  s1 = block_sum_ll(s1, sh);
+  s2 = block_sum_ll(s2, sh);
+  if (threadIdx.x == 0) {
+    f.part[blockIdx.x] = s1;
+    f.part2[blockIdx.x] = s2;
+    if (b.k0 == 0 && f.mode == 0) {
+      if (!(T.flags & F_FIELD_FROZEN)) {
+        if (T.flags & F_PERIODIC) T.Es += -(double)T.dcur * T.inv_len_scale + T.drive;
+        else T.Es += (double)T.dq * T.scale + T.drive;
+      }
+      T.dq = 0;
+      T.dcur = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
+  __shared__ long long sh[FB_THREADS / WAVE];
+  const FBlk b = f.fb[blockIdx.x];
+  Tube& T = f.tubes[b.tube];
+  const int N = T.N;
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  const bool frozen = (T.flags & F_FIELD_FROZEN) != 0;
+  // carry from the tube's earlier blocks
+  long long carry = 0;
+  for (int j = b.first_blk; j < (int)blockIdx.x; ++j) carry += f.part[j];
+  double mean = 0.0;
+  if (per) {
+    long long s2 = 0;
+    for (int j = b.first_blk; j < b.first_blk + b.nblk; ++j) s2 += f.part2[j];
+    mean = ((double)s2 + (double)T.bg_unit * 0.5 * (double)N * (double)N) / (double)N;
+  }
+  const int k = b.k0 + threadIdx.x * FB_PER;
+  long long r[FB_PER];
+  long long loc = 0;
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    r[i] = (k + i < N) ? f.rho[T.node_off + k + i] : 0;
+    loc += r[i];
+  }
+  // block exclusive scan of loc
+  long long incl = loc;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    long long o = __shfl_up(incl, d);
+    if (lane_id() >= d) incl += o;
+  }
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == WAVE - 1) sh[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x < WAVE) {
+    long long v = threadIdx.x < FB_THREADS / WAVE ? sh[threadIdx.x] : 0;
+    long long iv = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      long long o = __shfl_up(iv, d);
+      if (lane_id() >= d) iv += o;
+    }
+    if (threadIdx.x < FB_THREADS / WAVE) sh[threadIdx.x] = iv - v;
+  }
+  __syncthreads();
+  long long run = carry + sh[wv] + (incl - loc);   // sum of rho over cells < k
+  const double Es = T.Es;
+  const long long bgu = T.bg_unit;
+  // E_{k-1/2} for the node field
+  double eprev;
+  if (k == 0) eprev = per ? 0.0 : Es;
+  else {
+    long long eint = run + bgu * (long long)(k - 1) + bgu / 2;
+    eprev = per ? ((double)eint - mean) * T.scale + Es : (double)eint * T.scale + Es;
+  }
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    const int kk = k + i;
+    if (kk >= N) break;
+    run += r[i];
+    const long long eint = run + bgu * (long long)kk + bgu / 2;
+    const double e = per ? ((double)eint - mean) * T.scale + Es : (double)eint * T.scale + Es;
+    if (!frozen) {
+      f.E[T.cell_off + kk] = (float)e;
+      if (kk > 0 || !per) f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+      if (!isfinite(e)) atomicOr(f.err, E_NAN);
+    }
+    f.rho_last[T.node_off + kk] = r[i];
+    f.rho[T.node_off + kk] = 0;
+    eprev = e;
+    if (kk == N - 1) {
+      // last node: non-periodic ghost E_{N+1/2} = E_{N-1/2}; periodic node 0 = node N
+      if (!frozen && !per) f.ebar[T.node_off + N] = (float)e;
+      f.rho_last[T.node_off + N] = f.rho[T.node_off + N];
+      f.rho[T.node_off + N] = 0;
+    }
+  }
+  if (threadIdx.x == 0 && f.mode == 0 && b.k0 == 0) T.step += 1;
+}
+
+// Periodic node 0 (= node N): average of E_{N-1/2} and E_{1/2}; runs after k_field_b.
+__global__ void k_field_periodic_ends(FieldCtx f, int n_tubes) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tubes) return;
+  Tube& T = f.tubes[t];
+  if (!(T.flags & F_PERIODIC) || (T.flags & F_FIELD_FROZEN)) return;
+  const float v = 0.5f * (f.E[T.cell_off + T.N - 1] + f.E[T.cell_off]);
+  f.ebar[T.node_off] = v;
+  f.ebar[T.node_off + T.N] = v;
+}
+
+// ------------------------------------------------------------------ re-sort
+template <class B> __device__ __forceinline__ bool rec_alive(const B& b, long long i);
+template <> __device__ __forceinline__ bool rec_alive<LepBuf>(const LepBuf& b, long long i) { return b.w[i] != 0.0f; }
+template <> __device__ __forceinline__ bool rec_alive<PhoBuf>(const PhoBuf& b, long long i) { return b.x[i] != 0.0f; }
+
+__device__ __forceinline__ void rec_copy(const LepBuf& s, long long i, const LepBuf& d, long long j, uint32_t pos) {
+  d.pos[j] = pos; d.u[j] = s.u[i]; d.w[j] = s.w[i]; d.id[j] = s.id[i];
+}
+__device__ __forceinline__ void rec_copy(const PhoBuf& s, long long i, const PhoBuf& d, long long j, uint32_t pos) {
+  d.pos[j] = pos; d.x[j] = s.x[i]; d.w[j] = s.w[i]; d.n0[j] = s.n0[i]; d.id[j] = s.id[i];
+}
+__device__ __forceinline__ void rec_kill(const LepBuf& d, long long j) { d.w[j] = 0.0f; }
+__device__ __forceinline__ void rec_kill(const PhoBuf& d, long long j) { d.x[j] = 0.0f; }
+
+template <class B>
+struct RbCtx {
+  const Tube* tubes;
+  const Tile* tiles;
+  B src, dst;
+  Ctl* ctl;
+  const int32_t* chunk_old;
+  int32_t* chunk_new;
+  const int32_t* tt;
+  int32_t* tcount;       // live particles per tile
+  int32_t* tcursor;
+  long long* tchunk;     // first chunk of each tile in the new layout (n_tiles + 1)
+  int n_tiles;
+};
+
+// Tile (new) of the particle in `slot`, or -1 if the slot is dead/empty.
+template <class B>
+__device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int tile_old, int* cell_out, uint32_t* frac_out) {
+  if (tile_old < 0 || !rec_alive<B>(cx.src, slot)) return -1;
+  const Tile tl = cx.tiles[tile_old];
+  const Tube& T = cx.tubes[tl.tube];
+  const uint32_t pos = cx.src.pos[slot];
+  int cell = tl.base + (int)(pos >> FRAC);
+  if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
+  *cell_out = cell;
+  *frac_out = pos & 0xFFFFFFu;
+  return T.tile_first + cell / TILE;
+}
+
+template <class B>
+__device__ __forceinline__ void rb_slot_iter(const RbCtx<B>& cx, long long c, long long nsc, long long S, long long tail,
+                                             long long* slot, int* tile) {
+  if (c < nsc) { *slot = c * CHUNK + threadIdx.x; *tile = cx.chunk_old[c]; }
+  else { *slot = S + (c - nsc) * CHUNK + threadIdx.x; *tile = *slot < S + tail ? cx.tt[*slot] : -1; }
+}
+
+template <class B>
+__global__ __launch_bounds__(CHUNK) void k_rb_count(RbCtx<B> cx) {
+  const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+    long long slot; int tile;
+    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    int cell; uint32_t frac;
+    int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    while (true) {
+      uint64_t m = __ballot(nt >= 0);
+      if (!m) break;
+      int lead = __ffsll((long long)m) - 1;
+      int k = __shfl(nt, lead);
+      uint64_t mk = __ballot(nt == k);
+      if (lane_id() == lead) atomicAdd(&cx.tcount[k], (int)__popcll(mk));
+      if (nt == k) nt = -1;
+    }
+  }
+}
+
+// Exclusive scan of the padded chunk counts over all tiles (one workgroup).
+template <class B>
+__global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
+  __shared__ long long sh[1024 / WAVE];
+  long long carry = 0;
+  for (int base = 0; base < cx.n_tiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    long long v = 0;
+    if (t < cx.n_tiles) { v = (cx.tcount[t] + CHUNK - 1) / CHUNK; cx.tcursor[t] = 0; }
+    long long incl = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      long long o = __shfl_up(incl, d);
+      if (lane_id() >= d) incl += o;
+    }
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) sh[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+      long long sv = threadIdx.x < 1024 / WAVE ? sh[threadIdx.x] : 0;
+      long long iv = sv;
+#pragma unroll
+      for (int d = 1; d < WAVE; d <<= 1) {
+        long long o = __shfl_up(iv, d);
+        if (lane_id() >= d) iv += o;
+      }
+      if (threadIdx.x < 1024 / WAVE) sh[threadIdx.x] = iv - sv;
+    }
+    __syncthreads();
+    const long long ex = carry + sh[wv] + incl - v;
+    if (t < cx.n_tiles) cx.tchunk[t] = ex;
+    __syncthreads();
+    // block total
+    if (threadIdx.x == 1023) sh[0] = ex + v;
+    __syncthreads();
+    carry = sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cx.tchunk[cx.n_tiles] = carry;
+    cx.ctl->total_chunks_new = carry;
+  }
+}
+
+template <class B>
+__global__ void k_rb_chunks(RbCtx<B> cx) {
+  const long long tot = cx.ctl->total_chunks_new;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < tot; c += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = cx.n_tiles;      // find last t with tchunk[t] <= c
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (cx.tchunk[mid] <= c) lo = mid; else hi = mid;
+    }
+    cx.chunk_new[c] = lo;
+  }
+}
+
+template <class B>
+__global__ __launch_bounds__(CHUNK) void k_rb_scatter(RbCtx<B> cx) {
+  const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+    long long slot; int tile;
+    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    int cell = 0; uint32_t frac = 0;
+    const int nt0 = rb_locate(cx, slot, tile, &cell, &frac);
+    int nt = nt0;
+    long long dst = -1;
+    while (true) {
+      uint64_t m = __ballot(nt >= 0);
+      if (!m) break;
+      int lead = __ffsll((long long)m) - 1;
+      int k = __shfl(nt, lead);
+      uint64_t mk = __ballot(nt == k);
+      int base = 0;
+      if (lane_id() == lead) base = atomicAdd(&cx.tcursor[k], (int)__popcll(mk));
+      base = __shfl(base, lead);
+      if (nt == k) { dst = cx.tchunk[k] * CHUNK + base + rank_in(mk); nt = -1; }
+    }
+    if (nt0 >= 0) {
+      const Tile tl = cx.tiles[nt0];
+      rec_copy(cx.src, slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
+    }
+  }
+}
+
+template <class B>
+__global__ __launch_bounds__(CHUNK) void k_rb_pad(RbCtx<B> cx) {
+  const long long tot = cx.ctl->total_chunks_new;
+  for (long long c = blockIdx.x; c < tot; c += gridDim.x) {
+    const int t = cx.chunk_new[c];
+    const long long slot = c * CHUNK + threadIdx.x;
+    if (slot >= cx.tchunk[t] * CHUNK + cx.tcount[t]) rec_kill(cx.dst, slot);
+  }
+}
+
+template <class B>
+__global__ void k_rb_finish(RbCtx<B> cx) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    cx.ctl->n_sorted_chunks = cx.ctl->total_chunks_new;
+    cx.ctl->tail = 0;
+    cx.ctl->tail_snap = 0;
+  }
+}
+
+// ------------------------------------------------------------------ init
+struct InitCtx {
+  const Tube* tubes;
+  const Tile* tiles;
+  LepBuf L;
+  int32_t* ltt;
+  long long base_slot;
+  const long long* tube_off;   // first init index of each tube (n_tubes + 1)
+  const int32_t* kind;         // init kind per tube
+  const int32_t* ppc;          // ppc_init per tube
+  const int32_t* k_lo;         // first initialised cell per tube
+  const float* u0;             // initial momentum per tube
+  int n_tubes;
+};
+
+__global__ void k_init_particles(InitCtx cx) {
+  const long long tot = cx.tube_off[cx.n_tubes];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = cx.n_tubes;
+    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (cx.tube_off[mid] <= i) lo = mid; else hi = mid; }
+    const int t = lo;
+    const Tube& T = cx.tubes[t];
+    const long long li = i - cx.tube_off[t];
+    const int ppc = cx.ppc[t];
+    const long long ncell = T.N - cx.k_lo[t];
+    const long long per_sp = ncell * ppc;
+    const int sp = (int)(li / per_sp);
+    const long long rem = li - (long long)sp * per_sp;
+    const int cell = cx.k_lo[t] + (int)(rem / ppc);
+    const uint64_t id = (uint64_t)li + 1;
+    u4 r = draw(T.seed, id, 0, T_INIT, 0);
+    const int tile = T.tile_first + cell / TILE;
+    const Tile tl = cx.tiles[tile];
+    const long long slot = cx.base_slot + i;
+    cx.L.pos[slot] = ((uint32_t)(cell - tl.base) << FRAC) | (r.a >> 8);
+    cx.L.u[slot] = cx.u0[t];
+    cx.L.w[slot] = (cx.kind[t] == 1 && sp == 1) ? 1.0f : -1.0f;
+    cx.L.id[slot] = id;
+    cx.ltt[slot] = tile;
+  }
+}
+
+// Deposit every live lepton (initial field, loaded states): global atomics.
+__global__ __launch_bounds__(CHUNK) void k_deposit_all(Ctx cx) {
+  const long long nsc = cx.lc->n_sorted_chunks, S = nsc * CHUNK, tail = cx.lc->tail;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+    long long slot; int tile;
+    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = cx.lchunk[c]; }
+    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? cx.ltt[slot] : -1; }
+    if (tile < 0) continue;
+    const float w = cx.L.w[slot];
+    if (w == 0.0f) continue;
+    const Tile tl = cx.tiles[tile];
+    const Tube& T = cx.tubes[tl.tube];
+    const bool per = (T.flags & F_PERIODIC) != 0;
+    const uint32_t pos = cx.L.pos[slot];
+    int cell = tl.base + (int)(pos >> FRAC);
+    if (per) cell = wrap_cell(cell, T.N);
+    const uint32_t frac = pos & 0xFFFFFFu;
+    const int64_t Tw = __float2ll_rn(fabsf(w) * 16777216.0f);
+    const unsigned long long A = ((unsigned long long)Tw * frac + (1ull << 23)) >> FRAC;
+    const long long a = w > 0 ? (long long)A : -(long long)A;
+    const long long ta = w > 0 ? (long long)(Tw - (int64_t)A) : -(long long)(Tw - (int64_t)A);
+    int n1 = cell + 1;
+    if (per && n1 == T.N) n1 = 0;
+    atomicAdd((unsigned long long*)&cx.rho[T.node_off + cell], (unsigned long long)ta);
+    atomicAdd((unsigned long long*)&cx.rho[T.node_off + n1], (unsigned long long)a);
+  }
+}
+
+// Live particles per tube (diagnostics).
+template <class B>
+__global__ __launch_bounds__(CHUNK) void k_count_live(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
+                                                       const Tile* tiles, long long* out) {
+  const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
+  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+    long long slot; int tile;
+    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = chunk[c]; }
+    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? tt[slot] : -1; }
+    int t = (tile >= 0 && rec_alive<B>(buf, slot)) ? tiles[tile].tube : -1;
+    while (true) {
+      uint64_t m = __ballot(t >= 0);
+      if (!m) break;
+      int lead = __ffsll((long long)m) - 1;
+      int k = __shfl(t, lead);
+      uint64_t mk = __ballot(t == k);
+      if (lane_id() == lead) atomicAdd((unsigned long long*)&out[k], (unsigned long long)__popcll(mk));
+      if (t == k) t = -1;
+    }
+  }
+}
+
+}  // namespace gap

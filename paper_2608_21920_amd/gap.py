@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libgap (argument marshalling only).
+
+Every step of the particle loop runs in the library's HIP kernels; PyTorch
+provides device memory (through the allocator callbacks) and the stream.
+There is no CPU fallback: constructing a ``Gap`` without the built library
+or without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgap.so")
+
+QED_OFF, ETA_CO_OFF, FIELD_FROZEN, RECOIL_OFF, PERIODIC, MERGE_ON, TRACK_ALL, ANTI_ALIGNED = \
+    1, 2, 4, 8, 16, 32, 64, 128
+CONV_OFF, EMIT_OFF = 1024, 2048
+FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32, TRACK_ALL=64,
+             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048)
+
+ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
+          -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
+
+DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED = range(8)
+STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION = range(4)
+
+COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
+              "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
+              "lep_steps", "pho_steps", "rebuckets"]
+
+LEPTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("u", "<f4"), ("w", "<f4"), ("id", "<u8")])
+PHOTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("x", "<f4"), ("w", "<f4"), ("n0", "<i4"),
+                         ("pad", "<i4"), ("id", "<u8")])
+
+
+class GapError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s%s" % (ERRORS.get(code, str(code)), (": " + what) if what else ""))
+
+
+class GapParams(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int32), ("init_kind", C.c_int32), ("ppc_init", C.c_int32), ("ppc_ref", C.c_int32),
+        ("dx", C.c_double), ("cfl", C.c_double), ("alpha", C.c_double), ("b", C.c_double),
+        ("r_curv_cm", C.c_double), ("period_s", C.c_double), ("lambda_c_scale", C.c_double),
+        ("r_curv_scale", C.c_double), ("h_gap_frac", C.c_double), ("inj_rate", C.c_double),
+        ("inj_weight", C.c_double), ("x_thr", C.c_double), ("xc_floor", C.c_double), ("u_init", C.c_double),
+        ("merge_frac", C.c_double), ("seed", C.c_uint64), ("cap_leptons", C.c_int64), ("cap_photons", C.c_int64),
+        ("flags", C.c_uint32), ("nsub_max", C.c_int32), ("merge_every", C.c_int32), ("rebucket_every", C.c_int32),
+    ]
+
+
+class GapAllocator(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)),
+                ("ctx", C.c_void_p)]
+
+
+_DEFAULTS = dict(n_cells=1024, init_kind=1, ppc_init=16, ppc_ref=16, dx=0.25, cfl=0.45, alpha=1.5, b=0.1,
+                 r_curv_cm=1e7, period_s=1.0, lambda_c_scale=1.0, r_curv_scale=1.0, h_gap_frac=0.8, inj_rate=0.0,
+                 inj_weight=1.0, x_thr=2.0, xc_floor=1e-2, u_init=0.0, merge_frac=0.9, seed=0,
+                 cap_leptons=1 << 22, cap_photons=1 << 22, flags=0, nsub_max=64, merge_every=64, rebucket_every=0)
+
+
+def make_params(cfg: dict) -> GapParams:
+    p = GapParams()
+    for k, v in _DEFAULTS.items():
+        setattr(p, k, cfg.get(k, v))
+    if cfg.get("merge"):
+        p.flags |= MERGE_ON
+    return p
+
+
+_lib = None
+
+
+def load_library():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgap.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.gap_init.restype = C.c_int
+    lib.gap_init.argtypes = [P(GapParams), C.c_int32, C.c_void_p, P(GapAllocator), P(C.c_void_p)]
+    lib.gap_step.restype = C.c_int
+    lib.gap_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.gap_step_graph.restype = C.c_int
+    lib.gap_step_graph.argtypes = [C.c_void_p, C.c_int64]
+    lib.gap_sync.restype = C.c_int
+    lib.gap_sync.argtypes = [C.c_void_p]
+    lib.gap_diag.restype = C.c_int
+    lib.gap_diag.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, P(C.c_size_t)]
+    lib.gap_set_state.restype = C.c_int
+    lib.gap_set_state.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t]
+    lib.gap_free.restype = None
+    lib.gap_free.argtypes = [C.c_void_p]
+    lib.gap_strerror.restype = C.c_char_p
+    lib.gap_strerror.argtypes = [C.c_int]
+    lib.gap_sync_inverse_host.restype = C.c_int
+    lib.gap_sync_inverse_host.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+    _lib = lib
+    return lib
+
+
+def _check(code, what=""):
+    if code != 0:
+        raise GapError(code, what)
+
+
+def sync_inverse_host(r) -> np.ndarray:
+    """The library's table sampler of the photon spectrum, on the host."""
+    lib = load_library()
+    r = np.ascontiguousarray(r, dtype=np.float32)
+    out = np.empty_like(r)
+    _check(lib.gap_sync_inverse_host(r.ctypes.data, out.ctypes.data, r.size), "gap_sync_inverse_host")
+    return out
+
+
+class Gap:
+    """A set of flux tubes advanced on the current torch stream of ``device``."""
+
+    def __init__(self, cfgs, device="cuda:0", stream=None, use_torch_alloc=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Gap needs a GPU (no CPU fallback)")
+        self.torch = torch
+        self.device = torch.device(device)
+        lib = load_library()
+        self.lib = lib
+        if isinstance(cfgs, dict):
+            cfgs = [cfgs]
+        self.cfgs = [dict(c) for c in cfgs]
+        self.n_tubes = len(cfgs)
+        arr = (GapParams * self.n_tubes)(*[make_params(c) for c in cfgs])
+        self._params = arr
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self._bufs = {}
+            alloc_p = None
+            if use_torch_alloc:
+                dev = self.device
+
+                def _alloc(nbytes, ctx):
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                    self._bufs[t.data_ptr()] = t
+                    return t.data_ptr()
+
+                def _free(ptr, ctx):
+                    self._bufs.pop(ptr, None)
+                self._cb = GapAllocator(GapAllocator._fields_[0][1](_alloc), GapAllocator._fields_[1][1](_free), None)
+                alloc_p = C.byref(self._cb)
+            h = C.c_void_p()
+            code = lib.gap_init(arr, self.n_tubes, C.c_void_p(self.stream.cuda_stream), alloc_p, C.byref(h))
+            _check(code, "gap_init")
+            self.h = h
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gap_free(self.h)
+            self.h = None
+            self._bufs = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping
+    def step(self, n=1):
+        _check(self.lib.gap_step(self.h, int(n)), "gap_step")
+
+    def step_graph(self, n):
+        _check(self.lib.gap_step_graph(self.h, int(n)), "gap_step_graph")
+
+    def sync(self):
+        _check(self.lib.gap_sync(self.h), "gap_sync")
+
+    # -- diagnostics
+    def _diag(self, kind, tube, nbytes):
+        buf = np.empty(max(int(nbytes), 1), np.uint8)
+        wr = C.c_size_t(0)
+        code = self.lib.gap_diag(self.h, kind, tube, buf.ctypes.data, buf.nbytes, C.byref(wr))
+        if code == -1 and wr.value > buf.nbytes:
+            buf = np.empty(wr.value, np.uint8)
+            code = self.lib.gap_diag(self.h, kind, tube, buf.ctypes.data, buf.nbytes, C.byref(wr))
+        _check(code, "gap_diag(%d)" % kind)
+        return buf[:wr.value]
+
+    def counts(self, tube=0) -> dict:
+        v = self._diag(DIAG_COUNTS, tube, 256).view(np.int64)
+        return {k: int(v[i]) for i, k in enumerate(COUNT_KEYS)}
+
+    def n_cells(self, tube=0):
+        return int(self.cfgs[tube]["n_cells"])
+
+    def field(self, tube=0) -> np.ndarray:
+        return self._diag(DIAG_FIELD, tube, 4 * self.n_cells(tube)).view(np.float32).copy()
+
+    def node_field(self, tube=0) -> np.ndarray:
+        return self._diag(DIAG_NODE_E, tube, 4 * (self.n_cells(tube) + 1)).view(np.float32).copy()
+
+    def rho(self, tube=0) -> np.ndarray:
+        return self._diag(DIAG_RHO, tube, 8 * (self.n_cells(tube) + 1)).view(np.int64).copy()
+
+    def es(self, tube=0) -> float:
+        return float(self._diag(DIAG_ES, tube, 8).view(np.float64)[0])
+
+    def derived(self, tube=0) -> dict:
+        v = self._diag(DIAG_DERIVED, tube, 64).view(np.float64)
+        return dict(d_cm=v[0], lam=v[1], rc=v[2], dt=v[3], H=v[4], w0=v[5], s_co=v[6], N=int(v[7]))
+
+    def leptons(self, tube=0) -> np.ndarray:
+        return self._diag(DIAG_LEPTONS, tube, 0).view(LEPTON_DTYPE).copy()
+
+    def photons(self, tube=0) -> np.ndarray:
+        return self._diag(DIAG_PHOTONS, tube, 0).view(PHOTON_DTYPE).copy()
+
+    # -- state loading (single tube)
+    def set_particles(self, lep: np.ndarray, pho: np.ndarray | None = None):
+        lep = np.ascontiguousarray(lep, dtype=LEPTON_DTYPE)
+        pho = np.zeros(0, PHOTON_DTYPE) if pho is None else np.ascontiguousarray(pho, dtype=PHOTON_DTYPE)
+        hdr = np.array([lep.size, pho.size], np.int64)
+        buf = np.concatenate([hdr.view(np.uint8), lep.view(np.uint8), pho.view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_PARTICLES, 0, buf.ctypes.data, buf.nbytes), "set_particles")
+
+    def set_es_step(self, es: float, step: int):
+        buf = np.concatenate([np.array([es], np.float64).view(np.uint8), np.array([step], np.int64).view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_ES_STEP, 0, buf.ctypes.data, buf.nbytes), "set_es_step")
+
+    def set_field(self, E: np.ndarray, es: float):
+        buf = np.concatenate([np.ascontiguousarray(E, np.float32).view(np.uint8),
+                              np.array([es], np.float64).view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_FIELD, 0, buf.ctypes.data, buf.nbytes), "set_field")
+
+    def set_injection(self, acc: float, count: int):
+        buf = np.concatenate([np.array([acc], np.float64).view(np.uint8), np.array([count], np.uint64).view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_INJECTION, 0, buf.ctypes.data, buf.nbytes), "set_injection")
