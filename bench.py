@@ -1,0 +1,183 @@
+"""Benchmark of the per-step particle loop on one MI355X.
+
+A step is one pass of the whole loop (injection, lepton pass, photon pass,
+field, periodic re-sort) over the production gap: 65536 cells, alpha = 1.5,
+b = 0.1, R_curv = 1e7 cm, surface injection 0.1 n_co dx per step, started from
+the seeded initial state and grown (untimed) by the physics itself until the
+stores hold at least --grow-to particles.  Then --warmup untimed steps and
+--steps timed steps; inputs are resident in HBM throughout.
+
+Prints one JSON line.  `value` is particle-steps/s (leptons + photons
+advanced by one step), `roofline` is the dominant kernel's algorithmic HBM
+bytes per launch over its average launch time (HIP events on the library's
+stream), `cpu_baseline` is the FP64 oracle on a bounded sample of the same
+grown state, on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per unit of work: lepton-step reads
+# position, momentum, weight and writes position, momentum; an emission
+# evaluation also reads the 8-byte id.  Photon-step reads position, energy,
+# birth step and writes position; a conversion evaluation also reads id, weight.
+B_LEP, B_EMIT_EVAL, B_PHO, B_CONV_EVAL = 20, 8, 16, 12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def grow(g, target, max_steps, block=1000):
+    t0 = time.time()
+    while True:
+        c = g.counts()
+        n = c["n_lep"] + c["n_pho"]
+        if n >= target or c["step"] >= max_steps:
+            log("grown: step %d leptons %d photons %d (%.1f s)" % (c["step"], c["n_lep"], c["n_pho"], time.time() - t0))
+            return c
+        g.step(block)
+        g.sync()
+        log("  grow: step %d particles %d" % (c["step"] + block, n))
+
+
+def cpu_baseline(g, budget_s=15.0, sample=400_000):
+    """Oracle particle-steps/s on a random sample of the grown GPU state."""
+    from oracle.oracle import Oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import gpu_leptons_as_oracle, gpu_photons_as_oracle
+    L, P = g.leptons(), g.photons()
+    rng = np.random.default_rng(0)
+    nl = min(L.size, int(sample * L.size / max(L.size + P.size, 1)))
+    npho = min(P.size, sample - nl)
+    L = L[rng.choice(L.size, nl, replace=False)] if nl < L.size else L
+    P = P[rng.choice(P.size, npho, replace=False)] if npho < P.size else P
+    o = Oracle(g.cfgs[0])
+    step = g.counts()["step"]
+    o.set_state(gpu_leptons_as_oracle(L), gpu_photons_as_oracle(P), Es=g.es(), step=step)
+    t0 = time.time()
+    done = 0
+    ps = 0
+    while time.time() - t0 < budget_s and done < 50:
+        c0 = o.counts()
+        o.step(1)
+        c1 = o.counts()
+        ps += c0["n_lep"] + c0["n_pho"]
+        done += 1
+    el = time.time() - t0
+    return dict(value=ps / el, unit="particle-steps/s", cores=1, kind="oracle",
+                sample="%d leptons + %d photons drawn from the grown state, %d steps (%.1f s)" % (nl, npho, done, el))
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size, for scaling HBM traffic counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--grow-to", type=float, default=2.0e7)
+    ap.add_argument("--max-grow-steps", type=int, default=90000)
+    ap.add_argument("--graph", action="store_true", help="time graph replays instead of eager steps")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if a.copy_calib:
+        copy_calibration(a.copy_calib)
+        return
+
+    import torch
+    from paper_2608_21920_amd import Gap, workloads
+    cfg = dict(workloads.PRODUCTION)
+    g = Gap(cfg)
+    grow(g, a.grow_to, a.max_grow_steps)
+    g.step(a.warmup)
+    g.sync()
+
+    c0 = g.counts()
+    g.set_timing(not a.graph)
+    s = g.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    if a.graph:
+        g.step_graph(a.steps)
+    else:
+        g.step(a.steps)
+    e1.record(s)
+    g.sync()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tim = g.timing()
+    g.set_timing(False)
+    c1 = g.counts()
+    assert c1["err"] == 0, c1
+
+    d = {k: c1[k] - c0[k] for k in c1}
+    psteps = d["lep_steps"] + d["pho_steps"]
+    value = psteps / (ms / 1e3)
+    # algorithmic bytes of the sorted-region kernels and of the tail kernels
+    bytes_lep = B_LEP * (d["lep_steps"] - d["lep_steps_tail"]) + B_EMIT_EVAL * (d["n_emit_eval"] - d["emit_eval_tail"])
+    bytes_pho = B_PHO * (d["pho_steps"] - d["pho_steps_tail"]) + B_CONV_EVAL * (d["n_conv_eval"] - d["conv_eval_tail"])
+    bytes_lep_t = B_LEP * d["lep_steps_tail"] + B_EMIT_EVAL * d["emit_eval_tail"]
+    bytes_pho_t = B_PHO * d["pho_steps_tail"] + B_CONV_EVAL * d["conv_eval_tail"]
+    kern = {}
+    if not a.graph:
+        for name, byt in (("leptons", bytes_lep), ("photons", bytes_pho), ("leptons_tail", bytes_lep_t),
+                          ("photons_tail", bytes_pho_t)):
+            n, tms = tim[name]
+            kern[name] = dict(launches=n, avg_ms=tms / max(n, 1), bytes_per_launch=byt / max(n, 1),
+                              gbs=(byt / max(n, 1)) / (tms / max(n, 1) / 1e3) / 1e9 if tms > 0 else None)
+        dom = max(("leptons", "photons"), key=lambda k: tim[k][1])
+        roof = dict(bound="hbm", achieved=kern[dom]["gbs"], peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=kern[dom]["gbs"] / PEAK_HBM_GBS, traffic=None, kernel="k_" + dom,
+                    bytes_per_launch=kern[dom]["bytes_per_launch"], avg_launch_ms=kern[dom]["avg_ms"])
+    else:
+        roof = None
+    out = {
+        "metric": "particle-steps/s (leptons + photons), % of HBM roofline of the dominant kernel",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded initial gap grown by the simulation itself)",
+        "config": {"workload": "production gap: 65536 cells, alpha 1.5, b 0.1, R_curv 1e7 cm, surface "
+                               "injection 0.1 n_co dx/step, caps 5e7 per species",
+                   "n_cells": cfg["n_cells"], "step_at_start": c0["step"], "leptons": c0["n_lep"],
+                   "photons": c0["n_pho"], "parallelism": "single GPU", "graph": a.graph},
+        "roofline": roof,
+        "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if not a.graph else None,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g)
+    g.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,10 @@ int gap_sync(gap_t* g);
                                      int32 pad, uint64 id}                                 */
 #define GAP_DIAG_NODE_E   6  /* float[N+1]: node field used by the gather                   */
 #define GAP_DIAG_DERIVED  7  /* double[8]: d_cm, lambda~, R~, dt, H, w0, s_co, N            */
+#define GAP_DIAG_TIMING   8  /* double[14]: (launches, summed ms) of the lepton pass, photon
+                                pass, field, re-sort, prologue, lepton tail pass and photon
+                                tail pass since timing was enabled or last read (tube
+                                ignored; resets the record)                                 */
 
 /* indices of GAP_DIAG_COUNTS */
 #define GAP_C_LEPTONS     0   /* live leptons                      */
@@ -154,6 +158,10 @@ int gap_sync(gap_t* g);
 #define GAP_C_LEP_STEPS   15  /* lepton-steps taken                */
 #define GAP_C_PHO_STEPS   16  /* photon-steps taken                */
 #define GAP_C_REBUCKETS   17  /* re-sorts of the stores            */
+#define GAP_C_LEP_STEPS_TAIL 18  /* part of GAP_C_LEP_STEPS taken by the tail pass   */
+#define GAP_C_EMIT_EVAL_TAIL 19  /* part of GAP_C_EMIT_EVAL taken by the tail pass   */
+#define GAP_C_PHO_STEPS_TAIL 20  /* part of GAP_C_PHO_STEPS taken by the tail pass   */
+#define GAP_C_CONV_EVAL_TAIL 21  /* part of GAP_C_CONV_EVAL taken by the tail pass   */
 
 /* Copy a diagnostic of tube `tube` into host_buf (buf_bytes long); waits for
  * queued work.  *bytes_written receives the size used.  GAP_EINVAL if the
@@ -166,8 +174,11 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
 #define GAP_STATE_ES_STEP   1  /* double E_s, then int64 step                                  */
 #define GAP_STATE_FIELD     2  /* float E[N] then double E_s (for GAP_FIELD_FROZEN runs)       */
 #define GAP_STATE_INJECTION 3  /* double accumulator, then uint64 injected count              */
+#define GAP_STATE_TIMING    4  /* int32 on/off: HIP-event timing of each kernel group of
+                                  eager gap_step calls (not of graph replays)                  */
 
-/* Replace part of the state of tube `tube` (only valid when n_tubes == 1).
+/* Replace part of the state of tube `tube` (only valid when n_tubes == 1;
+ * GAP_STATE_TIMING is valid for any handle).
  * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);

@@ -177,9 +177,16 @@ struct gap_t {
   float* tab = nullptr;
   int* err = nullptr;
   long long* live = nullptr;
+  long long* shard = nullptr;   // [tube][NSHARD][C_N] event counters
   Store lep, pho;
+  // per-kernel event timing (eager steps only)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;   // (kernel id, start, stop)
   int R = 64;
   int64_t since_rb = 0;
+  int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
   bool any_periodic = false;
   int sticky = 0;
   // graph: replay is valid from the recorded start state and leaves the end state
@@ -210,6 +217,8 @@ void* dalloc(gap_t* g, size_t bytes) {
 void release(gap_t* g) {
   if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
   if (g->s) (void)hipStreamSynchronize(g->s);
+  for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
+  g->ev_pool.clear();
   for (void* p : g->owned) {
     if (g->custom_alloc) g->al.free(p, g->al.ctx);
     else (void)hipFree(p);
@@ -279,8 +288,34 @@ Ctx make_ctx(gap_t* g) {
   c.ebar = g->ebar;
   c.tab = g->tab;
   c.err = g->err;
+  c.shard = g->shard;
   return c;
 }
+
+hipEvent_t next_event(gap_t* g) {
+  if (g->ev_used == g->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g->ev_pool.push_back(e);
+  }
+  return g->ev_pool[g->ev_used++];
+}
+
+// kernel ids of the timing diagnostic
+enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_LEPTAIL = 5, KT_PHOTAIL = 6, KT_N = 7 };
+
+struct Timer {
+  gap_t* g; int id; hipEvent_t a = nullptr, b = nullptr;
+  Timer(gap_t* gg, int i) : g(gg), id(i) {
+    if (g->timing && g->ev_pool.size() < 200000) {
+      a = next_event(g); b = next_event(g);
+      if (a) (void)hipEventRecord(a, g->s);
+    }
+  }
+  ~Timer() {
+    if (a && b) { (void)hipEventRecord(b, g->s); g->ev_marks.push_back({id, {a, b}}); }
+  }
+};
 
 FieldCtx make_fctx(gap_t* g, int mode) {
   FieldCtx f;
@@ -352,11 +387,14 @@ void rebuild_field(gap_t* g) {
 
 void enqueue_step(gap_t* g) {
   Ctx cx = make_ctx(g);
-  k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
-  k_leptons<<<kGrid, CHUNK, 0, g->s>>>(cx);
-  k_photons<<<kGrid, CHUNK, 0, g->s>>>(cx);
-  field_pass(g, 0);
+  { Timer t(g, KT_PRE); k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes); }
+  { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, CHUNK, 0, g->s>>>(cx); }
+  { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, CHUNK, 0, g->s>>>(cx); }
+  { Timer t(g, KT_PHOTONS); k_photons<<<g->grid_pho, CHUNK, 0, g->s>>>(cx); }
+  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, CHUNK, 0, g->s>>>(cx); }
+  { Timer t(g, KT_FIELD); field_pass(g, 0); }
   if (++g->since_rb >= g->R) {
+    Timer t(g, KT_RESORT);
     rebucket_all(g);
     g->since_rb = 0;
   }
@@ -448,6 +486,11 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     T.x_thr = (float)q.x_thr;
     T.emit_k = (float)(kAlphaEM * d.dt / d.rc);
     T.conv_k = (float)(kAlphaEM * d.dt * q.b / d.lam);
+    {
+      // p <= conv_k 0.23 exp(-8/(3 chi)) <= 2^-27 for chi <= chi_skip
+      const double a = 0.23 * (double)T.conv_k * 134217728.0;
+      T.chi_skip = a > 1.0 ? (float)(8.0 / (3.0 * std::log(a))) : 3.0e38f;
+    }
     T.dpho = (int32_t)std::llrint(q.cfl * kTwo24);
     T.dtd = d.dt;
     T.scale = d.w0 / kTwo24;
@@ -481,6 +524,17 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   }
   g->R = rmin;
   g->n_fb = (int)g->fb_h.size();
+  {
+    // one resident round of workgroups for the persistent-range passes
+    int dev = 0, cus = 0, nl = 0, np = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons, CHUNK, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, CHUNK, 0));
+    g->grid_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
+    g->grid_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
+    g->grid_tail = std::max(8, cus * 4);
+  }
   if (g->total_nodes > (1LL << 30)) return GAP_EINVAL;
 
   g->tubes = (Tube*)dalloc(g, sizeof(Tube) * n_tubes);
@@ -495,6 +549,8 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->tab = (float*)dalloc(g, sizeof(float) * 2 * (NTAB + 1));
   g->err = (int*)dalloc(g, sizeof(int));
   g->live = (long long*)dalloc(g, sizeof(long long) * n_tubes);
+  g->shard = (long long*)dalloc(g, sizeof(long long) * n_tubes * NSHARD * C_N);
+  if (!g->shard) return GAP_ENOMEM;
   if (!g->tubes || !g->tiles || !g->rho || !g->rho_last || !g->E || !g->ebar || !g->fb || !g->part || !g->part2 ||
       !g->tab || !g->err || !g->live)
     return GAP_ENOMEM;
@@ -687,6 +743,18 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       if ((e = download_tubes(g))) return e;
       int64_t* o = (int64_t*)host_buf;
       for (int i = 0; i < 32; ++i) o[i] = g->th[tube].cnt[i];
+      {
+        std::vector<long long> sh((size_t)NSHARD * C_N);
+        HIPCHK(hipMemcpy(sh.data(), g->shard + (size_t)tube * NSHARD * C_N, sizeof(long long) * sh.size(),
+                         hipMemcpyDeviceToHost));
+        for (int k = 0; k < NSHARD; ++k)
+          for (int i = 0; i < 32; ++i) o[i] += sh[(size_t)k * C_N + i];
+        // totals include the tail passes (the *_TAIL slots hold that part)
+        o[GAP_C_LEP_STEPS] += o[GAP_C_LEP_STEPS_TAIL];
+        o[GAP_C_EMIT_EVAL] += o[GAP_C_EMIT_EVAL_TAIL];
+        o[GAP_C_PHO_STEPS] += o[GAP_C_PHO_STEPS_TAIL];
+        o[GAP_C_CONV_EVAL] += o[GAP_C_CONV_EVAL_TAIL];
+      }
       long long lv[2] = {0, 0};
       const int grid = kGrid;
       k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
@@ -721,6 +789,21 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       if (!fits(sizeof(double))) return GAP_EINVAL;
       if ((e = download_tubes(g))) return e;
       std::memcpy(host_buf, &g->th[tube].Es, sizeof(double));
+      return GAP_OK;
+    }
+    case GAP_DIAG_TIMING: {
+      // double[2 * KT_N]: launches and summed milliseconds per kernel group
+      if (!fits(sizeof(double) * 2 * KT_N)) return GAP_EINVAL;
+      double* o = (double*)host_buf;
+      for (int i = 0; i < 2 * KT_N; ++i) o[i] = 0.0;
+      for (auto& m : g->ev_marks) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, m.second.first, m.second.second));
+        o[2 * m.first] += 1.0;
+        o[2 * m.first + 1] += ms;
+      }
+      g->ev_marks.clear();
+      g->ev_used = 0;
       return GAP_OK;
     }
     case GAP_DIAG_DERIVED: {
@@ -763,6 +846,15 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
 
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes) {
   if (!g || !host_buf || tube < 0 || tube >= g->n_tubes) return GAP_EINVAL;
+  if (kind == GAP_STATE_TIMING) {
+    if (bytes < 4) return GAP_EINVAL;
+    int32_t on;
+    std::memcpy(&on, host_buf, 4);
+    g->timing = on != 0;
+    g->ev_marks.clear();
+    g->ev_used = 0;
+    return GAP_OK;
+  }
   if (g->n_tubes != 1) return GAP_ESTATE;
   int e = sync_and_err(g);
   if (e == GAP_EDEVICE) return e;

@@ -30,7 +30,8 @@ constexpr float TAB_YHI = 17.5f;
 enum : int {
   C_LEPTONS = 0, C_PHOTONS = 1, C_STEP = 2, C_EMIT = 3, C_PHO_BORN = 4, C_CONV = 5, C_ABSORBED = 6,
   C_OUTFLOW = 7, C_PHO_EXIT = 8, C_DROPPED = 9, C_MERGED = 10, C_ERR = 11, C_INJECTED = 12,
-  C_EMIT_EVAL = 13, C_CONV_EVAL = 14, C_LEP_STEPS = 15, C_PHO_STEPS = 16, C_REBUCKETS = 17, C_N = 32
+  C_EMIT_EVAL = 13, C_CONV_EVAL = 14, C_LEP_STEPS = 15, C_PHO_STEPS = 16, C_REBUCKETS = 17,
+  C_LEP_STEPS_TAIL = 18, C_EMIT_EVAL_TAIL = 19, C_PHO_STEPS_TAIL = 20, C_CONV_EVAL_TAIL = 21, C_N = 32
 };
 
 enum : uint32_t {
@@ -53,7 +54,8 @@ struct Tube {
   float xc_floor, x_thr;
   float emit_k;             // alpha_em * dt / R~
   float conv_k;             // alpha_em * dt * b / lambda~
-  float dtf_unused0, dtf_unused1;
+  float chi_skip;           // photons with chi below this cannot convert in one step
+  float pad3;
   int32_t dpho;             // photon displacement per step: rint(cfl 2^24)
   int32_t pad1;
   // double constants of the field
@@ -132,14 +134,19 @@ __device__ __forceinline__ uint64_t child_id(uint64_t seed, uint64_t parent, int
 }
 
 // ---------------------------------------------------------------- QED fits
-// emission-rate function of Sect. 3.1 (fit quoted with eq. tau_syn)
+// emission-rate function of Sect. 3.1 (fit quoted with eq. tau_syn):
+// 5/(2 sqrt 3) (1 + 16 sqrt3/5 chi + 1.1 chi^2)^(-1/6), via the hardware
+// base-2 logarithm and exponential
 __device__ __forceinline__ float t_syn(float chi) {
-  return 1.4433756729740644f * powf(1.0f + 5.5425625842204074f * chi + 1.1f * chi * chi, -1.0f / 6.0f);
+  const float v = 1.0f + 5.5425625842204074f * chi + 1.1f * chi * chi;
+  return 1.4433756729740644f * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * (-1.0f / 6.0f));
 }
-// pair-creation function of Sect. 3.2 (fit quoted with eq. tau_bw)
+// pair-creation function of Sect. 3.2 (fit quoted with eq. tau_bw):
+// 0.23 exp(-8/(3 chi)) (1 + 0.22 chi)^(-1/3)
 __device__ __forceinline__ float t_bw(float chi) {
   if (!(chi > 0.0f)) return 0.0f;
-  return 0.23f * expf(-8.0f / (3.0f * chi)) * powf(1.0f + 0.22f * chi, -1.0f / 3.0f);
+  const float e = -3.8471206f / chi - __builtin_amdgcn_logf(1.0f + 0.22f * chi) * (1.0f / 3.0f);   // 8/3 log2(e)
+  return 0.23f * __builtin_amdgcn_exp2f(e);
 }
 
 // Classical synchrotron number spectrum: xi = C^-1(r) from the table.

@@ -23,13 +23,20 @@ struct Ctx {
   const float* ebar;      // node field, sum_t (N_t + 1)
   const float* tab;       // photon spectrum table
   int* err;
+  long long* shard;       // event counters [tube][NSHARD][C_N], summed by the host
 };
+
+constexpr int NSHARD = 64;
+
+__device__ __forceinline__ long long* shard_at(long long* sh, int tube, int idx) {
+  return sh + ((long long)tube * NSHARD + (blockIdx.x % NSHARD)) * C_N + idx;
+}
 
 __device__ __forceinline__ int wrap_cell(int c, int N) { return c < 0 ? c + N : (c >= N ? c - N : c); }
 
 // Add `v` to counter `idx` of the tube `t` of each lane (t < 0: no-op), one
 // atomic per distinct tube in the wave.
-__device__ __forceinline__ void count_by_tube(Tube* tubes, int t, int idx, int64_t v) {
+__device__ __forceinline__ void count_by_tube(long long* shard, int t, int idx, int64_t v) {
   while (true) {
     uint64_t m = __ballot(t >= 0);
     if (!m) break;
@@ -38,9 +45,60 @@ __device__ __forceinline__ void count_by_tube(Tube* tubes, int t, int idx, int64
     long long s = (t == k) ? (long long)v : 0ll;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    if (lane_id() == lead && s != 0) atomic_add_i64(&tubes[k].cnt[idx], (int64_t)s);
+    if (lane_id() == lead && s != 0) atomicAdd((unsigned long long*)shard_at(shard, k, idx), (unsigned long long)s);
     if (t == k) t = -1;
   }
+}
+
+// Per-thread event counts of one tube, reduced over the workgroup and added
+// to the tube's shard once per flush (not once per wave).
+struct LocalCounts {
+  int v[8];
+  __device__ void clear() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0;
+  }
+};
+
+// counter slots of the lepton (KIND 0) and photon (KIND 1) passes; the tail
+// passes (KIND 2, 3) count their particle-steps and evaluations separately
+template <int KIND>
+__device__ __forceinline__ int cnt_index(int i) {
+  if (KIND == 2 && i == 0) return C_LEP_STEPS_TAIL;
+  if (KIND == 2 && i == 1) return C_EMIT_EVAL_TAIL;
+  if (KIND == 3 && i == 0) return C_PHO_STEPS_TAIL;
+  if (KIND == 3 && i == 1) return C_CONV_EVAL_TAIL;
+  if (KIND == 0 || KIND == 2) {
+    switch (i) {
+      case 0: return C_LEP_STEPS; case 1: return C_EMIT_EVAL; case 2: return C_EMIT; case 3: return C_PHO_BORN;
+      case 4: return C_DROPPED; case 5: return C_ABSORBED; case 6: return C_OUTFLOW; default: return -1;
+    }
+  }
+  switch (i) {
+    case 0: return C_PHO_STEPS; case 1: return C_CONV_EVAL; case 2: return C_CONV; case 3: return C_DROPPED;
+    case 4: return C_PHO_EXIT; default: return -1;
+  }
+}
+
+template <int KIND>
+__device__ void flush_counts(long long* shard, int tube, LocalCounts& lc, long long* s_cnt) {
+  __syncthreads();
+  if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int x = lc.v[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    if (lane_id() == 0 && x != 0) atomicAdd((unsigned long long*)&s_cnt[i], (unsigned long long)(long long)x);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int ci = cnt_index<KIND>(threadIdx.x);
+    if (ci >= 0 && s_cnt[threadIdx.x] != 0)
+      atomicAdd((unsigned long long*)shard_at(shard, tube, ci), (unsigned long long)s_cnt[threadIdx.x]);
+  }
+  lc.clear();
 }
 
 // Exclusive prefix sum of `v` over the wave; returns the exclusive value and
@@ -127,38 +185,110 @@ __device__ void flush_window(const Ctx& cx, int tile, long long* s_rho) {
   __syncthreads();
 }
 
+// Constants of one tile and its tube, read once per tile switch and held in
+// scalar registers (the tube records are also written by the kernels, so the
+// compiler cannot turn per-lane reads of them into scalar loads).
+struct KC {
+  int tile, tube, base, N, node_off, flags, nsub_max, dpho;
+  int64_t step, hfix;
+  float dt, lr, inv_rc, b, xc_floor, x_thr, emit_k, conv_k, cfl24, chi_skip;
+  uint64_t seed;
+};
+
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float rfl(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ int64_t rfl(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
+  KC k;
+  tile = rfl(tile);
+  const Tile tl = cx.tiles[tile];
+  const Tube& T = cx.tubes[rfl(tl.tube)];
+  k.tile = tile;
+  k.tube = rfl(tl.tube);
+  k.base = rfl(tl.base);
+  k.N = rfl(T.N);
+  k.node_off = rfl(T.node_off);
+  k.flags = rfl(T.flags);
+  k.nsub_max = rfl(T.nsub_max);
+  k.dpho = rfl(T.dpho);
+  k.step = rfl((int64_t)T.step);
+  k.hfix = rfl((int64_t)T.hfix);
+  k.dt = rfl(T.dt);
+  k.lr = rfl(T.lr);
+  k.inv_rc = rfl(T.inv_rc);
+  k.b = rfl(T.b);
+  k.xc_floor = rfl(T.xc_floor);
+  k.x_thr = rfl(T.x_thr);
+  k.emit_k = rfl(T.emit_k);
+  k.conv_k = rfl(T.conv_k);
+  k.cfl24 = rfl(T.cfl24);
+  k.chi_skip = rfl(T.chi_skip);
+  k.seed = (uint64_t)rfl((int64_t)T.seed);
+  return k;
+}
+
+// The same constants for a lane's own tile (tail chunks: not uniform).
+__device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
+  KC k;
+  const Tile tl = cx.tiles[tile];
+  const Tube& T = cx.tubes[tl.tube];
+  k.tile = tile; k.tube = tl.tube; k.base = tl.base; k.N = T.N; k.node_off = T.node_off; k.flags = T.flags;
+  k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = T.step; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
+  k.inv_rc = T.inv_rc; k.b = T.b; k.xc_floor = T.xc_floor; k.x_thr = T.x_thr; k.emit_k = T.emit_k;
+  k.conv_k = T.conv_k; k.cfl24 = T.cfl24; k.chi_skip = T.chi_skip; k.seed = T.seed;
+  return k;
+}
+
+// Small-argument forms used on the hot path (relative error < 1e-12 where
+// they are selected, far below FP32 rounding).
+__device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), x >= 0
+  if (x < 1e-2f) return x * (1.0f - 0.5f * x * (1.0f - (1.0f / 3.0f) * x * (1.0f - 0.25f * x)));
+  return -expm1f(-x);
+}
+
 // One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
-// boundaries, deposit, photon births.  `tile` < 0: no particle in this lane.
-__device__ void lepton_one(const Ctx& cx, long long slot, int tile, bool lds, long long* s_rho) {
-  float w = 0.0f;
-  if (tile >= 0) w = cx.L.w[slot];
-  const bool alive = tile >= 0 && w != 0.0f;
-  int tube = -1;
-  Tile tl{0, 0, 0, 0};
-  const Tube* Tp = cx.tubes;
-  uint32_t pos = 0;
-  float u = 0.0f;
-  if (alive) {
-    tl = cx.tiles[tile];
-    tube = tl.tube;
-    Tp = cx.tubes + tube;
-    pos = cx.L.pos[slot];
-    u = cx.L.u[slot];
+// boundaries, deposit, photon births.  UNI: the lane's tile is the
+// wave-uniform tile of a sorted chunk (tube constants come through scalar
+// loads, gather and deposit go through the LDS window); otherwise the lane's
+// own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
+template <bool UNI>
+__device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
+                           LocalCounts& lcn, float w, uint32_t pos, float u) {
+  bool alive;
+  KC k;
+  if (UNI) {
+    k = ku;
+    alive = w != 0.0f;
+  } else {
+    alive = tile >= 0 && w != 0.0f;
+    if (alive) k = lane_kc(cx, tile);
+    else { k = ku; k.tube = -1; k.base = 0; }
   }
-  const Tube& T = *Tp;
-  const int N = T.N;
-  const bool per = (T.flags & F_PERIODIC) != 0;
-  const int64_t step = T.step;
+  if (!alive) { pos = 0; u = 0.0f; }
+  const int tube = alive ? k.tube : -1;
+  const int N = k.N;
+  const uint32_t flags = (uint32_t)k.flags;
+  const bool per = (flags & F_PERIODIC) != 0;
+  const int64_t step = k.step;
+  struct { int base; } tl{k.base};
 
   // gather (node field, first-order shape) and kick
-  const int cell = tl.base + (int)(pos >> FRAC);
+  const int off = (int)(pos >> FRAC);
+  const int cell = tl.base + off;
   const uint32_t frac = pos & 0xFFFFFFu;
   const int cg = per ? wrap_cell(cell, N) : cell;
   const float xi = (float)frac * 5.9604645e-8f;
   float e0 = 0.0f, e1 = 0.0f;
-  if (alive) { e0 = cx.ebar[T.node_off + cg]; e1 = cx.ebar[T.node_off + cg + 1]; }
+  if (alive) {
+    if (UNI) { e0 = s_eb[off]; e1 = s_eb[off + 1]; }
+    else { e0 = cx.ebar[k.node_off + cg]; e1 = cx.ebar[k.node_off + cg + 1]; }
+  }
   const float sg = w < 0.0f ? -1.0f : 1.0f;
-  u += sg * ((1.0f - xi) * e0 + xi * e1) * T.dt;
+  u += sg * ((1.0f - xi) * e0 + xi * e1) * k.dt;
 
   // curvature emission: rate alpha_em gamma/R~ T_syn(chi), chi = gamma^2 lambda~/R~,
   // photon energy xi_s x_c with x_c = 1.5 gamma chi, QED zone h < H
@@ -168,43 +298,41 @@ __device__ void lepton_one(const Ctx& cx, long long slot, int tile, bool lds, lo
   float xc = 0.0f;
   int ncand = 0, nev = 0;
   bool eval = false;
-  if (alive && !(T.flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < T.hfix) {
-    const float g = sqrtf(1.0f + u * u);
-    const float chi = g * g * T.lr;
+  if (alive && !(flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < k.hfix) {
+    const float g = __builtin_amdgcn_sqrtf(1.0f + u * u);
+    const float chi = g * g * k.lr;
     xc = 1.5f * g * chi;
-    if (xc >= T.xc_floor) {
+    if (xc >= k.xc_floor) {
       eval = true;
       id = cx.L.id[slot];
-      const float dtau = T.emit_k * g * t_syn(chi);
+      const float dtau = k.emit_k * g * t_syn(chi);
       int nsub = (int)ceilf(dtau * 10.0f);
-      nsub = max(1, min(nsub, T.nsub_max));
-      const float p = -expm1f(-dtau / (float)nsub);
+      nsub = max(1, min(nsub, k.nsub_max));
+      const float p = one_minus_exp_neg(dtau / (float)nsub);
       float au = fabsf(u);
       for (int j = 0; j < nsub; ++j) {
-        u4 r = draw(T.seed, id, step, T_EMIT, (uint32_t)j);
+        u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
         if (bern(r.a, p)) {
           float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
           au -= x;
           evmask |= 1ull << j;
           ++nev;
-          if (x >= T.x_thr || (T.flags & F_TRACK_ALL)) ++ncand;
+          if (x >= k.x_thr || (flags & F_TRACK_ALL)) ++ncand;
         }
       }
-      if (!(T.flags & F_RECOIL_OFF)) u = copysignf(au, upk);
+      if (!(flags & F_RECOIL_OFF)) u = copysignf(au, upk);
     }
   }
 
   // drift: dh/dt = u / gamma, in fixed point
-  const float g2 = sqrtf(1.0f + u * u);
-  const int dfix = __float2int_rn(u / g2 * T.cfl24);
-  const long long np = (long long)pos + dfix;
-  const int noff = (int)(np >> FRAC);
-  const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
+  const int dfix = __float2int_rn(u * __builtin_amdgcn_rsqf(1.0f + u * u) * k.cfl24);
+  const long long npl = (long long)pos + dfix;
+  const int noff = (int)(npl >> FRAC);
+  const uint32_t nfrac = (uint32_t)npl & 0xFFFFFFu;
   bool dead = false;
-  int ncell = tl.base + noff;
-  if (alive && (np < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
-  int64_t Tw = 0;
-  if (alive) Tw = __float2ll_rn(fabsf(w) * 16777216.0f);
+  const int ncell = tl.base + noff;
+  if (alive && (npl < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
+  const int64_t Tw = alive ? __float2ll_rn(fabsf(w) * 16777216.0f) : 0;
   bool absorbed = false, outflow = false;
   if (alive && !dead && !per) {
     if (ncell < 0) { absorbed = true; dead = true; }
@@ -212,7 +340,7 @@ __device__ void lepton_one(const Ctx& cx, long long slot, int tile, bool lds, lo
   }
   if (alive) {
     if (dead) cx.L.w[slot] = 0.0f;
-    else { cx.L.pos[slot] = (uint32_t)np; cx.L.u[slot] = u; }
+    else { cx.L.pos[slot] = (uint32_t)npl; cx.L.u[slot] = u; }
   }
   if (absorbed) atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
   if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
@@ -224,124 +352,197 @@ __device__ void lepton_one(const Ctx& cx, long long slot, int tile, bool lds, lo
     const unsigned long long A = ((unsigned long long)Tw * nfrac + (1ull << 23)) >> FRAC;
     const long long a = sg > 0 ? (long long)A : -(long long)A;
     const long long ta = sg > 0 ? (long long)(Tw - (int64_t)A) : -(long long)(Tw - (int64_t)A);
-    if (lds) {
+    if (UNI) {
       atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)ta);
       atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)a);
     } else {
       int n1 = ncg + 1;
       if (per && n1 == N) n1 = 0;
-      atomicAdd((unsigned long long*)&cx.rho[T.node_off + ncg], (unsigned long long)ta);
-      atomicAdd((unsigned long long*)&cx.rho[T.node_off + n1], (unsigned long long)a);
+      atomicAdd((unsigned long long*)&cx.rho[k.node_off + ncg], (unsigned long long)ta);
+      atomicAdd((unsigned long long*)&cx.rho[k.node_off + n1], (unsigned long long)a);
     }
   }
 
   // photon births at the post-drift position, inside the QED zone
-  const bool keep = alive && !dead && (((int64_t)ncg << FRAC) + nfrac < T.hfix);
+  const bool keep = alive && !dead && (((int64_t)ncg << FRAC) + nfrac < k.hfix);
   const int nst = keep ? ncand : 0;
   if (__ballot(nst > 0)) {
     int dropped = 0;
-    long long first = reserve_tail(cx.pc, nst, &dropped);
+    const long long first = reserve_tail(cx.pc, nst, &dropped);
     if (nst > 0) {
       const long long lim = cx.pc->limit;
       float au = fabsf(upk);
       const float dir = upk >= 0.0f ? 1.0f : -1.0f;
       const float aw = fabsf(w);
-      long long k = first;
+      long long q = first;
       uint64_t m = evmask;
       while (m) {
-        int j = __ffsll((long long)m) - 1;
+        const int j = __ffsll((long long)m) - 1;
         m &= m - 1;
-        u4 r = draw(T.seed, id, step, T_EMIT, (uint32_t)j);
+        u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
         float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
         au -= x;
-        if (x >= T.x_thr || (T.flags & F_TRACK_ALL)) {
-          if (k < lim) {
-            cx.P.pos[k] = (uint32_t)np;
-            cx.P.x[k] = dir * x;
-            cx.P.w[k] = aw;
-            cx.P.n0[k] = (int32_t)(step + 1);
-            cx.P.id[k] = child_id(T.seed, id, step, 2u + (uint32_t)j);
-            cx.ptt[k] = tile;
+        if (x >= k.x_thr || (flags & F_TRACK_ALL)) {
+          if (q < lim) {
+            const uint32_t kk = (uint32_t)q;
+            cx.P.pos[kk] = (uint32_t)npl;
+            cx.P.x[kk] = dir * x;
+            cx.P.w[kk] = aw;
+            cx.P.n0[kk] = (int32_t)(step + 1);
+            cx.P.id[kk] = child_id(k.seed, id, step, 2u + (uint32_t)j);
+            cx.ptt[kk] = tile;
           }
-          ++k;
+          ++q;
         }
       }
     }
     if (dropped) atomicOr(cx.err, E_CAP);
-    count_by_tube(cx.tubes, nst > 0 ? tube : -1, C_PHO_BORN, nst - dropped);
-    count_by_tube(cx.tubes, dropped > 0 ? tube : -1, C_DROPPED, dropped);
+    lcn.v[3] += nst - dropped;
+    lcn.v[4] += dropped;
   }
 
-  // counters (one atomic per wave and tube)
-  count_by_tube(cx.tubes, alive ? tube : -1, C_LEP_STEPS, 1);
-  if (__ballot(eval)) {
-    count_by_tube(cx.tubes, eval ? tube : -1, C_EMIT_EVAL, 1);
-    count_by_tube(cx.tubes, nev > 0 ? tube : -1, C_EMIT, nev);
-  }
-  if (__ballot(dead)) {
-    count_by_tube(cx.tubes, absorbed ? tube : -1, C_ABSORBED, 1);
-    count_by_tube(cx.tubes, outflow ? tube : -1, C_OUTFLOW, 1);
+  // event counts: sorted chunks accumulate per thread (flushed per
+  // workgroup); tail lanes may belong to different tubes
+  lcn.v[0] += alive ? 1 : 0;
+  lcn.v[1] += eval ? 1 : 0;
+  lcn.v[2] += nev;
+  lcn.v[5] += absorbed ? 1 : 0;
+  lcn.v[6] += outflow ? 1 : 0;
+  if (!UNI) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const int v = lcn.v[i];
+      if (__ballot(v != 0)) count_by_tube(cx.shard, v != 0 ? tube : -1, cnt_index<2>(i), v);
+    }
+    lcn.clear();
   }
 }
 
-// Lepton pass.  Each workgroup takes a contiguous range of chunks (XCD-aware:
-// consecutive ranges go to the same XCD); sorted chunks deposit through an
-// LDS window of their tile, tail chunks with global atomics.
+// Node field of a tile window into LDS (nodes base .. base + WIN).
+__device__ void load_window(const Ctx& cx, int tile, float* s_eb) {
+  const Tile tl = cx.tiles[tile];
+  const Tube& T = cx.tubes[tl.tube];
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  for (int j = threadIdx.x; j <= WIN; j += blockDim.x) {
+    int node = tl.base + j;
+    float v = 0.0f;
+    if (per) v = cx.ebar[T.node_off + wrap_cell(node, T.N)];
+    else if (node >= 0 && node <= T.N) v = cx.ebar[T.node_off + node];
+    s_eb[j] = v;
+  }
+  __syncthreads();
+}
+
+struct LepIn { float w; uint32_t pos; float u; int tile; uint32_t slot; };
+
+__device__ __forceinline__ LepIn lep_load(const Ctx& cx, long long c, long long nsc, long long S, long long tail) {
+  LepIn r;
+  if (c < nsc) { r.slot = (uint32_t)c * CHUNK + threadIdx.x; r.tile = cx.lchunk[c]; }
+  else {
+    r.slot = (uint32_t)(S + (c - nsc) * CHUNK) + threadIdx.x;
+    const int t = cx.ltt[r.slot];           // in bounds: the store keeps a chunk of slack
+    r.tile = r.slot < S + tail ? t : -1;
+  }
+  r.w = cx.L.w[r.slot];
+  r.pos = cx.L.pos[r.slot];
+  r.u = cx.L.u[r.slot];
+  return r;
+}
+
+// Lepton pass over the sorted region.  Each workgroup takes a contiguous
+// range of chunks (XCD-aware: consecutive ranges go to the same XCD) and
+// prefetches the next chunk's records while it pushes the current one; the
+// chunk's tile constants sit in scalar registers, gather and deposit go
+// through an LDS window of the tile.
 __global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
   __shared__ long long s_rho[WIN + 2];
+  __shared__ float s_eb[WIN + 2];
+  __shared__ long long s_cnt[8];
+  LocalCounts lcn;
+  lcn.clear();
+  int ctube = -1;
   for (int j = threadIdx.x; j < WIN + 2; j += blockDim.x) s_rho[j] = 0;
   __syncthreads();
   const long long nsc = cx.lc->n_sorted_chunks;
-  const long long S = nsc * CHUNK;
-  const long long tail = cx.lc->tail_snap;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
   const int G = gridDim.x, bx = blockIdx.x;
   const int r = (bx & 7) * (G >> 3) + (bx >> 3);
-  const long long c0 = nch * r / G, c1 = nch * (r + 1) / G;
+  const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
   int held = -1;
+  KC kc;
+  LepIn cur;
+  if (c0 < c1) cur = lep_load(cx, c0, nsc, 0, 0);
   for (long long c = c0; c < c1; ++c) {
-    if (c < nsc) {
-      const int tile = cx.lchunk[c];
-      if (tile != held) {
-        if (held >= 0) flush_window(cx, held, s_rho);
-        held = tile;
+    LepIn nxt;
+    if (c + 1 < c1) nxt = lep_load(cx, c + 1, nsc, 0, 0);
+    const int tile = cur.tile;
+    if (tile != held) {
+      if (held >= 0) flush_window(cx, held, s_rho);
+      held = tile;
+      kc = load_kc(cx, tile);
+      if (kc.tube != ctube) {
+        if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
+        ctube = kc.tube;
       }
-      lepton_one(cx, c * CHUNK + threadIdx.x, tile, true, s_rho);
-    } else {
-      if (held >= 0) { flush_window(cx, held, s_rho); held = -1; }
-      const long long slot = S + (c - nsc) * CHUNK + threadIdx.x;
-      const int tile = slot < S + tail ? cx.ltt[slot] : -1;
-      lepton_one(cx, slot, tile, false, s_rho);
+      load_window(cx, tile, s_eb);
     }
+    lepton_one<true>(cx, cur.slot, tile, kc, s_rho, s_eb, lcn, cur.w, cur.pos, cur.u);
+    cur = nxt;
   }
   if (held >= 0) flush_window(cx, held, s_rho);
+  if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
+}
+
+// Lepton pass over the tail (particles appended since the last re-sort):
+// each lane carries its own tile; gather and deposit use global memory.
+__global__ __launch_bounds__(CHUNK) void k_leptons_tail(Ctx cx) {
+  LocalCounts lcn;
+  lcn.clear();
+  const long long nsc = cx.lc->n_sorted_chunks;
+  const long long S = nsc * CHUNK;
+  const long long tail = cx.lc->tail_snap;
+  const long long ntc = (tail + CHUNK - 1) / CHUNK;
+  const KC kc0 = load_kc(cx, 0);
+  for (long long c = blockIdx.x; c < ntc; c += gridDim.x) {
+    const LepIn cur = lep_load(cx, nsc + c, nsc, S, tail);
+    lepton_one<false>(cx, cur.slot, cur.tile, kc0, nullptr, nullptr, lcn, cur.w, cur.pos, cur.u);
+  }
 }
 
 // ------------------------------------------------------------------ photons
+// sin(a) for the accumulated angle; a power series where |a| < 0.05
+// (truncation a^7/5040 < 2e-13 relative).
+__device__ __forceinline__ float sin_small(float a) {
+  const float a2 = a * a;
+  if (fabsf(a) < 0.05f) return a * (1.0f - a2 * (1.0f / 6.0f) * (1.0f - a2 * (1.0f / 20.0f)));
+  return sinf(a);
+}
+
 // One photon: free streaming at c, exit above H, conversion with
 // rate alpha_em (b/lambda~) sin(psi) T_BW(x b sin psi), sin(psi) = |sin(s/R~)|.
-__device__ void photon_one(const Ctx& cx, long long slot, int tile) {
-  float x = 0.0f;
-  if (tile >= 0) x = cx.P.x[slot];
-  const bool alive = tile >= 0 && x != 0.0f;
-  int tube = -1;
-  Tile tl{0, 0, 0, 0};
-  const Tube* Tp = cx.tubes;
-  uint32_t pos = 0;
-  int32_t n0 = 0;
-  if (alive) {
-    tl = cx.tiles[tile];
-    tube = tl.tube;
-    Tp = cx.tubes + tube;
-    pos = cx.P.pos[slot];
-    n0 = cx.P.n0[slot];
+// Below chi_skip the fit gives p < 2^-27, under every 24-bit uniform: no
+// draw is needed and none is made.
+template <bool UNI>
+__device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, LocalCounts& lcn, float x, uint32_t pos,
+                           int32_t n0) {
+  bool alive;
+  KC k;
+  if (UNI) {
+    k = ku;
+    alive = x != 0.0f;
+  } else {
+    alive = tile >= 0 && x != 0.0f;
+    if (alive) k = lane_kc(cx, tile);
+    else { k = ku; k.tube = -1; k.base = 0; }
   }
-  const Tube& T = *Tp;
-  const int N = T.N;
-  const bool per = (T.flags & F_PERIODIC) != 0;
-  const int64_t step = T.step;
+  if (!alive) { x = 0.0f; pos = 0; n0 = 0; }
+  const int tube = alive ? k.tube : -1;
+  const int N = k.N;
+  const uint32_t flags = (uint32_t)k.flags;
+  const bool per = (flags & F_PERIODIC) != 0;
+  const int64_t step = k.step;
+  struct { int base; } tl{k.base};
   const float dir = x >= 0.0f ? 1.0f : -1.0f;
-  const long long np = (long long)pos + (x >= 0.0f ? T.dpho : -T.dpho);
+  const long long np = (long long)pos + (x >= 0.0f ? k.dpho : -k.dpho);
   const int noff = (int)(np >> FRAC);
   const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
   const int ncell = tl.base + noff;
@@ -350,22 +551,23 @@ __device__ void photon_one(const Ctx& cx, long long slot, int tile) {
   const int ncg = per ? wrap_cell(ncell, N) : ncell;
   bool exited = false;
   if (alive && !dead) {
-    if ((!per && (ncell < 0 || ncell >= N)) || (((int64_t)ncg << FRAC) + nfrac >= T.hfix)) { exited = true; dead = true; }
+    if ((!per && (ncell < 0 || ncell >= N)) || (((int64_t)ncg << FRAC) + nfrac >= k.hfix)) { exited = true; dead = true; }
   }
   bool eval = false, conv = false;
   float w = 0.0f;
   uint64_t id = 0;
-  if (alive && !dead && !(T.flags & (F_QED_OFF | F_CONV_OFF))) {
-    const float s = (float)(step + 1 - (int64_t)n0) * T.dt;
-    const float sp = fabsf(sinf(s * T.inv_rc));
-    const float chi = fabsf(x) * T.b * sp;
-    const float p = -expm1f(-T.conv_k * sp * t_bw(chi));
-    if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
-      eval = true;
-      id = cx.P.id[slot];
-      u4 r = draw(T.seed, id, step, T_CONV, 0);
-      conv = bern(r.a, p);
-      if (conv) w = cx.P.w[slot];
+  if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
+    const float sp = fabsf(sin_small((float)(step + 1 - (int64_t)n0) * k.dt * k.inv_rc));
+    const float chi = fabsf(x) * k.b * sp;
+    if (chi > k.chi_skip) {
+      const float p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
+      if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
+        eval = true;
+        id = cx.P.id[slot];
+        u4 r = draw(k.seed, id, step, T_CONV, 0);
+        conv = bern(r.a, p);
+        if (conv) w = cx.P.w[slot];
+      }
     }
   }
   if (alive) {
@@ -375,45 +577,97 @@ __device__ void photon_one(const Ctx& cx, long long slot, int tile) {
   // pair births: e- and e+ at the photon position, gamma = x/2 each, along the photon
   if (__ballot(conv)) {
     int dropped = 0;
-    long long first = reserve_tail(cx.lc, conv ? 2 : 0, &dropped);
+    const long long first = reserve_tail(cx.lc, conv ? 2 : 0, &dropped);
     if (conv) {
       const long long lim = cx.lc->limit;
       const float gm = 0.5f * fabsf(x);
       const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
-      for (int k = 0; k < 2; ++k) {
-        long long sl = first + k;
+      for (int e = 0; e < 2; ++e) {
+        const long long sl = first + e;
         if (sl < lim) {
-          cx.L.pos[sl] = (uint32_t)np;
-          cx.L.u[sl] = up;
-          cx.L.w[sl] = k == 0 ? -w : w;
-          cx.L.id[sl] = child_id(T.seed, id, step, (uint32_t)k);
-          cx.ltt[sl] = tile;
+          const uint32_t s32 = (uint32_t)sl;
+          cx.L.pos[s32] = (uint32_t)np;
+          cx.L.u[s32] = up;
+          cx.L.w[s32] = e == 0 ? -w : w;
+          cx.L.id[s32] = child_id(k.seed, id, step, (uint32_t)e);
+          cx.ltt[s32] = tile;
         }
       }
     }
     if (dropped) atomicOr(cx.err, E_CAP);
-    count_by_tube(cx.tubes, conv ? tube : -1, C_CONV, 1);
-    count_by_tube(cx.tubes, dropped > 0 ? tube : -1, C_DROPPED, dropped);
+    lcn.v[3] += dropped;
   }
-  count_by_tube(cx.tubes, alive ? tube : -1, C_PHO_STEPS, 1);
-  if (__ballot(eval)) count_by_tube(cx.tubes, eval ? tube : -1, C_CONV_EVAL, 1);
-  if (__ballot(exited)) count_by_tube(cx.tubes, exited ? tube : -1, C_PHO_EXIT, 1);
+  lcn.v[0] += alive ? 1 : 0;
+  lcn.v[1] += eval ? 1 : 0;
+  lcn.v[2] += conv ? 1 : 0;
+  lcn.v[4] += exited ? 1 : 0;
+  if (!UNI) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int v = lcn.v[i];
+      if (__ballot(v != 0)) count_by_tube(cx.shard, v != 0 ? tube : -1, cnt_index<3>(i), v);
+    }
+    lcn.clear();
+  }
+}
+
+struct PhoIn { float x; uint32_t pos; int32_t n0; int tile; uint32_t slot; };
+
+__device__ __forceinline__ PhoIn pho_load(const Ctx& cx, long long c, long long nsc, long long S, long long tail) {
+  PhoIn r;
+  if (c < nsc) { r.slot = (uint32_t)c * CHUNK + threadIdx.x; r.tile = cx.pchunk[c]; }
+  else {
+    r.slot = (uint32_t)(S + (c - nsc) * CHUNK) + threadIdx.x;
+    const int t = cx.ptt[r.slot];
+    r.tile = r.slot < S + tail ? t : -1;
+  }
+  r.x = cx.P.x[r.slot];
+  r.pos = cx.P.pos[r.slot];
+  r.n0 = cx.P.n0[r.slot];
+  return r;
 }
 
 __global__ __launch_bounds__(CHUNK) void k_photons(Ctx cx) {
   const long long nsc = cx.pc->n_sorted_chunks;
-  const long long S = nsc * CHUNK;
-  const long long tail = cx.pc->tail_snap;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
   const int G = gridDim.x, bx = blockIdx.x;
   const int r = (bx & 7) * (G >> 3) + (bx >> 3);
-  const long long c0 = nch * r / G, c1 = nch * (r + 1) / G;
+  const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
+  __shared__ long long s_cnt[8];
+  LocalCounts lcn;
+  lcn.clear();
+  int ctube = -1;
+  KC kc;
+  int held = -1;
+  PhoIn cur;
+  if (c0 < c1) cur = pho_load(cx, c0, nsc, 0, 0);
   for (long long c = c0; c < c1; ++c) {
-    long long slot;
-    int tile;
-    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = cx.pchunk[c]; }
-    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? cx.ptt[slot] : -1; }
-    photon_one(cx, slot, tile);
+    PhoIn nxt;
+    if (c + 1 < c1) nxt = pho_load(cx, c + 1, nsc, 0, 0);
+    if (cur.tile != held) {
+      held = cur.tile;
+      kc = load_kc(cx, held);
+      if (kc.tube != ctube) {
+        if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
+        ctube = kc.tube;
+      }
+    }
+    photon_one<true>(cx, cur.slot, cur.tile, kc, lcn, cur.x, cur.pos, cur.n0);
+    cur = nxt;
+  }
+  if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
+}
+
+__global__ __launch_bounds__(CHUNK) void k_photons_tail(Ctx cx) {
+  LocalCounts lcn;
+  lcn.clear();
+  const long long nsc = cx.pc->n_sorted_chunks;
+  const long long S = nsc * CHUNK;
+  const long long tail = cx.pc->tail_snap;
+  const long long ntc = (tail + CHUNK - 1) / CHUNK;
+  const KC kc0 = load_kc(cx, 0);
+  for (long long c = blockIdx.x; c < ntc; c += gridDim.x) {
+    const PhoIn cur = pho_load(cx, nsc + c, nsc, S, tail);
+    photon_one<false>(cx, cur.slot, cur.tile, kc0, lcn, cur.x, cur.pos, cur.n0);
   }
 }
 
@@ -632,25 +886,63 @@ __device__ __forceinline__ void rb_slot_iter(const RbCtx<B>& cx, long long c, lo
   else { *slot = S + (c - nsc) * CHUNK + threadIdx.x; *tile = *slot < S + tail ? cx.tt[*slot] : -1; }
 }
 
+// Destination tiles of one workgroup's contiguous chunk range are counted in
+// an LDS histogram over a window of RB_HW tiles (a range of sorted chunks
+// only reaches its own tiles +- 1); tiles outside the window go straight to
+// global atomics, aggregated per wave.
+constexpr int RB_HW = 1024;
+
+__device__ __forceinline__ void rb_range(long long nch, long long* c0, long long* c1) {
+  const int G = gridDim.x, bx = blockIdx.x;
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  *c0 = nch * r / G;
+  *c1 = nch * (r + 1) / G;
+}
+
+// Wave-aggregated add of 1 per lane to bin `k` (k < 0: no-op).  `lds`: bins
+// are LDS entries relative to dlo, else global tile counters.  Returns this
+// lane's rank-based position (old value + rank) when `ret` is set.
+__device__ __forceinline__ int rb_wave_add(int k, int* lds_bins, int dlo, int* gbins, bool lds, bool ret) {
+  int out = -1;
+  while (true) {
+    uint64_t m = __ballot(k >= 0);
+    if (!m) break;
+    const int lead = __ffsll((long long)m) - 1;
+    const int kk = __shfl(k, lead);
+    const uint64_t mk = __ballot(k == kk);
+    int base = 0;
+    if (lane_id() == lead) {
+      if (lds) base = atomicAdd(&lds_bins[kk - dlo], (int)__popcll(mk));
+      else base = atomicAdd(&gbins[kk], (int)__popcll(mk));
+    }
+    if (ret) base = __shfl(base, lead);
+    if (k == kk) { out = base + rank_in(mk); k = -1; }
+  }
+  return out;
+}
+
 template <class B>
 __global__ __launch_bounds__(CHUNK) void k_rb_count(RbCtx<B> cx) {
+  __shared__ int s_h[RB_HW];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
-  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+  long long c0, c1;
+  rb_range(nch, &c0, &c1);
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
+  __syncthreads();
+  const int dlo = c0 < nsc ? cx.chunk_old[c0] - 1 : -(1 << 30);
+  for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
     rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
     int cell; uint32_t frac;
-    int nt = rb_locate(cx, slot, tile, &cell, &frac);
-    while (true) {
-      uint64_t m = __ballot(nt >= 0);
-      if (!m) break;
-      int lead = __ffsll((long long)m) - 1;
-      int k = __shfl(nt, lead);
-      uint64_t mk = __ballot(nt == k);
-      if (lane_id() == lead) atomicAdd(&cx.tcount[k], (int)__popcll(mk));
-      if (nt == k) nt = -1;
-    }
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+    rb_wave_add(inw ? nt : -1, s_h, dlo, cx.tcount, true, false);
+    rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcount, false, false);
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
+    if (s_h[j] > 0) atomicAdd(&cx.tcount[dlo + j], s_h[j]);
 }
 
 // Exclusive scan of the padded chunk counts over all tiles (one workgroup).
@@ -712,28 +1004,47 @@ __global__ void k_rb_chunks(RbCtx<B> cx) {
 
 template <class B>
 __global__ __launch_bounds__(CHUNK) void k_rb_scatter(RbCtx<B> cx) {
+  __shared__ int s_h[RB_HW];
+  __shared__ long long s_base[RB_HW];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
-  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+  long long c0, c1;
+  rb_range(nch, &c0, &c1);
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
+  __syncthreads();
+  const int dlo = c0 < nsc ? cx.chunk_old[c0] - 1 : -(1 << 30);
+  // pass A: how many of this range go to each window tile
+  for (long long c = c0; c < c1; ++c) {
+    long long slot; int tile;
+    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    int cell; uint32_t frac;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+    rb_wave_add(inw ? nt : -1, s_h, dlo, nullptr, true, false);
+  }
+  __syncthreads();
+  // one reservation per (workgroup, tile)
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
+    const int n = s_h[j];
+    if (n > 0) {
+      const int t = dlo + j;
+      s_base[j] = cx.tchunk[t] * CHUNK + atomicAdd(&cx.tcursor[t], n);
+      s_h[j] = 0;
+    }
+  }
+  __syncthreads();
+  // pass B: place the records
+  for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
     rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
     int cell = 0; uint32_t frac = 0;
-    const int nt0 = rb_locate(cx, slot, tile, &cell, &frac);
-    int nt = nt0;
-    long long dst = -1;
-    while (true) {
-      uint64_t m = __ballot(nt >= 0);
-      if (!m) break;
-      int lead = __ffsll((long long)m) - 1;
-      int k = __shfl(nt, lead);
-      uint64_t mk = __ballot(nt == k);
-      int base = 0;
-      if (lane_id() == lead) base = atomicAdd(&cx.tcursor[k], (int)__popcll(mk));
-      base = __shfl(base, lead);
-      if (nt == k) { dst = cx.tchunk[k] * CHUNK + base + rank_in(mk); nt = -1; }
-    }
-    if (nt0 >= 0) {
-      const Tile tl = cx.tiles[nt0];
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+    const int ri = rb_wave_add(inw ? nt : -1, s_h, dlo, nullptr, true, true);
+    const int ro = rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcursor, false, true);
+    if (nt >= 0) {
+      const long long dst = inw ? s_base[nt - dlo] + ri : cx.tchunk[nt] * CHUNK + ro;
+      const Tile tl = cx.tiles[nt];
       rec_copy(cx.src, slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
     }
   }

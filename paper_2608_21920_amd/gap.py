@@ -24,12 +24,14 @@ FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16,
 ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
-DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED = range(8)
-STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION = range(4)
+DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING = range(9)
+STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING = range(5)
+TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
               "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
-              "lep_steps", "pho_steps", "rebuckets"]
+              "lep_steps", "pho_steps", "rebuckets", "lep_steps_tail", "emit_eval_tail", "pho_steps_tail",
+              "conv_eval_tail"]
 
 LEPTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("u", "<f4"), ("w", "<f4"), ("id", "<u8")])
 PHOTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("x", "<f4"), ("w", "<f4"), ("n0", "<i4"),
@@ -223,6 +225,15 @@ class Gap:
 
     def photons(self, tube=0) -> np.ndarray:
         return self._diag(DIAG_PHOTONS, tube, 0).view(PHOTON_DTYPE).copy()
+
+    def set_timing(self, on: bool):
+        buf = np.array([1 if on else 0], np.int32)
+        _check(self.lib.gap_set_state(self.h, STATE_TIMING, 0, buf.ctypes.data, buf.nbytes), "set_timing")
+
+    def timing(self) -> dict:
+        """{kernel group: (launches, total ms)} since timing was enabled or last read."""
+        v = self._diag(DIAG_TIMING, 0, 112).view(np.float64)
+        return {k: (int(v[2 * i]), float(v[2 * i + 1])) for i, k in enumerate(TIMING_KEYS)}
 
     # -- state loading (single tube)
     def set_particles(self, lep: np.ndarray, pho: np.ndarray | None = None):
