@@ -356,11 +356,11 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst) {
   cx.n_tiles = g->n_tiles;
   const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
   k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
-  k_rb_count<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_rb_count<B><<<kGrid, TPB, 0, g->s>>>(cx);
   k_rb_scan<B><<<1, 1024, 0, g->s>>>(cx);
   k_rb_chunks<B><<<kGrid, 256, 0, g->s>>>(cx);
-  k_rb_scatter<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
-  k_rb_pad<B><<<kGrid, CHUNK, 0, g->s>>>(cx);
+  k_rb_scatter<B><<<kGrid, TPB, 0, g->s>>>(cx);
+  k_rb_pad<B><<<kGrid, TPB, 0, g->s>>>(cx);
   k_rb_finish<B><<<1, 1, 0, g->s>>>(cx);
   st.cur ^= 1;
 }
@@ -381,17 +381,17 @@ void field_pass(gap_t* g, int mode) {
 void rebuild_field(gap_t* g) {
   const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
   k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
-  k_deposit_all<<<kGrid, CHUNK, 0, g->s>>>(make_ctx(g));
+  k_deposit_all<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
   field_pass(g, 1);
 }
 
 void enqueue_step(gap_t* g) {
   Ctx cx = make_ctx(g);
   { Timer t(g, KT_PRE); k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes); }
-  { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, CHUNK, 0, g->s>>>(cx); }
-  { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, CHUNK, 0, g->s>>>(cx); }
-  { Timer t(g, KT_PHOTONS); k_photons<<<g->grid_pho, CHUNK, 0, g->s>>>(cx); }
-  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, CHUNK, 0, g->s>>>(cx); }
+  { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_PHOTONS); k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
   if (++g->since_rb >= g->R) {
     Timer t(g, KT_RESORT);
@@ -529,8 +529,8 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     int dev = 0, cus = 0, nl = 0, np = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons, CHUNK, 0));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, CHUNK, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons, TPB, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
     g->grid_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
     g->grid_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
     g->grid_tail = std::max(8, cus * 4);
@@ -759,12 +759,12 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       const int grid = kGrid;
       k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
       { const Ctl* c = g->lep.ctl;
-        k_count_live<LepBuf><<<grid, CHUNK, 0, g->s>>>(g->lep.lep(g->lep.cur), c, g->lep.chunk[g->lep.cur], g->lep.tt, g->tiles, g->live); }
+        k_count_live<LepBuf><<<grid, TPB, 0, g->s>>>(g->lep.lep(g->lep.cur), c, g->lep.chunk[g->lep.cur], g->lep.tt, g->tiles, g->live); }
       HIPCHK(hipStreamSynchronize(g->s));
       HIPCHK(hipMemcpy(&lv[0], g->live + tube, 8, hipMemcpyDeviceToHost));
       k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
       { const Ctl* c = g->pho.ctl;
-        k_count_live<PhoBuf><<<grid, CHUNK, 0, g->s>>>(g->pho.pho(g->pho.cur), c, g->pho.chunk[g->pho.cur], g->pho.tt, g->tiles, g->live); }
+        k_count_live<PhoBuf><<<grid, TPB, 0, g->s>>>(g->pho.pho(g->pho.cur), c, g->pho.chunk[g->pho.cur], g->pho.tt, g->tiles, g->live); }
       HIPCHK(hipStreamSynchronize(g->s));
       HIPCHK(hipMemcpy(&lv[1], g->live + tube, 8, hipMemcpyDeviceToHost));
       o[GAP_C_LEPTONS] = lv[0];
@@ -919,7 +919,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
       if (frozen) {
         const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
         k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
-        k_deposit_all<<<kGrid, CHUNK, 0, g->s>>>(make_ctx(g));
+        k_deposit_all<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
         // keep E: only record the node charge
         FieldCtx f = make_fctx(g, 1);
         k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);

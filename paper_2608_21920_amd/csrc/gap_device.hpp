@@ -10,7 +10,8 @@ namespace gap {
 // ---------------------------------------------------------------- layout
 // Particles live in per-species stores of fixed capacity, split into
 //  * a sorted region: chunks of CHUNK slots, each chunk belonging to one tile
-//    of TILE cells, padded with dead slots;
+//    of TILE cells, padded with dead slots (a workgroup of TPB threads pushes
+//    one chunk per iteration, VEC consecutive slots per thread);
 //  * a tail: particles appended since the last re-sort (births, injection),
 //    each carrying its tile index in `tt`.
 // A position is a 32-bit fixed-point offset from the tile's window base
@@ -18,7 +19,10 @@ namespace gap {
 constexpr int TILE = 128;       // cells per tile
 constexpr int MARGIN = 64;      // cells of slack on each side of a tile
 constexpr int WIN = 256;        // cells addressable from a tile base
-constexpr int CHUNK = 256;      // slots per chunk = threads per workgroup
+constexpr int TPB = 256;        // threads per workgroup
+constexpr int VEC = 4;          // consecutive slots per thread in the sorted passes
+constexpr int CHUNK = TPB * VEC; // slots per chunk
+constexpr int PPC = CHUNK / TPB; // 256-slot pieces per chunk
 constexpr int FRAC = 24;        // fractional bits of a position
 constexpr int WAVE = 64;
 

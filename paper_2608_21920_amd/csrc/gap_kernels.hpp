@@ -257,7 +257,7 @@ __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), 
 // own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
 template <bool UNI>
 __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
-                           LocalCounts& lcn, float w, uint32_t pos, float u) {
+                           LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out) {
   bool alive;
   KC k;
   if (UNI) {
@@ -265,8 +265,7 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     alive = w != 0.0f;
   } else {
     alive = tile >= 0 && w != 0.0f;
-    if (alive) k = lane_kc(cx, tile);
-    else { k = ku; k.tube = -1; k.base = 0; }
+    k = lane_kc(cx, alive ? tile : 0);   // tile 0 always exists; no branch on the struct
   }
   if (!alive) { pos = 0; u = 0.0f; }
   const int tube = alive ? k.tube : -1;
@@ -338,9 +337,13 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     if (ncell < 0) { absorbed = true; dead = true; }
     else if (ncell >= N) { outflow = true; dead = true; }
   }
-  if (alive) {
-    if (dead) cx.L.w[slot] = 0.0f;
-    else { cx.L.pos[slot] = (uint32_t)npl; cx.L.u[slot] = u; }
+  if (alive && dead) cx.L.w[slot] = 0.0f;
+  if (UNI) {           // the caller stores the chunk's records with vector stores
+    *pos_out = (uint32_t)npl;
+    *u_out = u;
+  } else if (alive && !dead) {
+    cx.L.pos[slot] = (uint32_t)npl;
+    cx.L.u[slot] = u;
   }
   if (absorbed) atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
   if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
@@ -433,28 +436,39 @@ __device__ void load_window(const Ctx& cx, int tile, float* s_eb) {
   __syncthreads();
 }
 
-struct LepIn { float w; uint32_t pos; float u; int tile; uint32_t slot; };
+// Records of VEC consecutive slots of a sorted chunk (one thread).
+struct Lep4 { float4 w; uint4 pos; float4 u; int tile; uint32_t slot0; };
 
-__device__ __forceinline__ LepIn lep_load(const Ctx& cx, long long c, long long nsc, long long S, long long tail) {
-  LepIn r;
-  if (c < nsc) { r.slot = (uint32_t)c * CHUNK + threadIdx.x; r.tile = cx.lchunk[c]; }
-  else {
-    r.slot = (uint32_t)(S + (c - nsc) * CHUNK) + threadIdx.x;
-    const int t = cx.ltt[r.slot];           // in bounds: the store keeps a chunk of slack
-    r.tile = r.slot < S + tail ? t : -1;
-  }
-  r.w = cx.L.w[r.slot];
-  r.pos = cx.L.pos[r.slot];
-  r.u = cx.L.u[r.slot];
+__device__ __forceinline__ Lep4 lep_load4(const Ctx& cx, long long c) {
+  Lep4 r;
+  r.slot0 = (uint32_t)c * CHUNK + VEC * threadIdx.x;
+  r.tile = cx.lchunk[c];
+  r.w = *reinterpret_cast<const float4*>(cx.L.w + r.slot0);
+  r.pos = *reinterpret_cast<const uint4*>(cx.L.pos + r.slot0);
+  r.u = *reinterpret_cast<const float4*>(cx.L.u + r.slot0);
   return r;
 }
 
+// Slot and tile of 256-slot piece q (sorted pieces first, then the tail).
+__device__ __forceinline__ void piece_slot(long long q, long long nsq, long long S, long long tail, const int32_t* chunk,
+                                           const int32_t* tt, uint32_t* slot, int* tile) {
+  if (q < nsq) {
+    *slot = (uint32_t)(q * TPB) + threadIdx.x;
+    *tile = chunk[q / PPC];
+  } else {
+    *slot = (uint32_t)(S + (q - nsq) * TPB) + threadIdx.x;
+    const int t = tt[*slot];            // in bounds: the store keeps a chunk of slack
+    *tile = *slot < S + tail ? t : -1;
+  }
+}
+
 // Lepton pass over the sorted region.  Each workgroup takes a contiguous
-// range of chunks (XCD-aware: consecutive ranges go to the same XCD) and
-// prefetches the next chunk's records while it pushes the current one; the
-// chunk's tile constants sit in scalar registers, gather and deposit go
-// through an LDS window of the tile.
-__global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
+// range of chunks (XCD-aware: consecutive ranges go to the same XCD); each
+// thread pushes VEC consecutive slots loaded and stored as 16-byte vectors,
+// and the next chunk's records are prefetched while the current one is
+// pushed.  The chunk's tile constants sit in scalar registers; gather and
+// deposit go through an LDS window of the tile.
+__global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
   __shared__ long long s_rho[WIN + 2];
   __shared__ float s_eb[WIN + 2];
   __shared__ long long s_cnt[8];
@@ -469,11 +483,11 @@ __global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
   const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
   int held = -1;
   KC kc;
-  LepIn cur;
-  if (c0 < c1) cur = lep_load(cx, c0, nsc, 0, 0);
+  Lep4 cur;
+  if (c0 < c1) cur = lep_load4(cx, c0);
   for (long long c = c0; c < c1; ++c) {
-    LepIn nxt;
-    if (c + 1 < c1) nxt = lep_load(cx, c + 1, nsc, 0, 0);
+    Lep4 nxt;
+    if (c + 1 < c1) nxt = lep_load4(cx, c + 1);
     const int tile = cur.tile;
     if (tile != held) {
       if (held >= 0) flush_window(cx, held, s_rho);
@@ -485,7 +499,20 @@ __global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
       }
       load_window(cx, tile, s_eb);
     }
-    lepton_one<true>(cx, cur.slot, tile, kc, s_rho, s_eb, lcn, cur.w, cur.pos, cur.u);
+    float4 w = cur.w, u = cur.u;
+    uint4 p = cur.pos;
+    // one body, four records: process .x, write the result into .x, rotate
+#pragma unroll 1
+    for (int j = 0; j < VEC; ++j) {
+      uint32_t po;
+      float uo;
+      lepton_one<true>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo);
+      w = make_float4(w.y, w.z, w.w, w.x);
+      p = make_uint4(p.y, p.z, p.w, po);
+      u = make_float4(u.y, u.z, u.w, uo);
+    }
+    *reinterpret_cast<uint4*>(cx.L.pos + cur.slot0) = p;
+    *reinterpret_cast<float4*>(cx.L.u + cur.slot0) = u;
     cur = nxt;
   }
   if (held >= 0) flush_window(cx, held, s_rho);
@@ -493,18 +520,23 @@ __global__ __launch_bounds__(CHUNK) void k_leptons(Ctx cx) {
 }
 
 // Lepton pass over the tail (particles appended since the last re-sort):
-// each lane carries its own tile; gather and deposit use global memory.
-__global__ __launch_bounds__(CHUNK) void k_leptons_tail(Ctx cx) {
+// one slot per thread, each lane with its own tile; global gather/deposit.
+__global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
   LocalCounts lcn;
   lcn.clear();
   const long long nsc = cx.lc->n_sorted_chunks;
   const long long S = nsc * CHUNK;
   const long long tail = cx.lc->tail_snap;
-  const long long ntc = (tail + CHUNK - 1) / CHUNK;
+  const long long nq = (tail + TPB - 1) / TPB;
   const KC kc0 = load_kc(cx, 0);
-  for (long long c = blockIdx.x; c < ntc; c += gridDim.x) {
-    const LepIn cur = lep_load(cx, nsc + c, nsc, S, tail);
-    lepton_one<false>(cx, cur.slot, cur.tile, kc0, nullptr, nullptr, lcn, cur.w, cur.pos, cur.u);
+  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+    uint32_t slot;
+    int tile;
+    piece_slot(S / TPB + q, S / TPB, S, tail, cx.lchunk, cx.ltt, &slot, &tile);
+    const float w = cx.L.w[slot];
+    const uint32_t pos = cx.L.pos[slot];
+    const float u = cx.L.u[slot];
+    lepton_one<false>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr);
   }
 }
 
@@ -523,7 +555,7 @@ __device__ __forceinline__ float sin_small(float a) {
 // draw is needed and none is made.
 template <bool UNI>
 __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, LocalCounts& lcn, float x, uint32_t pos,
-                           int32_t n0) {
+                           int32_t n0, uint32_t* pos_out, float* x_out) {
   bool alive;
   KC k;
   if (UNI) {
@@ -531,8 +563,7 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     alive = x != 0.0f;
   } else {
     alive = tile >= 0 && x != 0.0f;
-    if (alive) k = lane_kc(cx, tile);
-    else { k = ku; k.tube = -1; k.base = 0; }
+    k = lane_kc(cx, alive ? tile : 0);
   }
   if (!alive) { x = 0.0f; pos = 0; n0 = 0; }
   const int tube = alive ? k.tube : -1;
@@ -570,7 +601,10 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
       }
     }
   }
-  if (alive) {
+  if (UNI) {           // the caller stores the chunk's records with vector stores
+    *pos_out = (uint32_t)np;
+    *x_out = (dead || conv) ? 0.0f : x;
+  } else if (alive) {
     if (dead || conv) cx.P.x[slot] = 0.0f;
     else cx.P.pos[slot] = (uint32_t)np;
   }
@@ -611,23 +645,19 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   }
 }
 
-struct PhoIn { float x; uint32_t pos; int32_t n0; int tile; uint32_t slot; };
+struct Pho4 { float4 x; uint4 pos; int4 n0; int tile; uint32_t slot0; };
 
-__device__ __forceinline__ PhoIn pho_load(const Ctx& cx, long long c, long long nsc, long long S, long long tail) {
-  PhoIn r;
-  if (c < nsc) { r.slot = (uint32_t)c * CHUNK + threadIdx.x; r.tile = cx.pchunk[c]; }
-  else {
-    r.slot = (uint32_t)(S + (c - nsc) * CHUNK) + threadIdx.x;
-    const int t = cx.ptt[r.slot];
-    r.tile = r.slot < S + tail ? t : -1;
-  }
-  r.x = cx.P.x[r.slot];
-  r.pos = cx.P.pos[r.slot];
-  r.n0 = cx.P.n0[r.slot];
+__device__ __forceinline__ Pho4 pho_load4(const Ctx& cx, long long c) {
+  Pho4 r;
+  r.slot0 = (uint32_t)c * CHUNK + VEC * threadIdx.x;
+  r.tile = cx.pchunk[c];
+  r.x = *reinterpret_cast<const float4*>(cx.P.x + r.slot0);
+  r.pos = *reinterpret_cast<const uint4*>(cx.P.pos + r.slot0);
+  r.n0 = *reinterpret_cast<const int4*>(cx.P.n0 + r.slot0);
   return r;
 }
 
-__global__ __launch_bounds__(CHUNK) void k_photons(Ctx cx) {
+__global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
   const long long nsc = cx.pc->n_sorted_chunks;
   const int G = gridDim.x, bx = blockIdx.x;
   const int r = (bx & 7) * (G >> 3) + (bx >> 3);
@@ -638,11 +668,11 @@ __global__ __launch_bounds__(CHUNK) void k_photons(Ctx cx) {
   int ctube = -1;
   KC kc;
   int held = -1;
-  PhoIn cur;
-  if (c0 < c1) cur = pho_load(cx, c0, nsc, 0, 0);
+  Pho4 cur;
+  if (c0 < c1) cur = pho_load4(cx, c0);
   for (long long c = c0; c < c1; ++c) {
-    PhoIn nxt;
-    if (c + 1 < c1) nxt = pho_load(cx, c + 1, nsc, 0, 0);
+    Pho4 nxt;
+    if (c + 1 < c1) nxt = pho_load4(cx, c + 1);
     if (cur.tile != held) {
       held = cur.tile;
       kc = load_kc(cx, held);
@@ -651,23 +681,41 @@ __global__ __launch_bounds__(CHUNK) void k_photons(Ctx cx) {
         ctube = kc.tube;
       }
     }
-    photon_one<true>(cx, cur.slot, cur.tile, kc, lcn, cur.x, cur.pos, cur.n0);
+    float4 x = cur.x;
+    uint4 p = cur.pos;
+    int4 n0 = cur.n0;
+#pragma unroll 1
+    for (int j = 0; j < VEC; ++j) {
+      uint32_t po;
+      float xo;
+      photon_one<true>(cx, cur.slot0 + j, held, kc, lcn, x.x, p.x, n0.x, &po, &xo);
+      x = make_float4(x.y, x.z, x.w, xo);
+      p = make_uint4(p.y, p.z, p.w, po);
+      n0 = make_int4(n0.y, n0.z, n0.w, n0.x);
+    }
+    *reinterpret_cast<uint4*>(cx.P.pos + cur.slot0) = p;
+    *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;
     cur = nxt;
   }
   if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
 }
 
-__global__ __launch_bounds__(CHUNK) void k_photons_tail(Ctx cx) {
+__global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
   LocalCounts lcn;
   lcn.clear();
   const long long nsc = cx.pc->n_sorted_chunks;
   const long long S = nsc * CHUNK;
   const long long tail = cx.pc->tail_snap;
-  const long long ntc = (tail + CHUNK - 1) / CHUNK;
+  const long long nq = (tail + TPB - 1) / TPB;
   const KC kc0 = load_kc(cx, 0);
-  for (long long c = blockIdx.x; c < ntc; c += gridDim.x) {
-    const PhoIn cur = pho_load(cx, nsc + c, nsc, S, tail);
-    photon_one<false>(cx, cur.slot, cur.tile, kc0, lcn, cur.x, cur.pos, cur.n0);
+  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+    uint32_t slot;
+    int tile;
+    piece_slot(S / TPB + q, S / TPB, S, tail, cx.pchunk, cx.ptt, &slot, &tile);
+    const float x = cx.P.x[slot];
+    const uint32_t pos = cx.P.pos[slot];
+    const int32_t n0 = cx.P.n0[slot];
+    photon_one<false>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr);
   }
 }
 
@@ -880,10 +928,11 @@ __device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int
 }
 
 template <class B>
-__device__ __forceinline__ void rb_slot_iter(const RbCtx<B>& cx, long long c, long long nsc, long long S, long long tail,
+__device__ __forceinline__ void rb_slot_iter(const RbCtx<B>& cx, long long q, long long nsq, long long S, long long tail,
                                              long long* slot, int* tile) {
-  if (c < nsc) { *slot = c * CHUNK + threadIdx.x; *tile = cx.chunk_old[c]; }
-  else { *slot = S + (c - nsc) * CHUNK + threadIdx.x; *tile = *slot < S + tail ? cx.tt[*slot] : -1; }
+  uint32_t s32;
+  piece_slot(q, nsq, S, tail, cx.chunk_old, cx.tt, &s32, tile);
+  *slot = s32;
 }
 
 // Destination tiles of one workgroup's contiguous chunk range are counted in
@@ -922,18 +971,18 @@ __device__ __forceinline__ int rb_wave_add(int k, int* lds_bins, int dlo, int* g
 }
 
 template <class B>
-__global__ __launch_bounds__(CHUNK) void k_rb_count(RbCtx<B> cx) {
+__global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
   __shared__ int s_h[RB_HW];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
-  rb_range(nch, &c0, &c1);
+  rb_range(nq, &c0, &c1);
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
   __syncthreads();
-  const int dlo = c0 < nsc ? cx.chunk_old[c0] - 1 : -(1 << 30);
+  const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
-    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell; uint32_t frac;
     const int nt = rb_locate(cx, slot, tile, &cell, &frac);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
@@ -1003,20 +1052,20 @@ __global__ void k_rb_chunks(RbCtx<B> cx) {
 }
 
 template <class B>
-__global__ __launch_bounds__(CHUNK) void k_rb_scatter(RbCtx<B> cx) {
+__global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   __shared__ int s_h[RB_HW];
   __shared__ long long s_base[RB_HW];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
+  const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
-  rb_range(nch, &c0, &c1);
+  rb_range(nq, &c0, &c1);
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
   __syncthreads();
-  const int dlo = c0 < nsc ? cx.chunk_old[c0] - 1 : -(1 << 30);
+  const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   // pass A: how many of this range go to each window tile
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
-    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell; uint32_t frac;
     const int nt = rb_locate(cx, slot, tile, &cell, &frac);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
@@ -1036,7 +1085,7 @@ __global__ __launch_bounds__(CHUNK) void k_rb_scatter(RbCtx<B> cx) {
   // pass B: place the records
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
-    rb_slot_iter(cx, c, nsc, S, tail, &slot, &tile);
+    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell = 0; uint32_t frac = 0;
     const int nt = rb_locate(cx, slot, tile, &cell, &frac);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
@@ -1051,11 +1100,11 @@ __global__ __launch_bounds__(CHUNK) void k_rb_scatter(RbCtx<B> cx) {
 }
 
 template <class B>
-__global__ __launch_bounds__(CHUNK) void k_rb_pad(RbCtx<B> cx) {
-  const long long tot = cx.ctl->total_chunks_new;
-  for (long long c = blockIdx.x; c < tot; c += gridDim.x) {
-    const int t = cx.chunk_new[c];
-    const long long slot = c * CHUNK + threadIdx.x;
+__global__ __launch_bounds__(TPB) void k_rb_pad(RbCtx<B> cx) {
+  const long long tot = cx.ctl->total_chunks_new * PPC;
+  for (long long q = blockIdx.x; q < tot; q += gridDim.x) {
+    const int t = cx.chunk_new[q / PPC];
+    const long long slot = q * TPB + threadIdx.x;
     if (slot >= cx.tchunk[t] * CHUNK + cx.tcount[t]) rec_kill(cx.dst, slot);
   }
 }
@@ -1112,13 +1161,12 @@ __global__ void k_init_particles(InitCtx cx) {
 }
 
 // Deposit every live lepton (initial field, loaded states): global atomics.
-__global__ __launch_bounds__(CHUNK) void k_deposit_all(Ctx cx) {
+__global__ __launch_bounds__(TPB) void k_deposit_all(Ctx cx) {
   const long long nsc = cx.lc->n_sorted_chunks, S = nsc * CHUNK, tail = cx.lc->tail;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
-  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-    long long slot; int tile;
-    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = cx.lchunk[c]; }
-    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? cx.ltt[slot] : -1; }
+  const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+  for (long long c = blockIdx.x; c < nq; c += gridDim.x) {
+    uint32_t slot; int tile;
+    piece_slot(c, nsq, S, tail, cx.lchunk, cx.ltt, &slot, &tile);
     if (tile < 0) continue;
     const float w = cx.L.w[slot];
     if (w == 0.0f) continue;
@@ -1142,14 +1190,13 @@ __global__ __launch_bounds__(CHUNK) void k_deposit_all(Ctx cx) {
 
 // Live particles per tube (diagnostics).
 template <class B>
-__global__ __launch_bounds__(CHUNK) void k_count_live(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
-                                                       const Tile* tiles, long long* out) {
+__global__ __launch_bounds__(TPB) void k_count_live(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
+                                                     const Tile* tiles, long long* out) {
   const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
-  const long long nch = nsc + (tail + CHUNK - 1) / CHUNK;
-  for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-    long long slot; int tile;
-    if (c < nsc) { slot = c * CHUNK + threadIdx.x; tile = chunk[c]; }
-    else { slot = S + (c - nsc) * CHUNK + threadIdx.x; tile = slot < S + tail ? tt[slot] : -1; }
+  const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+  for (long long c = blockIdx.x; c < nq; c += gridDim.x) {
+    uint32_t slot; int tile;
+    piece_slot(c, nsq, S, tail, chunk, tt, &slot, &tile);
     int t = (tile >= 0 && rec_alive<B>(buf, slot)) ? tiles[tile].tube : -1;
     while (true) {
       uint64_t m = __ballot(t >= 0);
