@@ -3,6 +3,7 @@
 // declared in include/gap.h.
 #include "gap.h"
 #include "gap_kernels.hpp"
+#include "gap_merge.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -186,6 +187,13 @@ struct gap_t {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;   // (kernel id, start, stop)
   int R = 64;
   int64_t since_rb = 0;
+  int64_t host_step = 0;        // steps enqueued (all tubes advance together)
+  bool merge_on = false;
+  int merge_every = 64;
+  SortBuf sort_l{}, sort_p{};
+  uint32_t* merge_start = nullptr;
+  double* thresh_l = nullptr;
+  double* thresh_p = nullptr;
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
   bool any_periodic = false;
   int sticky = 0;
@@ -193,7 +201,7 @@ struct gap_t {
   hipGraphExec_t gexec = nullptr;
   int64_t gsteps = -1;
   int gs_l = -1, gs_p = -1, ge_l = -1, ge_p = -1;
-  int64_t gs_since = -1, ge_since = -1;
+  int64_t gs_since = -1, ge_since = -1, gs_step = -1;
 };
 
 namespace {
@@ -385,7 +393,35 @@ void rebuild_field(gap_t* g) {
   field_pass(g, 1);
 }
 
+template <class B>
+void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh) {
+  const int t1 = (g->n_tubes + 255) / 256;
+  k_fill_i64<<<std::max(1, t1), 256, 0, g->s>>>(g->live, g->n_tubes, 0);
+  k_count_live<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->live, g->n_tubes);
+  k_merge_flags<<<t1, 256, 0, g->s>>>(g->live, thresh, sb.flags, g->n_tubes);
+  k_fill_i64<<<1, 64, 0, g->s>>>(sb.n, 1, 0);
+  k_merge_keys<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->tubes, sb);
+  int src = 0;
+  for (int pass = 0; pass < 12; ++pass) {
+    k_rs_hist<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
+    k_rs_scan<<<1, 1024, 0, g->s>>>(sb);
+    k_rs_scatter<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
+    src ^= 1;
+  }
+  k_merge_bounds<<<kGrid, 256, 0, g->s>>>(sb, src, g->merge_start);
+  k_merge_maxscan<<<1, 1024, 0, g->s>>>(sb, g->merge_start);
+  k_merge_pairs<B><<<kGrid, 256, 0, g->s>>>(buf, sb, src, g->merge_start, g->tubes, g->tiles, st.chunk[st.cur], st.tt,
+                                            st.ctl, g->shard);
+}
+
+void merge_all(gap_t* g) {
+  merge_store<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->sort_l, g->thresh_l);
+  merge_store<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->sort_p, g->thresh_p);
+  // merged-away records are dead slots until the next scheduled re-sort
+}
+
 void enqueue_step(gap_t* g) {
+  if (g->merge_on && g->host_step % g->merge_every == 0) merge_all(g);
   Ctx cx = make_ctx(g);
   { Timer t(g, KT_PRE); k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes); }
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
@@ -398,6 +434,7 @@ void enqueue_step(gap_t* g) {
     rebucket_all(g);
     g->since_rb = 0;
   }
+  ++g->host_step;
 }
 
 int read_err(gap_t* g) {
@@ -557,6 +594,38 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   int e;
   if ((e = alloc_store(g, g->lep, cap_l, false))) return e;
   if ((e = alloc_store(g, g->pho, cap_p, true))) return e;
+  for (int t = 0; t < n_tubes; ++t) if (g->P[t].flags & GAP_MERGE_ON) g->merge_on = true;
+  if (g->merge_on) {
+    g->merge_every = std::max(1, g->P[0].merge_every);
+    for (int sp = 0; sp < 2; ++sp) {
+      SortBuf& sb = sp ? g->sort_p : g->sort_l;
+      const size_t n = (size_t)(sp ? g->pho.capacity : g->lep.capacity);
+      sb.max_blocks = (int)(n / RS_ITEMS + 1);
+      for (int b = 0; b < 2; ++b) {
+        sb.major[b] = (uint32_t*)dalloc(g, n * 4);
+        sb.id[b] = (uint64_t*)dalloc(g, n * 8);
+        sb.val[b] = (uint32_t*)dalloc(g, n * 4);
+        if (!sb.major[b] || !sb.id[b] || !sb.val[b]) return GAP_ENOMEM;
+      }
+      sb.bhist = (uint32_t*)dalloc(g, (size_t)256 * sb.max_blocks * 4);
+      sb.flags = (uint32_t*)dalloc(g, (size_t)n_tubes * 4);
+      sb.n = (long long*)dalloc(g, 8);
+      if (!sb.bhist || !sb.flags || !sb.n) return GAP_ENOMEM;
+    }
+    g->merge_start = (uint32_t*)dalloc(g, (size_t)std::max(g->lep.capacity, g->pho.capacity) * 4);
+    g->thresh_l = (double*)dalloc(g, sizeof(double) * n_tubes);
+    g->thresh_p = (double*)dalloc(g, sizeof(double) * n_tubes);
+    if (!g->merge_start || !g->thresh_l || !g->thresh_p) return GAP_ENOMEM;
+    std::vector<double> tl(n_tubes), tp(n_tubes);
+    for (int t = 0; t < n_tubes; ++t) {
+      const bool on = (g->P[t].flags & GAP_MERGE_ON) != 0;
+      tl[t] = on ? g->P[t].merge_frac * (double)g->P[t].cap_leptons : 1e300;
+      tp[t] = on ? g->P[t].merge_frac * (double)g->P[t].cap_photons : 1e300;
+    }
+    HIPCHK(hipStreamSynchronize(g->s));
+    HIPCHK(hipMemcpy(g->thresh_l, tl.data(), sizeof(double) * n_tubes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->thresh_p, tp.data(), sizeof(double) * n_tubes, hipMemcpyHostToDevice));
+  }
   HIPCHK(hipStreamSynchronize(g->s));
   if ((e = upload_tubes(g))) return e;
   HIPCHK(hipMemcpy(g->tiles, g->tiles_h.data(), sizeof(Tile) * g->n_tiles, hipMemcpyHostToDevice));
@@ -654,14 +723,14 @@ int export_store(gap_t* g, const Store& st, bool photon, int tube, std::vector<H
 
 int graph_capture(gap_t* g, int64_t n) {
   if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
-  g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_since = g->since_rb;
+  g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_since = g->since_rb; g->gs_step = g->host_step;
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal));
   for (int64_t i = 0; i < n; ++i) enqueue_step(g);
   hipError_t e = hipStreamEndCapture(g->s, &graph);
   g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_since = g->since_rb;
   // nothing ran yet: back to the start state
-  g->lep.cur = g->gs_l; g->pho.cur = g->gs_p; g->since_rb = g->gs_since;
+  g->lep.cur = g->gs_l; g->pho.cur = g->gs_p; g->since_rb = g->gs_since; g->host_step = g->gs_step;
   if (e != hipSuccess) return GAP_EDEVICE;
   e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
@@ -710,13 +779,15 @@ int gap_step_graph(gap_t* g, int64_t n_steps) {
   if (n_steps == 0) return g->sticky;
   if (g->s == nullptr) return GAP_ESTATE;   // stream capture needs a non-default stream
   const bool valid = g->gexec && g->gsteps == n_steps && g->lep.cur == g->gs_l && g->pho.cur == g->gs_p &&
-                     g->since_rb == g->gs_since;
+                     g->since_rb == g->gs_since &&
+                     (!g->merge_on || (g->host_step - g->gs_step) % g->merge_every == 0);
   if (!valid) {
     int e = graph_capture(g, n_steps);
     if (e) return e;
   }
   HIPCHK(hipGraphLaunch(g->gexec, g->s));
   g->lep.cur = g->ge_l; g->pho.cur = g->ge_p; g->since_rb = g->ge_since;
+  g->host_step += n_steps;
   return g->sticky;
 }
 
@@ -759,12 +830,12 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       const int grid = kGrid;
       k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
       { const Ctl* c = g->lep.ctl;
-        k_count_live<LepBuf><<<grid, TPB, 0, g->s>>>(g->lep.lep(g->lep.cur), c, g->lep.chunk[g->lep.cur], g->lep.tt, g->tiles, g->live); }
+        k_count_live<LepBuf><<<grid, TPB, 0, g->s>>>(g->lep.lep(g->lep.cur), c, g->lep.chunk[g->lep.cur], g->lep.tt, g->tiles, g->live, g->n_tubes); }
       HIPCHK(hipStreamSynchronize(g->s));
       HIPCHK(hipMemcpy(&lv[0], g->live + tube, 8, hipMemcpyDeviceToHost));
       k_fill_i64<<<1, 256, 0, g->s>>>(g->live, g->n_tubes, 0);
       { const Ctl* c = g->pho.ctl;
-        k_count_live<PhoBuf><<<grid, TPB, 0, g->s>>>(g->pho.pho(g->pho.cur), c, g->pho.chunk[g->pho.cur], g->pho.tt, g->tiles, g->live); }
+        k_count_live<PhoBuf><<<grid, TPB, 0, g->s>>>(g->pho.pho(g->pho.cur), c, g->pho.chunk[g->pho.cur], g->pho.tt, g->tiles, g->live, g->n_tubes); }
       HIPCHK(hipStreamSynchronize(g->s));
       HIPCHK(hipMemcpy(&lv[1], g->live + tube, 8, hipMemcpyDeviceToHost));
       o[GAP_C_LEPTONS] = lv[0];
@@ -933,6 +1004,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
       if (bytes < 16) return GAP_EINVAL;
       std::memcpy(&T.Es, b, 8);
       std::memcpy(&T.step, b + 8, 8);
+      g->host_step = T.step;
       if ((e = upload_tubes(g))) return e;
       if (!frozen) rebuild_field(g);
       return sync_and_err(g);

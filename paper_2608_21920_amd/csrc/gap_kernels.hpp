@@ -684,17 +684,19 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
     float4 x = cur.x;
     uint4 p = cur.pos;
     int4 n0 = cur.n0;
+    bool xchg = false;
 #pragma unroll 1
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float xo;
       photon_one<true>(cx, cur.slot0 + j, held, kc, lcn, x.x, p.x, n0.x, &po, &xo);
+      xchg |= xo != x.x;
       x = make_float4(x.y, x.z, x.w, xo);
       p = make_uint4(p.y, p.z, p.w, po);
       n0 = make_int4(n0.y, n0.z, n0.w, n0.x);
     }
     *reinterpret_cast<uint4*>(cx.P.pos + cur.slot0) = p;
-    *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;
+    if (xchg) *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;   // only when a photon died
     cur = nxt;
   }
   if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
@@ -1188,10 +1190,14 @@ __global__ __launch_bounds__(TPB) void k_deposit_all(Ctx cx) {
   }
 }
 
-// Live particles per tube (diagnostics).
+// Live particles per tube: per-workgroup LDS counts (tubes < 1024), one
+// global add per workgroup and tube.
 template <class B>
 __global__ __launch_bounds__(TPB) void k_count_live(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
-                                                     const Tile* tiles, long long* out) {
+                                                     const Tile* tiles, long long* out, int n_tubes) {
+  __shared__ int s_n[1024];
+  for (int j = threadIdx.x; j < 1024; j += blockDim.x) s_n[j] = 0;
+  __syncthreads();
   const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   for (long long c = blockIdx.x; c < nq; c += gridDim.x) {
@@ -1204,10 +1210,16 @@ __global__ __launch_bounds__(TPB) void k_count_live(B buf, const Ctl* ctl, const
       int lead = __ffsll((long long)m) - 1;
       int k = __shfl(t, lead);
       uint64_t mk = __ballot(t == k);
-      if (lane_id() == lead) atomicAdd((unsigned long long*)&out[k], (unsigned long long)__popcll(mk));
+      if (lane_id() == lead) {
+        if (k < 1024) atomicAdd(&s_n[k], (int)__popcll(mk));
+        else atomicAdd((unsigned long long*)&out[k], (unsigned long long)__popcll(mk));
+      }
       if (t == k) t = -1;
     }
   }
+  __syncthreads();
+  for (int j = threadIdx.x; j < 1024 && j < n_tubes; j += blockDim.x)
+    if (s_n[j]) atomicAdd((unsigned long long*)&out[j], (unsigned long long)s_n[j]);
 }
 
 }  // namespace gap

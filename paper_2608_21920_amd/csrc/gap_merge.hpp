@@ -1,0 +1,269 @@
+// gap_merge.hpp -- weight-doubling merge of over-full stores: a stable LSD
+// radix sort of (group key, id) written for this library, and the pairing
+// kernel.  Groups are (cell, charge sign, direction, floor(log2 gamma)) for
+// leptons and (cell, direction, floor(log2 x)) for photons; within a group
+// consecutive particles in id order fuse pairwise, the survivor (one random
+// bit of Philox(seed; id of the first, step, MERGE)) taking both weights.
+#pragma once
+#include "gap_kernels.hpp"
+
+namespace gap {
+
+constexpr int RS_TPB = 256;
+constexpr int RS_TILES = 16;                    // 256-item tiles per block
+constexpr int RS_ITEMS = RS_TPB * RS_TILES;     // items per block
+
+struct SortBuf {
+  uint32_t* major[2];   // group key
+  uint64_t* id[2];      // minor key
+  uint32_t* val[2];     // slot of the record
+  uint32_t* bhist;      // [256][nblocks] digit counts per block
+  uint32_t* flags;      // per tube: merge this step
+  long long* n;         // number of items
+  int max_blocks;
+};
+
+// floor(log2 v) + 64 clamped to [0, 127] from the FP64 exponent (v >= 1 here)
+__device__ __forceinline__ uint32_t lg2bin_d(double v) {
+  const int e = (int)((__double_as_longlong(v) >> 52) & 0x7FF) - 1023;
+  const int b = e + 64;
+  return (uint32_t)(b < 0 ? 0 : (b > 127 ? 127 : b));
+}
+__device__ __forceinline__ uint32_t rec_group(const LepBuf& b, uint32_t slot, uint32_t gcell) {
+  const double u = (double)b.u[slot];
+  const double g = sqrt(1.0 + u * u);
+  return (gcell << 9) | ((b.w[slot] > 0.0f ? 1u : 0u) << 8) | ((u >= 0.0 ? 1u : 0u) << 7) | lg2bin_d(g);
+}
+__device__ __forceinline__ uint32_t rec_group(const PhoBuf& b, uint32_t slot, uint32_t gcell) {
+  const float x = b.x[slot];
+  return (gcell << 9) | ((x >= 0.0f ? 1u : 0u) << 7) | lg2bin_d(fabs((double)x));
+}
+
+// Per-tube decision: merge when the live count exceeds merge_frac * cap.
+__global__ void k_merge_flags(const long long* live, const double* thresh, uint32_t* flags, int n_tubes) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tubes) flags[t] = (double)live[t] > thresh[t] ? 1u : 0u;
+}
+
+// Gather the merge candidates (live particles of flagged tubes) with their
+// keys.  The order of the gathered list does not matter: the sort's full key
+// (group, id) is unique.
+template <class B>
+__global__ __launch_bounds__(TPB) void k_merge_keys(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
+                                                    const Tile* tiles, const Tube* tubes, SortBuf sb) {
+  const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
+  const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+    uint32_t slot;
+    int tile;
+    piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
+    bool take = false;
+    uint32_t key = 0;
+    if (tile >= 0 && rec_alive<B>(buf, slot)) {
+      const Tile tl = tiles[tile];
+      const Tube& T = tubes[tl.tube];
+      if (sb.flags[tl.tube]) {
+        int cell = tl.base + (int)(buf.pos[slot] >> FRAC);
+        if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
+        const uint32_t gcell = (uint32_t)(T.cell_off + cell);
+        key = rec_group(buf, slot, gcell);
+        take = true;
+      }
+    }
+    const uint64_t m = __ballot(take);
+    long long base = 0;
+    if (lane_id() == 0 && m) base = (long long)atomicAdd((unsigned long long*)sb.n, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0);
+    if (take) {
+      const long long i = base + rank_in(m);
+      sb.major[0][i] = key;
+      sb.id[0][i] = buf.id[slot];
+      sb.val[0][i] = slot;
+    }
+  }
+}
+
+// digit d of the composite key (passes 0..7: id bytes, 8..11: group bytes)
+__device__ __forceinline__ uint32_t rs_digit(uint32_t major, uint64_t id, int pass) {
+  return pass < 8 ? (uint32_t)(id >> (8 * pass)) & 0xFFu : (major >> (8 * (pass - 8))) & 0xFFu;
+}
+
+__global__ __launch_bounds__(RS_TPB) void k_rs_hist(SortBuf sb, int src, int pass) {
+  __shared__ uint32_t h[256];
+  const long long n = *sb.n;
+  const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const long long i0 = (long long)b * RS_ITEMS;
+    for (int k = threadIdx.x; k < RS_ITEMS; k += RS_TPB) {
+      const long long i = i0 + k;
+      if (i < n) atomicAdd(&h[rs_digit(sb.major[src][i], sb.id[src][i], pass)], 1u);
+    }
+    __syncthreads();
+    sb.bhist[(long long)threadIdx.x * sb.max_blocks + b] = h[threadIdx.x];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of bhist in digit-major order (one workgroup); bhist then
+// holds each (digit, block)'s first output position.
+__global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
+  __shared__ long long sh[1024 / WAVE];
+  const long long n = *sb.n;
+  const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+  const long long total = 256LL * nb;
+  long long carry = 0;
+  for (long long base = 0; base < total; base += 1024) {
+    const long long t = base + threadIdx.x;
+    long long v = 0;
+    uint32_t* ptr = nullptr;
+    if (t < total) {
+      const int d = (int)(t / nb), b = (int)(t % nb);
+      ptr = &sb.bhist[(long long)d * sb.max_blocks + b];
+      v = *ptr;
+    }
+    long long incl = v;
+#pragma unroll
+    for (int k = 1; k < WAVE; k <<= 1) {
+      long long o = __shfl_up(incl, k);
+      if (lane_id() >= k) incl += o;
+    }
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) sh[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+      long long sv = threadIdx.x < 1024 / WAVE ? sh[threadIdx.x] : 0;
+      long long iv = sv;
+#pragma unroll
+      for (int k = 1; k < WAVE; k <<= 1) {
+        long long o = __shfl_up(iv, k);
+        if (lane_id() >= k) iv += o;
+      }
+      if (threadIdx.x < 1024 / WAVE) sh[threadIdx.x] = iv - sv;
+    }
+    __syncthreads();
+    const long long ex = carry + sh[wv] + incl - v;
+    if (ptr) *ptr = (uint32_t)ex;
+    __syncthreads();
+    if (threadIdx.x == 1023) sh[0] = ex + v;
+    __syncthreads();
+    carry = sh[0];
+    __syncthreads();
+  }
+}
+
+// Stable scatter: items keep their order among equal digits.  Each block
+// walks its items in 256-item tiles; a lane's rank is the number of earlier
+// items of its block with the same digit.
+__global__ __launch_bounds__(RS_TPB) void k_rs_scatter(SortBuf sb, int src, int pass) {
+  __shared__ uint32_t run[256];          // per digit: items of this block already placed
+  __shared__ uint32_t wcnt[RS_TPB / WAVE][256];
+  const long long n = *sb.n;
+  const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+  const int dst = src ^ 1;
+  const int w = threadIdx.x / WAVE;
+  const uint64_t lt = (1ull << lane_id()) - 1ull;
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    run[threadIdx.x] = 0;
+    __syncthreads();
+    const long long i0 = (long long)b * RS_ITEMS;
+    for (int tile = 0; tile < RS_TILES; ++tile) {
+      const long long i = i0 + (long long)tile * RS_TPB + threadIdx.x;
+      const bool ok = i < n;
+      uint32_t mj = 0, v = 0;
+      uint64_t id = 0;
+      uint32_t d = 256;
+      if (ok) { mj = sb.major[src][i]; id = sb.id[src][i]; v = sb.val[src][i]; d = rs_digit(mj, id, pass); }
+      // lanes of this wave with the same digit
+      uint64_t same = __ballot(ok);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t bb = __ballot(ok && ((d >> bit) & 1u));
+        same &= ((d >> bit) & 1u) ? bb : ~bb;
+      }
+      if (!ok) same = 0;
+      for (int k = threadIdx.x; k < (RS_TPB / WAVE) * 256; k += RS_TPB) (&wcnt[0][0])[k] = 0;
+      __syncthreads();
+      // the highest lane of each digit group records the group size
+      if (ok && (same >> lane_id()) == 1ull) wcnt[w][d] = (uint32_t)__popcll(same);
+      __syncthreads();
+      if (ok) {
+        uint32_t before = run[d] + (uint32_t)__popcll(same & lt);
+        for (int ww = 0; ww < w; ++ww) before += wcnt[ww][d];
+        const long long o = (long long)sb.bhist[(long long)d * sb.max_blocks + b] + before;
+        sb.major[dst][o] = mj;
+        sb.id[dst][o] = id;
+        sb.val[dst][o] = v;
+      }
+      __syncthreads();
+      {
+        uint32_t add = 0;
+        for (int ww = 0; ww < RS_TPB / WAVE; ++ww) add += wcnt[ww][threadIdx.x];
+        run[threadIdx.x] += add;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Pairing: the k-th particle of a group (in id order) pairs with the (k+1)-th
+// when k is even; k = i - (first index of the group), the first index coming
+// from a max-scan of the group starts.
+__global__ void k_merge_bounds(SortBuf sb, int src, uint32_t* start) {
+  const long long n = *sb.n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    start[i] = (i == 0 || sb.major[src][i] != sb.major[src][i - 1]) ? (uint32_t)i : 0u;
+}
+
+// Inclusive max-scan of start[] in place (one workgroup, sequential blocks).
+__global__ __launch_bounds__(1024) void k_merge_maxscan(SortBuf sb, uint32_t* start) {
+  __shared__ uint32_t sh[1024 / WAVE];
+  const long long n = *sb.n;
+  uint32_t carry = 0;
+  for (long long base = 0; base < n; base += 1024) {
+    const long long i = base + threadIdx.x;
+    uint32_t v = i < n ? start[i] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int k = 1; k < WAVE; k <<= 1) {
+      uint32_t o = __shfl_up(incl, k);
+      if (lane_id() >= k) incl = max(incl, o);
+    }
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) sh[wv] = incl;
+    __syncthreads();
+    uint32_t pre = carry;
+    for (int ww = 0; ww < wv; ++ww) pre = max(pre, sh[ww]);
+    const uint32_t r = max(pre, incl);
+    if (i < n) start[i] = r;
+    __syncthreads();
+    if (threadIdx.x == 1023) sh[0] = r;
+    __syncthreads();
+    carry = max(carry, sh[0]);
+    __syncthreads();
+  }
+}
+
+template <class B>
+__global__ void k_merge_pairs(B buf, SortBuf sb, int src, const uint32_t* start, const Tube* tubes, const Tile* tiles,
+                              const int32_t* chunk, const int32_t* tt, const Ctl* ctl, long long* shard) {
+  const long long n = *sb.n;
+  const long long nsorted_slots = ctl->n_sorted_chunks * CHUNK;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += (long long)gridDim.x * blockDim.x) {
+    if (sb.major[src][i + 1] != sb.major[src][i]) continue;
+    if (((i - (long long)start[i]) & 1) != 0) continue;
+    const uint32_t sa = sb.val[src][i], sbb = sb.val[src][i + 1];
+    const int tile = sa < nsorted_slots ? chunk[sa / CHUNK] : tt[sa];
+    const int t = tiles[tile].tube;
+    const Tube& T = tubes[t];
+    const u4 r = draw(T.seed, sb.id[src][i], T.step, T_MERGE, 0);
+    const uint32_t keep = (r.a & 1u) ? sbb : sa, drop = (r.a & 1u) ? sa : sbb;
+    buf.w[keep] += buf.w[drop];
+    rec_kill(buf, drop);
+    atomicAdd((unsigned long long*)(shard + ((long long)t * NSHARD + (blockIdx.x % NSHARD)) * C_N + C_MERGED), 1ull);
+  }
+}
+
+}  // namespace gap
