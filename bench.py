@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("gap.hip", "gap_device.hpp", "gap_kernels.hpp", "gap_merge.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_leptons_k_photons_production.txt")
-# algorithmic bytes per unit of work: lepton-step reads
+# algorithmic bytes per unit of work: a lepton-step reads
 # position, momentum, weight and writes position, momentum; an emission
 # evaluation also reads the 8-byte id.  Photon-step reads position, energy,
 # birth step and writes position; a conversion evaluation also reads id, weight.

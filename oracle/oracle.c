@@ -353,7 +353,7 @@ static void node_field(orc_sim* s) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Initial state (Sect. 6.1 initial condition; BJ configs).             */
+/* Initial state (Sect. 6.1 initial condition; uniform-pair start).     */
 /* ------------------------------------------------------------------ */
 static void init_particles(orc_sim* s) {
   const orc_params* p = &s->p;
