@@ -47,6 +47,7 @@
 #define ORC_REPLAY       512u
 #define ORC_CONV_OFF     1024u
 #define ORC_EMIT_OFF     2048u
+#define ORC_INJ_FIXED    4096u   /* injection count independent of inj_weight */
 
 /* Random-stream tags (upper 16 bits of the fourth counter word). */
 #define TAG_INIT  1u
@@ -88,7 +89,10 @@ typedef struct {
 typedef struct { int32_t cell; double xi, u, w; uint64_t id; } olep;
 typedef struct { int32_t cell; double xi, x, w; int64_t n0; uint64_t id; } opho;
 
-typedef struct { int32_t kind, sub; int64_t step; uint64_t id; double x; } oevent;
+/* A recorded QED event.  kind 0: emission by lepton `id` (x = signed photon
+ * energy, dir * x); kind 1: conversion of photon `id`; kind 2: birth of the
+ * tracked photon `id` at (cell, xi) with signed energy x and weight w. */
+typedef struct { int32_t kind, sub; int64_t step; uint64_t id; double x; int32_t cell; double xi, w; } oevent;
 
 typedef struct {
   orc_params p;
@@ -278,13 +282,14 @@ static int push_pho(orc_sim* s, opho g) {
   return 1;
 }
 
-static void log_event(orc_sim* s, int32_t kind, int64_t step, uint64_t id, int32_t sub, double x) {
+static void log_event(orc_sim* s, int32_t kind, int64_t step, uint64_t id, int32_t sub, double x,
+                      int32_t cell, double xi, double w) {
   if (!(s->p.flags & ORC_RECORD)) return;
   if (s->nev == s->ev_alloc) {
     s->ev_alloc = s->ev_alloc ? 2 * s->ev_alloc : 4096;
     s->ev = (oevent*)realloc(s->ev, sizeof(oevent) * s->ev_alloc);
   }
-  oevent e = {kind, sub, step, id, x};
+  oevent e = {kind, sub, step, id, x, cell, xi, w};
   s->ev[s->nev++] = e;
 }
 
@@ -425,6 +430,38 @@ static const oevent* ev_find(const orc_sim* s, int32_t kind, int64_t step, uint6
   return NULL;
 }
 
+/* First recorded event of (kind, step, id) in sub order, and the next one. */
+static const oevent* ev_first(const orc_sim* s, int32_t kind, int64_t step, uint64_t id) {
+  int64_t lo = 0, hi = s->nrep;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (ev_cmp(&s->rep[mid], kind, step, id, INT32_MIN) < 0) lo = mid + 1; else hi = mid;
+  }
+  if (lo < s->nrep && s->rep[lo].kind == kind && s->rep[lo].step == step && s->rep[lo].id == id) return &s->rep[lo];
+  return NULL;
+}
+static const oevent* ev_next(const orc_sim* s, const oevent* e) {
+  const oevent* f = e + 1;
+  if (f < s->rep + s->nrep && f->kind == e->kind && f->step == e->step && f->id == e->id) return f;
+  return NULL;
+}
+
+/* All recorded events of one kind at one step. */
+static const oevent* ev_kind_first(const orc_sim* s, int32_t kind, int64_t step) {
+  int64_t lo = 0, hi = s->nrep;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (ev_cmp(&s->rep[mid], kind, step, 0, INT32_MIN) < 0) lo = mid + 1; else hi = mid;
+  }
+  if (lo < s->nrep && s->rep[lo].kind == kind && s->rep[lo].step == step) return &s->rep[lo];
+  return NULL;
+}
+static const oevent* ev_kind_next(const orc_sim* s, const oevent* e) {
+  const oevent* f = e + 1;
+  if (f < s->rep + s->nrep && f->kind == e->kind && f->step == e->step) return f;
+  return NULL;
+}
+
 /* ------------------------------------------------------------------ */
 /* Merge (weight doubling): per (cell, charge sign, direction,          */
 /* floor(log2 gamma)) group, sorted by id, consecutive pairs fuse; the  */
@@ -526,6 +563,25 @@ static void wrap_cell(const orc_sim* s, int32_t* k, double* xi) {
 
 typedef struct { double x; uint64_t id; } pending_ph;
 
+/* One emitted photon of energy x (m_e c^2): recoil along the motion with x
+ * clamped to |u| (Sect. 4), energy bookkeeping, event log, and a pending
+ * photon birth if it is tracked (x >= x_thr, Sect. 6.1). */
+static void emit_apply(orc_sim* s, olep* l, int64_t n, int j, double x, pending_ph* pend, int* npend) {
+  const orc_params* p = &s->p;
+  double au = fabs(l->u);
+  if (x > au) x = au;
+  double dir = l->u >= 0 ? 1.0 : -1.0;
+  if (!(p->flags & ORC_RECOIL_OFF)) l->u = dir * (au - x);
+  s->n_emit++;
+  s->e_rad += x * fabs(l->w);
+  log_event(s, 0, n, l->id, j, dir * x, 0, 0.0, 0.0);
+  if ((x >= p->x_thr || (p->flags & ORC_TRACK_ALL)) && *npend < 64) {
+    pend[*npend].x = dir * x;
+    pend[*npend].id = child_id(p->seed, l->id, n, 2u + (uint32_t)j);
+    (*npend)++;
+  }
+}
+
 static void step_once(orc_sim* s) {
   const orc_params* p = &s->p;
   const int64_t n = s->step;
@@ -543,7 +599,7 @@ static void step_once(orc_sim* s) {
   /* (1) surface injection of cold electrons into cell 0 (Sect. 2.3: the
    * atmosphere supplies charges; here a deterministic accumulator). */
   if (p->inj_rate > 0.0 && !periodic) {
-    s->inj_acc += p->inj_rate * p->ppc_ref / p->inj_weight;
+    s->inj_acc += p->inj_rate * p->ppc_ref / ((p->flags & ORC_INJ_FIXED) ? 1.0 : p->inj_weight);
     int64_t m = (int64_t)floor(s->inj_acc);
     s->inj_acc -= (double)m;
     for (int64_t j = 0; j < m; ++j) {
@@ -572,7 +628,15 @@ static void step_once(orc_sim* s) {
      * x_curv; Sect. 6.1: QED only below H, sub-cycling when the step is long) */
     int npend = 0;
     double h = (l->cell + l->xi) * p->dx;
-    if (qed && !(p->flags & ORC_EMIT_OFF) && h < s->H) {
+    if (replay) {
+      /* frozen realisation: each recorded emission of this lepton at this
+       * step is a constant recoil offset, whatever its current momentum */
+      for (const oevent* e = ev_first(s, 0, n, l->id); e; e = ev_next(s, e)) {
+        if (!(p->flags & ORC_RECOIL_OFF)) l->u -= e->x;
+        s->n_emit++;
+        s->e_rad += fabs(e->x) * fabs(l->w);
+      }
+    } else if (qed && !(p->flags & ORC_EMIT_OFF) && h < s->H) {
       double g = sqrt(1.0 + l->u * l->u);
       double chi = g * g * s->lr;          /* chi = gamma b sin(psi), sin(psi) = gamma r_g/R */
       double xc = 1.5 * g * chi;           /* x_curv = (3/2) b (r_g/R) gamma^3 */
@@ -584,28 +648,9 @@ static void step_once(orc_sim* s) {
         double pe = -expm1(-dtau / nsub);
         s->n_emit_eval++;
         for (int j = 0; j < nsub; ++j) {
-          double x = -1.0;
-          if (replay) {
-            const oevent* e = ev_find(s, 0, n, l->id, j);
-            if (e) x = e->x;
-          } else {
-            uint32_t r[4];
-            draw(p->seed, l->id, n, TAG_EMIT, (uint32_t)j, r);
-            if (u24(r[0]) < pe) x = sync_inverse(s, u24(r[1])) * xc;
-          }
-          if (x < 0) continue;
-          double au = fabs(l->u);
-          if (x > au) x = au;
-          double dir = l->u >= 0 ? 1.0 : -1.0;
-          if (!(p->flags & ORC_RECOIL_OFF)) l->u = dir * (au - x);
-          s->n_emit++;
-          s->e_rad += x * fabs(l->w);
-          log_event(s, 0, n, l->id, j, x);
-          if ((x >= p->x_thr || (p->flags & ORC_TRACK_ALL)) && npend < 64) {
-            pend[npend].x = dir * x;
-            pend[npend].id = child_id(p->seed, l->id, n, 2u + (uint32_t)j);
-            npend++;
-          }
+          uint32_t r[4];
+          draw(p->seed, l->id, n, TAG_EMIT, (uint32_t)j, r);
+          if (u24(r[0]) < pe) emit_apply(s, l, n, j, sync_inverse(s, u24(r[1])) * xc, pend, &npend);
         }
       }
     }
@@ -631,11 +676,23 @@ static void step_once(orc_sim* s) {
     for (int j = 0; j < npend; ++j) {
       if (hn < s->H) {
         opho g = {l->cell, l->xi, pend[j].x, fabs(l->w), n + 1, pend[j].id};
-        if (push_pho(s, g)) s->n_pho_born++;
+        if (push_pho(s, g)) {
+          s->n_pho_born++;
+          log_event(s, 2, n, g.id, j, g.x, g.cell, g.xi, g.w);
+        }
         l = &s->lep[i];                        /* (no realloc of lep here; kept for clarity) */
       }
     }
     deposit_one(s, l->cell, l->xi, l->w);
+  }
+
+  /* (2b) frozen realisation: the recorded photon births of this step, with
+   * their recorded states */
+  if (replay) {
+    for (const oevent* e = ev_kind_first(s, 2, n); e; e = ev_kind_next(s, e)) {
+      opho g = {e->cell, e->xi, e->x, e->w, n + 1, e->id};
+      if (push_pho(s, g)) s->n_pho_born++;
+    }
   }
 
   /* (3) photons existing at the start of the step: free streaming at c,
@@ -652,7 +709,7 @@ static void step_once(orc_sim* s) {
       g->w = 0.0;
       continue;
     }
-    if (!qed || (p->flags & ORC_CONV_OFF)) continue;
+    if (!replay && (!qed || (p->flags & ORC_CONV_OFF))) continue;
     double path = (double)(n + 1 - g->n0) * s->dt;
     double sinpsi = fabs(sin(path / s->rc));
     double chi = fabs(g->x) * p->b * sinpsi;
@@ -672,7 +729,7 @@ static void step_once(orc_sim* s) {
       double up = dir * sqrt(fmax(gam * gam - 1.0, 0.0));
       olep em = {g->cell, g->xi, up, -g->w, child_id(p->seed, g->id, n, 0)};
       olep ep = {g->cell, g->xi, up, g->w, child_id(p->seed, g->id, n, 1)};
-      log_event(s, 1, n, g->id, 0, fabs(g->x));
+      log_event(s, 1, n, g->id, 0, fabs(g->x), 0, 0.0, 0.0);
       push_lep(s, em);
       push_lep(s, ep);
       s->n_conv++;
@@ -742,9 +799,11 @@ void orc_get_photons(const orc_sim* s, int32_t* cell, double* xi, double* x, dou
   }
 }
 
-void orc_get_events(const orc_sim* s, int32_t* kind, int32_t* sub, int64_t* step, uint64_t* id, double* x) {
+void orc_get_events(const orc_sim* s, int32_t* kind, int32_t* sub, int64_t* step, uint64_t* id, double* x,
+                    int32_t* cell, double* xi, double* w) {
   for (int64_t i = 0; i < s->nev; ++i) {
     kind[i] = s->ev[i].kind; sub[i] = s->ev[i].sub; step[i] = s->ev[i].step; id[i] = s->ev[i].id; x[i] = s->ev[i].x;
+    cell[i] = s->ev[i].cell; xi[i] = s->ev[i].xi; w[i] = s->ev[i].w;
   }
 }
 
@@ -781,9 +840,12 @@ static int ev_sort_cmp(const void* a, const void* b) {
   return ev_cmp(x, y->kind, y->step, y->id, y->sub);
 }
 void orc_set_replay(orc_sim* s, int64_t n, const int32_t* kind, const int32_t* sub, const int64_t* step,
-                    const uint64_t* id, const double* x) {
+                    const uint64_t* id, const double* x, const int32_t* cell, const double* xi, const double* w) {
   oevent* e = (oevent*)malloc(sizeof(oevent) * (n ? n : 1));
-  for (int64_t i = 0; i < n; ++i) { e[i].kind = kind[i]; e[i].sub = sub[i]; e[i].step = step[i]; e[i].id = id[i]; e[i].x = x[i]; }
+  for (int64_t i = 0; i < n; ++i) {
+    e[i].kind = kind[i]; e[i].sub = sub[i]; e[i].step = step[i]; e[i].id = id[i]; e[i].x = x[i];
+    e[i].cell = cell[i]; e[i].xi = xi[i]; e[i].w = w[i];
+  }
   qsort(e, n, sizeof(oevent), ev_sort_cmp);
   s->rep = e; s->nrep = n;
 }

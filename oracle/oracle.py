@@ -18,7 +18,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 FLAGS = dict(
     QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32,
-    TRACK_ALL=64, ANTI_ALIGNED=128, RECORD=256, REPLAY=512, CONV_OFF=1024, EMIT_OFF=2048,
+    TRACK_ALL=64, ANTI_ALIGNED=128, RECORD=256, REPLAY=512, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096,
 )
 
 
@@ -86,13 +86,13 @@ def _load():
         lib.orc_rho.argtypes = [C.c_void_p, C.c_void_p]
         lib.orc_get_leptons.argtypes = [C.c_void_p] + [C.c_void_p] * 5
         lib.orc_get_photons.argtypes = [C.c_void_p] + [C.c_void_p] * 6
-        lib.orc_get_events.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+        lib.orc_get_events.argtypes = [C.c_void_p] + [C.c_void_p] * 8
         lib.orc_set_state.restype = C.c_int32
         lib.orc_set_state.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 5 + [C.c_int64] + \
             [C.c_void_p] * 6 + [C.c_double, C.c_int64]
         lib.orc_set_field.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.orc_set_injection.argtypes = [C.c_void_p, C.c_double, C.c_uint64]
-        lib.orc_set_replay.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 5
+        lib.orc_set_replay.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 8
         lib.orc_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         lib.orc_tsyn.restype = C.c_double
         lib.orc_tsyn.argtypes = [C.c_double]
@@ -216,11 +216,15 @@ class Oracle:
         self.lib.orc_get_photons(self.h, *[_ptr(a[k]) for k in ("cell", "xi", "x", "w", "n0", "id")])
         return a
 
+    _EV = (("kind", np.int32), ("sub", np.int32), ("step", np.int64), ("id", np.uint64), ("x", np.float64),
+           ("cell", np.int32), ("xi", np.float64), ("w", np.float64))
+
     def events(self) -> dict:
+        """Recorded QED events: kind 0 emission (x signed), 1 conversion,
+        2 tracked-photon birth (id, cell, xi, signed x, w)."""
         n = self.counts()["n_events"]
-        a = dict(kind=np.empty(n, np.int32), sub=np.empty(n, np.int32), step=np.empty(n, np.int64),
-                 id=np.empty(n, np.uint64), x=np.empty(n))
-        self.lib.orc_get_events(self.h, *[_ptr(a[k]) for k in ("kind", "sub", "step", "id", "x")])
+        a = {k: np.empty(n, dt) for k, dt in self._EV}
+        self.lib.orc_get_events(self.h, *[_ptr(a[k]) for k, _ in self._EV])
         return a
 
     def set_state(self, lep: dict, pho: dict | None = None, Es: float = 0.0, step: int = 0) -> int:
@@ -245,7 +249,5 @@ class Oracle:
         self.lib.orc_set_injection(self.h, float(acc), int(count))
 
     def set_replay(self, ev: dict) -> None:
-        self._rep = {k: np.ascontiguousarray(ev[k], dtype=dt) for k, dt in
-                     (("kind", np.int32), ("sub", np.int32), ("step", np.int64), ("id", np.uint64), ("x", np.float64))}
-        self.lib.orc_set_replay(self.h, self._rep["kind"].size,
-                                *[_ptr(self._rep[k]) for k in ("kind", "sub", "step", "id", "x")])
+        self._rep = {k: np.ascontiguousarray(ev[k], dtype=dt) for k, dt in self._EV}
+        self.lib.orc_set_replay(self.h, self._rep["kind"].size, *[_ptr(self._rep[k]) for k, _ in self._EV])
