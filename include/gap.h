@@ -59,6 +59,9 @@ extern "C" {
 #define GAP_ANTI_ALIGNED 128u   /* eta_co = +e n_co instead of -e n_co                 */
 #define GAP_CONV_OFF     1024u  /* photons never convert                               */
 #define GAP_EMIT_OFF     2048u  /* leptons never emit                                  */
+#define GAP_INJ_FIXED    4096u  /* injection count per step from inj_rate * ppc_ref
+                                   alone: inj_weight scales the injected charge only
+                                   (the injected density is inj_rate * inj_weight)    */
 
 /* initial states (gap_params.init_kind) */
 #define GAP_INIT_GAP      0  /* vacuum below H, electrons at ppc_init per cell above H  */
@@ -176,12 +179,47 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
 #define GAP_STATE_INJECTION 3  /* double accumulator, then uint64 injected count              */
 #define GAP_STATE_TIMING    4  /* int32 on/off: HIP-event timing of each kernel group of
                                   eager gap_step calls (not of graph replays)                  */
+#define GAP_STATE_DRIVE     5  /* double alpha, then double inj_weight: the imposed current
+                                  j_m = alpha j_co (Sect. 2.2) and the weight of one injected
+                                  electron from the next step on; ends a pending window        */
 
 /* Replace part of the state of tube `tube` (only valid when n_tubes == 1;
- * GAP_STATE_TIMING is valid for any handle).
+ * GAP_STATE_TIMING and GAP_STATE_DRIVE are valid for any handle).
  * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);
+
+/* Differentiable window (frozen QED).
+ *
+ * gap_window_forward runs `window_steps` steps from the current state, as
+ * gap_step would but with neither merge nor re-sort inside a segment of
+ * `ckpt_every` steps, saving the state (device memory, owned by the handle)
+ * at the start of every segment and at the end.  loss[t] (host array of
+ * n_tubes doubles) receives the time-averaged field energy density
+ *   L_t = 1/(W N_t) sum_{m=1..W} sum_k (E^{n0+m}_{k+1/2})^2
+ * over the fields after each of the W steps (E in units of
+ * m_e c omega_p,co / e).  Every tube must be non-periodic and not
+ * GAP_FIELD_FROZEN; ckpt_every must keep particles inside their tile window,
+ * i.e. ckpt_every <= (64 - 2) / cfl - 1 (136 steps at cfl = 0.45); GAP_EINVAL
+ * otherwise.  Blocks until the window has run.
+ *
+ * gap_backward then returns, per tube, dL/dalpha and dL/dn_inj of that window
+ * (host arrays of n_tubes doubles), where n_inj = inj_rate * inj_weight is the
+ * injected charge per step in units of n_co dx (use GAP_INJ_FIXED so that the
+ * number of injected macro-electrons does not depend on inj_weight).  The map
+ * differentiated is the push (Sect. 4: kick by E, drift at u/gamma) and the
+ * field (Sect. 2.2: Gauss integration from the surface field, which the drive
+ * alpha j_co and the absorbed and injected charges advance) with the QED
+ * events of the window frozen: an emission is a constant recoil offset, and
+ * photons and pairs born inside the window are constants; the fixed-point
+ * rounding of the charge split and drift counts as the identity.  Each
+ * segment is recomputed from its saved state with a tape of the lepton
+ * positions and momenta (device memory of (ckpt_every + 1) x slots x 8 bytes)
+ * and run in reverse; afterwards the handle is back at the window's end
+ * state.  GAP_ESTATE if no window was run, or if steps or state changes came
+ * after it.  Blocks until done. */
+int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss);
+int gap_backward(gap_t* g, double* dL_dalpha, double* dL_dninj);
 
 /* Release the handle and every buffer it owns (waits for queued work). */
 void gap_free(gap_t* g);

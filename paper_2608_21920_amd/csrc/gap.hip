@@ -4,6 +4,7 @@
 #include "gap.h"
 #include "gap_kernels.hpp"
 #include "gap_merge.hpp"
+#include "gap_adjoint.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -150,6 +151,38 @@ struct Store {
 
 struct Derived { double d_cm, lam, rc, dt, H, w0, s_co; int N; };
 
+// Saved state at the start of a window segment (stores re-sorted, tail empty).
+struct WinCkpt {
+  long long nl = 0, np = 0, nch_l = 0, nch_p = 0;
+  uint32_t* lpos = nullptr; float* lu = nullptr; float* lw = nullptr; uint64_t* lid = nullptr; int32_t* lchunk = nullptr;
+  uint32_t* ppos = nullptr; float* px = nullptr; float* pw = nullptr; int32_t* pn0 = nullptr; uint64_t* pid = nullptr;
+  int32_t* pchunk = nullptr;
+  Ctl lctl{}, pctl{};
+  Tube* tubes = nullptr;
+  float* ebar = nullptr;
+  float* E = nullptr;
+  long long* shard = nullptr;
+  int64_t host_step = 0;
+};
+
+// A window of steps run by gap_window_forward, kept for gap_backward.
+struct WinState {
+  bool valid = false;
+  int64_t W = 0, K = 0, nseg = 0, step_end = 0;
+  long long max_used = 0;
+  std::vector<WinCkpt> ck;
+  std::vector<void*> mem;       // allocations of this window
+  double* loss_acc = nullptr;
+  // reverse-pass buffers
+  long long M = 0;              // tape stride (slots)
+  uint32_t* tpos = nullptr; float* tu = nullptr; TapeMeta* meta = nullptr;
+  float* teb = nullptr; float* tE = nullptr; float* wlast = nullptr;
+  float* lam[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  double* lamE = nullptr; double* suf = nullptr; double* lamEb = nullptr;
+  AdjTube* at = nullptr;
+  uint32_t* hvals = nullptr; uint64_t hmask = 0;
+};
+
 }  // namespace
 
 struct gap_t {
@@ -198,6 +231,7 @@ struct gap_t {
   bool any_periodic = false;
   int sticky = 0;
   // graph: replay is valid from the recorded start state and leaves the end state
+  WinState win;
   hipGraphExec_t gexec = nullptr;
   int64_t gsteps = -1;
   int gs_l = -1, gs_p = -1, ge_l = -1, ge_p = -1;
@@ -222,9 +256,12 @@ void* dalloc(gap_t* g, size_t bytes) {
   return p;
 }
 
+void win_release(gap_t* g);
+
 void release(gap_t* g) {
   if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
   if (g->s) (void)hipStreamSynchronize(g->s);
+  win_release(g);
   for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
   g->ev_pool.clear();
   for (void* p : g->owned) {
@@ -420,6 +457,288 @@ void merge_all(gap_t* g) {
   // merged-away records are dead slots until the next scheduled re-sort
 }
 
+// ------------------------------------------------------------------ window
+int sync_and_err(gap_t* g);
+Ctl read_ctl(const Store& st);
+
+void* walloc(gap_t* g, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (g->custom_alloc) p = g->al.alloc(bytes, g->al.ctx);
+  else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  if (p) {
+    g->win.mem.push_back(p);
+    (void)hipMemsetAsync(p, 0, bytes, g->s);
+  }
+  return p;
+}
+
+void win_release(gap_t* g) {
+  if (!g->win.mem.empty() && g->s) (void)hipStreamSynchronize(g->s);
+  for (void* p : g->win.mem) {
+    if (g->custom_alloc) g->al.free(p, g->al.ctx);
+    else (void)hipFree(p);
+  }
+  g->win = WinState{};
+}
+
+// One step of a window: no merge, no re-sort (slots stay put).
+void enqueue_window_step(gap_t* g) {
+  Ctx cx = make_ctx(g);
+  k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
+  k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
+  k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+  k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
+  k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+  field_pass(g, 0);
+  ++g->host_step;
+}
+
+#define D2D(dst, src, bytes) HIPCHK(hipMemcpyAsync((dst), (src), (bytes), hipMemcpyDeviceToDevice, g->s))
+
+int save_ckpt(gap_t* g, WinCkpt& c) {
+  HIPCHK(hipStreamSynchronize(g->s));
+  c.lctl = read_ctl(g->lep);
+  c.pctl = read_ctl(g->pho);
+  if (c.lctl.tail != 0 || c.pctl.tail != 0) return GAP_ESTATE;
+  c.nch_l = c.lctl.n_sorted_chunks;
+  c.nch_p = c.pctl.n_sorted_chunks;
+  c.nl = c.nch_l * CHUNK;
+  c.np = c.nch_p * CHUNK;
+  const size_t nl = (size_t)c.nl, np = (size_t)c.np;
+  c.lpos = (uint32_t*)walloc(g, nl * 4); c.lu = (float*)walloc(g, nl * 4); c.lw = (float*)walloc(g, nl * 4);
+  c.lid = (uint64_t*)walloc(g, nl * 8); c.lchunk = (int32_t*)walloc(g, (size_t)c.nch_l * 4 + 4);
+  c.ppos = (uint32_t*)walloc(g, np * 4); c.px = (float*)walloc(g, np * 4); c.pw = (float*)walloc(g, np * 4);
+  c.pn0 = (int32_t*)walloc(g, np * 4); c.pid = (uint64_t*)walloc(g, np * 8);
+  c.pchunk = (int32_t*)walloc(g, (size_t)c.nch_p * 4 + 4);
+  c.tubes = (Tube*)walloc(g, sizeof(Tube) * g->n_tubes);
+  c.ebar = (float*)walloc(g, sizeof(float) * g->total_nodes);
+  c.E = (float*)walloc(g, sizeof(float) * g->total_cells);
+  c.shard = (long long*)walloc(g, sizeof(long long) * g->n_tubes * NSHARD * C_N);
+  if (!c.lpos || !c.lu || !c.lw || !c.lid || !c.lchunk || !c.ppos || !c.px || !c.pw || !c.pn0 || !c.pid ||
+      !c.pchunk || !c.tubes || !c.ebar || !c.E || !c.shard)
+    return GAP_ENOMEM;
+  const Store& L = g->lep;
+  const Store& P = g->pho;
+  const int bl = L.cur, bp = P.cur;
+  if (nl) {
+    D2D(c.lpos, L.pos[bl], nl * 4); D2D(c.lu, L.a[bl], nl * 4); D2D(c.lw, L.w[bl], nl * 4);
+    D2D(c.lid, L.id[bl], nl * 8); D2D(c.lchunk, L.chunk[bl], (size_t)c.nch_l * 4);
+  }
+  if (np) {
+    D2D(c.ppos, P.pos[bp], np * 4); D2D(c.px, P.a[bp], np * 4); D2D(c.pw, P.w[bp], np * 4);
+    D2D(c.pn0, P.n0[bp], np * 4); D2D(c.pid, P.id[bp], np * 8); D2D(c.pchunk, P.chunk[bp], (size_t)c.nch_p * 4);
+  }
+  D2D(c.tubes, g->tubes, sizeof(Tube) * g->n_tubes);
+  D2D(c.ebar, g->ebar, sizeof(float) * g->total_nodes);
+  D2D(c.E, g->E, sizeof(float) * g->total_cells);
+  D2D(c.shard, g->shard, sizeof(long long) * g->n_tubes * NSHARD * C_N);
+  c.host_step = g->host_step;
+  return GAP_OK;
+}
+
+int restore_ckpt(gap_t* g, const WinCkpt& c) {
+  Store& L = g->lep;
+  Store& P = g->pho;
+  const int bl = L.cur, bp = P.cur;
+  const size_t nl = (size_t)c.nl, np = (size_t)c.np;
+  if (nl) {
+    D2D(L.pos[bl], c.lpos, nl * 4); D2D(L.a[bl], c.lu, nl * 4); D2D(L.w[bl], c.lw, nl * 4);
+    D2D(L.id[bl], c.lid, nl * 8); D2D(L.chunk[bl], c.lchunk, (size_t)c.nch_l * 4);
+  }
+  if (np) {
+    D2D(P.pos[bp], c.ppos, np * 4); D2D(P.a[bp], c.px, np * 4); D2D(P.w[bp], c.pw, np * 4);
+    D2D(P.n0[bp], c.pn0, np * 4); D2D(P.id[bp], c.pid, np * 8); D2D(P.chunk[bp], c.pchunk, (size_t)c.nch_p * 4);
+  }
+  HIPCHK(hipMemcpyAsync(L.ctl, &c.lctl, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
+  HIPCHK(hipMemcpyAsync(P.ctl, &c.pctl, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
+  D2D(g->tubes, c.tubes, sizeof(Tube) * g->n_tubes);
+  D2D(g->ebar, c.ebar, sizeof(float) * g->total_nodes);
+  D2D(g->E, c.E, sizeof(float) * g->total_cells);
+  D2D(g->shard, c.shard, sizeof(long long) * g->n_tubes * NSHARD * C_N);
+  HIPCHK(hipStreamSynchronize(g->s));
+  g->host_step = c.host_step;
+  g->since_rb = 0;
+  return GAP_OK;
+}
+
+int window_forward(gap_t* g, int64_t W, int64_t K, double* loss) {
+  for (int t = 0; t < g->n_tubes; ++t) {
+    const gap_params& q = g->P[t];
+    if (q.flags & (GAP_PERIODIC | GAP_FIELD_FROZEN)) return GAP_EINVAL;
+    const int64_t rmax = std::max(1, (int)std::floor((MARGIN - 2) / q.cfl) - 1);
+    if (K > rmax) return GAP_EINVAL;
+  }
+  win_release(g);
+  WinState& w = g->win;
+  w.W = W;
+  w.K = K;
+  w.nseg = (W + K - 1) / K;
+  w.ck.resize((size_t)w.nseg + 1);
+  w.loss_acc = (double*)walloc(g, sizeof(double) * g->n_tubes);
+  if (!w.loss_acc) return GAP_ENOMEM;
+  int e;
+  for (int64_t sg = 0; sg < w.nseg; ++sg) {
+    rebucket_all(g);
+    g->since_rb = 0;
+    if ((e = save_ckpt(g, w.ck[sg]))) return e;
+    const int64_t Ks = std::min(K, W - sg * K);
+    for (int64_t j = 0; j < Ks; ++j) {
+      enqueue_window_step(g);
+      k_loss<<<g->n_tubes, ADJ_THREADS, 0, g->s>>>(g->E, g->tubes, w.loss_acc);
+    }
+    HIPCHK(hipStreamSynchronize(g->s));
+    const Ctl c = read_ctl(g->lep);
+    w.max_used = std::max<long long>(w.max_used, c.n_sorted_chunks * CHUNK + c.tail);
+  }
+  rebucket_all(g);
+  g->since_rb = 0;
+  if ((e = save_ckpt(g, w.ck[(size_t)w.nseg]))) return e;
+  if ((e = sync_and_err(g))) return e;
+  std::vector<double> acc(g->n_tubes);
+  HIPCHK(hipMemcpy(acc.data(), w.loss_acc, sizeof(double) * g->n_tubes, hipMemcpyDeviceToHost));
+  for (int t = 0; t < g->n_tubes; ++t) loss[t] = acc[t] / ((double)W * g->P[t].n_cells);
+  w.step_end = g->host_step;
+  w.valid = true;
+  return GAP_OK;
+}
+
+int backward_alloc(gap_t* g) {
+  WinState& w = g->win;
+  if (w.tpos) return GAP_OK;
+  w.M = (w.max_used + CHUNK - 1) / CHUNK * CHUNK + CHUNK;
+  const size_t M = (size_t)w.M, K = (size_t)w.K;
+  w.tpos = (uint32_t*)walloc(g, (K + 1) * M * 4);
+  w.tu = (float*)walloc(g, (K + 1) * M * 4);
+  w.meta = (TapeMeta*)walloc(g, (K + 1) * sizeof(TapeMeta));
+  w.teb = (float*)walloc(g, K * (size_t)g->total_nodes * 4);
+  w.tE = (float*)walloc(g, (K + 1) * (size_t)g->total_cells * 4);
+  w.wlast = (float*)walloc(g, M * 4);
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 3; ++k) w.lam[b][k] = (float*)walloc(g, M * 4);
+  w.lamE = (double*)walloc(g, (size_t)g->total_cells * 8);
+  w.suf = (double*)walloc(g, (size_t)g->total_nodes * 8);
+  w.lamEb = (double*)walloc(g, (size_t)g->total_nodes * 8);
+  w.at = (AdjTube*)walloc(g, sizeof(AdjTube) * g->n_tubes);
+  uint64_t hs = 1024;
+  while (hs < 2 * (uint64_t)M) hs <<= 1;
+  w.hmask = hs - 1;
+  w.hvals = (uint32_t*)walloc(g, hs * 4);
+  if (!w.tpos || !w.tu || !w.meta || !w.teb || !w.tE || !w.wlast || !w.lamE || !w.suf || !w.lamEb || !w.at ||
+      !w.hvals)
+    return GAP_ENOMEM;
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 3; ++k)
+      if (!w.lam[b][k]) return GAP_ENOMEM;
+  return GAP_OK;
+}
+
+int backward(gap_t* g, double* dalpha, double* dninj) {
+  WinState& w = g->win;
+  if (!w.valid || g->host_step != w.step_end) return GAP_ESTATE;
+  int e;
+  if ((e = backward_alloc(g))) return e;
+  {
+    std::vector<AdjTube> at(g->n_tubes);
+    for (int t = 0; t < g->n_tubes; ++t) {
+      AdjTube& a = at[t];
+      std::memset(&a, 0, sizeof(a));
+      a.w0 = g->D[t].w0;
+      a.s_co = g->D[t].s_co;
+      a.dt = g->D[t].dt;
+      a.cfl = g->P[t].cfl;
+      a.lossw = 2.0 / ((double)w.W * g->P[t].n_cells);
+      a.N = g->P[t].n_cells;
+      a.cell_off = g->th[t].cell_off;
+      a.node_off = g->th[t].node_off;
+    }
+    HIPCHK(hipStreamSynchronize(g->s));
+    HIPCHK(hipMemcpy(w.at, at.data(), sizeof(AdjTube) * g->n_tubes, hipMemcpyHostToDevice));
+  }
+  const size_t M = (size_t)w.M;
+  const int fgrid = (int)std::min<long long>(4096, (w.M + 255) / 256);
+  int cur = 0;
+  for (int64_t sg = w.nseg - 1; sg >= 0; --sg) {
+    if ((e = restore_ckpt(g, w.ck[(size_t)sg]))) return e;
+    const int64_t Ks = std::min(w.K, w.W - sg * w.K);
+    D2D(w.tE, g->E, sizeof(float) * g->total_cells);
+    // recompute the segment, taping the lepton store before each step
+    for (int64_t j = 0; j < Ks; ++j) {
+      Ctx cx = make_ctx(g);
+      k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
+      k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + j * M, w.tu + j * M, w.wlast, w.meta + j,
+                                      w.M, 0, g->err);
+      D2D(w.teb + j * (size_t)g->total_nodes, g->ebar, sizeof(float) * g->total_nodes);
+      k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
+      k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+      k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
+      k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+      field_pass(g, 0);
+      ++g->host_step;
+      D2D(w.tE + (j + 1) * (size_t)g->total_cells, g->E, sizeof(float) * g->total_cells);
+    }
+    {
+      Ctx cx = make_ctx(g);
+      k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + Ks * M, w.tu + Ks * M, w.wlast, w.meta + Ks,
+                                      w.M, 1, g->err);
+    }
+    // adjoint of the state after the segment, in this recomputed layout
+    if (sg == w.nseg - 1) {
+      for (int k = 0; k < 3; ++k) k_fill_i32<<<fgrid, 256, 0, g->s>>>((int32_t*)w.lam[cur][k], w.M, 0);
+      k_adj_init<<<g->n_tubes, ADJ_THREADS, 0, g->s>>>(w.lamE, w.tE + Ks * (size_t)g->total_cells, w.at);
+    } else {
+      const WinCkpt& nx = w.ck[(size_t)sg + 1];
+      const int hgrid = (int)std::min<uint64_t>(4096, (w.hmask + 256) / 256);
+      k_hash_clear<<<hgrid, 256, 0, g->s>>>(w.hvals, (long long)w.hmask + 1);
+      k_hash_insert<<<fgrid, 256, 0, g->s>>>(nx.lid, nx.lw, nx.lchunk, g->tiles, nx.nl, w.hvals, w.hmask);
+      const int nw = cur ^ 1;
+      k_lam_map<<<fgrid, 256, 0, g->s>>>(g->lep.lep(g->lep.cur), g->lep.ctl, g->lep.chunk[g->lep.cur], g->lep.tt,
+                                         g->tiles, nx.lid, nx.lchunk, w.hvals, w.hmask,
+                                         w.lam[cur][0], w.lam[cur][1], w.lam[cur][2], w.lam[nw][0], w.lam[nw][1],
+                                         w.lam[nw][2], w.M, g->err);
+      cur = nw;
+    }
+    // reverse steps
+    AdjCtx ac;
+    ac.tiles = g->tiles;
+    ac.chunk = g->lep.chunk[g->lep.cur];
+    ac.tt = g->lep.tt;
+    ac.wlast = w.wlast;
+    ac.lxi = w.lam[cur][0];
+    ac.lu = w.lam[cur][1];
+    ac.lw = w.lam[cur][2];
+    ac.lamE = w.lamE;
+    ac.suf = w.suf;
+    ac.lamEb = w.lamEb;
+    ac.at = w.at;
+    for (int64_t j = Ks - 1; j >= 0; --j) {
+      k_adj_field<<<g->n_tubes, ADJ_THREADS, 0, g->s>>>(w.lamE, w.suf, w.at);
+      ac.pos0 = w.tpos + j * M;
+      ac.u0 = w.tu + j * M;
+      ac.pos1 = w.tpos + (j + 1) * M;
+      ac.u1 = w.tu + (j + 1) * M;
+      ac.meta0 = w.meta + j;
+      ac.eb0 = w.teb + j * (size_t)g->total_nodes;
+      k_adj_leptons<<<kGrid, TPB, 0, g->s>>>(ac);
+      const float* Eprev = (sg > 0 || j > 0) ? w.tE + j * (size_t)g->total_cells : nullptr;
+      k_adj_nodes<<<g->n_tubes, ADJ_THREADS, 0, g->s>>>(w.lamE, w.lamEb, Eprev, w.at);
+    }
+  }
+  if ((e = sync_and_err(g))) return e;
+  std::vector<AdjTube> at(g->n_tubes);
+  HIPCHK(hipMemcpy(at.data(), w.at, sizeof(AdjTube) * g->n_tubes, hipMemcpyDeviceToHost));
+  for (int t = 0; t < g->n_tubes; ++t) {
+    dalpha[t] = at[t].dalpha;
+    const double rate = g->P[t].inj_rate;
+    dninj[t] = rate > 0 ? at[t].dinjw / rate : 0.0;
+  }
+  if ((e = restore_ckpt(g, w.ck[(size_t)w.nseg]))) return e;
+  return sync_and_err(g);
+}
+
+#undef D2D
+
 void enqueue_step(gap_t* g) {
   if (g->merge_on && g->host_step % g->merge_every == 0) merge_all(g);
   Ctx cx = make_ctx(g);
@@ -532,7 +851,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     T.dtd = d.dt;
     T.scale = d.w0 / kTwo24;
     T.drive = q.alpha * d.s_co * d.dt;
-    T.inj_per_step = q.inj_rate * q.ppc_ref / q.inj_weight;
+    T.inj_per_step = q.inj_rate * q.ppc_ref / ((q.flags & GAP_INJ_FIXED) ? 1.0 : q.inj_weight);
     T.inv_len_scale = d.w0 / ((double)q.n_cells * kTwo24 * kTwo24);
     T.bg_unit = (q.flags & GAP_ETA_CO_OFF) ? 0 : (int64_t)std::llrint(-d.s_co) * q.ppc_ref * (int64_t)kTwo24;
     T.hfix = (int64_t)std::ceil(q.h_gap_frac * q.n_cells * kTwo24);
@@ -926,6 +1245,27 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     g->ev_used = 0;
     return GAP_OK;
   }
+  g->win.valid = false;     // any other state change ends a pending window
+  if (kind == GAP_STATE_DRIVE) {
+    if (bytes < 16) return GAP_EINVAL;
+    double v[2];
+    std::memcpy(v, host_buf, 16);
+    if (!std::isfinite(v[0]) || !(v[1] > 0) || v[1] >= 65536.0) return GAP_EINVAL;
+    int e = sync_and_err(g);
+    if (e == GAP_EDEVICE) return e;
+    if ((e = download_tubes(g))) return e;
+    gap_params& q = g->P[tube];
+    Tube& T = g->th[tube];
+    q.alpha = v[0];
+    q.inj_weight = v[1];
+    T.drive = q.alpha * g->D[tube].s_co * g->D[tube].dt;
+    T.inj_w = (float)q.inj_weight;
+    T.inj_T = std::llrint((double)T.inj_w * kTwo24);
+    T.inj_per_step = q.inj_rate * q.ppc_ref / ((q.flags & GAP_INJ_FIXED) ? 1.0 : q.inj_weight);
+    if ((e = upload_tubes(g))) return e;
+    g->win.valid = false;
+    return GAP_OK;
+  }
   if (g->n_tubes != 1) return GAP_ESTATE;
   int e = sync_and_err(g);
   if (e == GAP_EDEVICE) return e;
@@ -1038,6 +1378,16 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     default:
       return GAP_EINVAL;
   }
+}
+
+int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss) {
+  if (!g || window_steps < 1 || ckpt_every < 1 || !loss) return GAP_EINVAL;
+  return window_forward(g, window_steps, ckpt_every, loss);
+}
+
+int gap_backward(gap_t* g, double* dL_dalpha, double* dL_dninj) {
+  if (!g || !dL_dalpha || !dL_dninj) return GAP_EINVAL;
+  return backward(g, dL_dalpha, dL_dninj);
 }
 
 void gap_free(gap_t* g) {

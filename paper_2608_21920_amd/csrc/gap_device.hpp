@@ -40,7 +40,8 @@ enum : int {
 
 enum : uint32_t {
   F_QED_OFF = 1u, F_ETA_CO_OFF = 2u, F_FIELD_FROZEN = 4u, F_RECOIL_OFF = 8u, F_PERIODIC = 16u,
-  F_MERGE_ON = 32u, F_TRACK_ALL = 64u, F_ANTI_ALIGNED = 128u, F_CONV_OFF = 1024u, F_EMIT_OFF = 2048u
+  F_MERGE_ON = 32u, F_TRACK_ALL = 64u, F_ANTI_ALIGNED = 128u, F_CONV_OFF = 1024u, F_EMIT_OFF = 2048u,
+  F_INJ_FIXED = 4096u
 };
 
 // sticky device error bits
@@ -92,7 +93,7 @@ struct Ctl {                  // control block of one store
   int64_t limit;              // appends stop at this slot (keeps room for re-sort padding)
   int64_t total_chunks_new;   // written by the re-sort scan
   int64_t cap_live;           // live-particle cap (merge threshold reference)
-  int64_t pad;
+  int64_t tail_pre;           // tail length before this step's injection
 };
 
 struct LepBuf { uint32_t* pos; float* u; float* w; uint64_t* id; };

@@ -139,6 +139,7 @@ __device__ __forceinline__ long long reserve_tail(Ctl* c, int n, int* dropped) {
 // the snapshots of the tails that this step's passes will process.
 __global__ void k_pre(Ctx cx, int n_tubes) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  cx.lc->tail_pre = cx.lc->tail;
   for (int t = 0; t < n_tubes; ++t) {
     Tube& T = cx.tubes[t];
     if (T.inj_per_step <= 0.0 || (T.flags & F_PERIODIC)) continue;

@@ -17,15 +17,15 @@ LIB_PATH = os.path.join(_HERE, "libgap.so")
 
 QED_OFF, ETA_CO_OFF, FIELD_FROZEN, RECOIL_OFF, PERIODIC, MERGE_ON, TRACK_ALL, ANTI_ALIGNED = \
     1, 2, 4, 8, 16, 32, 64, 128
-CONV_OFF, EMIT_OFF = 1024, 2048
+CONV_OFF, EMIT_OFF, INJ_FIXED = 1024, 2048, 4096
 FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32, TRACK_ALL=64,
-             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048)
+             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096)
 
 ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING = range(9)
-STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING = range(5)
+STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE = range(6)
 TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
@@ -105,6 +105,10 @@ def load_library():
     lib.gap_free.argtypes = [C.c_void_p]
     lib.gap_strerror.restype = C.c_char_p
     lib.gap_strerror.argtypes = [C.c_int]
+    lib.gap_window_forward.restype = C.c_int
+    lib.gap_window_forward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.gap_backward.restype = C.c_int
+    lib.gap_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gap_sync_inverse_host.restype = C.c_int
     lib.gap_sync_inverse_host.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     _lib = lib
@@ -252,6 +256,60 @@ class Gap:
                               np.array([es], np.float64).view(np.uint8)])
         _check(self.lib.gap_set_state(self.h, STATE_FIELD, 0, buf.ctypes.data, buf.nbytes), "set_field")
 
+    def set_drive(self, alpha: float, inj_weight: float, tube: int = 0):
+        buf = np.array([alpha, inj_weight], np.float64)
+        _check(self.lib.gap_set_state(self.h, STATE_DRIVE, int(tube), buf.ctypes.data, buf.nbytes), "set_drive")
+
+    # -- differentiable window (frozen QED)
+    def window_forward(self, steps: int, ckpt_every: int = 100) -> np.ndarray:
+        loss = np.zeros(self.n_tubes, np.float64)
+        _check(self.lib.gap_window_forward(self.h, int(steps), int(ckpt_every), loss.ctypes.data),
+               "gap_window_forward")
+        return loss
+
+    def backward(self):
+        da = np.zeros(self.n_tubes, np.float64)
+        dn = np.zeros(self.n_tubes, np.float64)
+        _check(self.lib.gap_backward(self.h, da.ctypes.data, dn.ctypes.data), "gap_backward")
+        return da, dn
+
     def set_injection(self, acc: float, count: int):
         buf = np.concatenate([np.array([acc], np.float64).view(np.uint8), np.array([count], np.uint64).view(np.uint8)])
         _check(self.lib.gap_set_state(self.h, STATE_INJECTION, 0, buf.ctypes.data, buf.nbytes), "set_injection")
+
+
+def _window_loss_function():
+    import torch
+
+    class GapWindowLoss(torch.autograd.Function):
+        """Time-averaged field energy density of a window of steps, as a
+        function of the imposed current alpha and the injected charge density
+        n_inj (per tube, CPU float64 tensors).  The forward sets the drive of
+        every tube (inj_weight = n_inj / inj_rate), runs the window on the GPU
+        and returns the per-tube losses; the backward runs the library's
+        reverse pass."""
+
+        @staticmethod
+        def forward(ctx, alpha, n_inj, gap, steps, ckpt_every):
+            a = alpha.detach().cpu().double().numpy().reshape(-1)
+            n = n_inj.detach().cpu().double().numpy().reshape(-1)
+            for t in range(gap.n_tubes):
+                rate = float(gap.cfgs[t].get("inj_rate", 0.0))
+                w = n[t] / rate if rate > 0 else float(gap.cfgs[t].get("inj_weight", 1.0))
+                gap.set_drive(float(a[t]), w, t)
+            loss = gap.window_forward(int(steps), int(ckpt_every))
+            ctx.gap = gap
+            return torch.as_tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad):
+            da, dn = ctx.gap.backward()
+            g = grad.detach().cpu().double()
+            return g * torch.as_tensor(da), g * torch.as_tensor(dn), None, None, None
+
+    return GapWindowLoss
+
+
+def window_loss(alpha, n_inj, gap: Gap, steps: int, ckpt_every: int = 100):
+    """Differentiable per-tube window loss (see GapWindowLoss)."""
+    return _window_loss_function().apply(alpha, n_inj, gap, steps, ckpt_every)

@@ -1,0 +1,163 @@
+"""The differentiable window on the GPU (frozen QED) against the FP64 oracle
+adjoint, against finite differences of the GPU window itself, and for
+consistency (checkpoint interval, state restored, batched tubes, autograd).
+
+Bars: window loss within 1e-6 relative of the oracle's (FP32 field vs FP64);
+gradients within 1e-3 relative of the FP64 adjoint while both sides follow
+the same realisation (short windows from the same seeded initial state)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2608_21920_amd import Gap, workloads, window_loss
+from paper_2608_21920_amd import gap as G
+from oracle.oracle import FLAGS as OF
+from oracle import adjoint as A
+
+from gpu_util import by_id, gpu_leptons_as_oracle
+
+pytestmark = pytest.mark.gpu
+
+DENSE_QED = dict(n_cells=256, init_kind=1, ppc_init=8, alpha=1.5, b=1.0, lambda_c_scale=7.4e7,
+                 r_curv_scale=4.3e-8, inj_rate=0.5, seed=3)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu(cfg, **kw):
+    return Gap(dict(cfg, flags=cfg.get("flags", 0) | G.INJ_FIXED, **kw))
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("name,cfg,W,K", [
+    ("tiny preset", dict(workloads.TINY, n_cells=256, ppc_init=8, inj_rate=0.5), 60, 20),
+    ("dense QED", DENSE_QED, 24, 8),
+])
+def test_window_matches_oracle_adjoint(torch_gpu, name, cfg, W, K):
+    _say("case: window vs oracle adjoint, %s, W=%d K=%d" % (name, W, K))
+    g = _gpu(cfg)
+    loss = g.window_forward(W, K)[0]
+    da, dn = g.backward()
+    win = A.Window(cfg, W, None)
+    ad = A.adjoint(win)
+    ev = win.events
+    _say("  oracle events: emit %d conv %d; loss gpu %.9e orc %.9e; dalpha %.6e / %.6e; dninj %.6e / %.6e" % (
+        (ev["kind"] == 0).sum(), (ev["kind"] == 1).sum(), loss, ad["loss"], da[0], ad["dL_dalpha"], dn[0],
+        ad["dL_dninj"]))
+    assert _rel(loss, ad["loss"]) < 1e-6
+    assert _rel(da[0], ad["dL_dalpha"]) < 1e-3
+    assert _rel(dn[0], ad["dL_dninj"]) < 1e-3
+    g.close()
+
+
+def test_adjoint_matches_gpu_finite_differences(torch_gpu):
+    _say("case: GPU adjoint vs GPU finite differences, QED off")
+    cfg = dict(n_cells=1000, init_kind=1, ppc_init=16, alpha=1.5, inj_rate=0.5, flags=G.QED_OFF)
+    W, K = 80, 40
+    g = _gpu(cfg)
+    g.window_forward(W, K)
+    da, dn = g.backward()
+    g.close()
+
+    def loss(alpha, w):
+        h = _gpu(cfg)
+        h.set_drive(alpha, w)
+        v = h.window_forward(W, K)[0]
+        h.close()
+        return v
+    ha = 1e-3
+    fa = (loss(1.5 + ha, 1.0) - loss(1.5 - ha, 1.0)) / (2 * ha)
+    hw = 2.0 ** -10                      # on the 2^-24 grid of the fixed-point charge
+    fn = (loss(1.5, 1.0 + hw) - loss(1.5, 1.0 - hw)) / (2 * hw * 0.5)
+    _say("  dalpha adj %.6e fd %.6e; dninj adj %.6e fd %.6e" % (da[0], fa, dn[0], fn))
+    assert _rel(da[0], fa) < 1e-3
+    assert _rel(dn[0], fn) < 1e-3
+
+
+def test_checkpoint_interval_and_restored_state(torch_gpu):
+    _say("case: checkpoint interval independence, state after backward")
+    cfg = dict(workloads.TINY, n_cells=512, ppc_init=8, inj_rate=0.5)
+    res = []
+    for K in (7, 25, 60):
+        g = _gpu(cfg)
+        loss = g.window_forward(60, K)[0]
+        L1, E1 = by_id(gpu_leptons_as_oracle(g.leptons())), g.field()
+        da, dn = g.backward()
+        L2, E2 = by_id(gpu_leptons_as_oracle(g.leptons())), g.field()
+        for k in ("cell", "xi", "u", "w", "id"):
+            assert np.array_equal(L1[k], L2[k]), k
+        assert np.array_equal(E1, E2)
+        g.step(5)                       # the handle keeps stepping after a backward
+        assert g.counts()["err"] == 0
+        res.append((loss, da[0], dn[0]))
+        g.close()
+    for loss, a, n in res[1:]:
+        assert loss == res[0][0]
+        assert _rel(a, res[0][1]) < 1e-5 and _rel(n, res[0][2]) < 1e-5
+
+
+def test_autograd_function(torch_gpu):
+    import torch
+    _say("case: torch.autograd window loss")
+    cfg = dict(workloads.TINY, n_cells=256, ppc_init=8, inj_rate=0.5)
+    g = _gpu(cfg)
+    alpha = torch.tensor([1.5], dtype=torch.float64, requires_grad=True)
+    ninj = torch.tensor([0.5], dtype=torch.float64, requires_grad=True)
+    L = window_loss(alpha, ninj, g, 40, 20)
+    (3.0 * L.sum()).backward()
+    g.close()
+    h = _gpu(cfg)
+    h.window_forward(40, 20)
+    da, dn = h.backward()
+    h.close()
+    assert _rel(alpha.grad.item(), 3.0 * da[0]) < 1e-5
+    assert _rel(ninj.grad.item(), 3.0 * dn[0]) < 1e-5
+
+
+def test_batched_window_equals_single_tubes(torch_gpu):
+    _say("case: batched window vs single-tube windows")
+    cfgs = [dict(workloads.TINY, n_cells=256, ppc_init=8, inj_rate=0.5, seed=4),
+            dict(workloads.TINY, n_cells=300, ppc_init=4, inj_rate=0.3, alpha=-1.0, seed=5)]
+    gb = Gap([dict(c, flags=G.INJ_FIXED) for c in cfgs])
+    lb = gb.window_forward(40, 20)
+    dab, dnb = gb.backward()
+    gb.close()
+    for t, c in enumerate(cfgs):
+        g = _gpu(c)
+        l1 = g.window_forward(40, 20)[0]
+        da, dn = g.backward()
+        g.close()
+        assert lb[t] == l1
+        assert _rel(dab[t], da[0]) < 1e-5 and _rel(dnb[t], dn[0]) < 1e-5
+
+
+def test_window_argument_checks(torch_gpu):
+    g = _gpu(dict(n_cells=64, init_kind=2, flags=G.QED_OFF))
+    with pytest.raises(G.GapError):
+        g.backward()                               # no window yet
+    with pytest.raises(G.GapError):
+        g.window_forward(10, 200)                  # segment longer than the tile margin allows
+    g.window_forward(10, 5)
+    g.step(1)
+    with pytest.raises(G.GapError):
+        g.backward()                               # stepped after the window
+    g.close()
+    p = Gap(dict(n_cells=64, init_kind=2, flags=G.QED_OFF | G.PERIODIC))
+    with pytest.raises(G.GapError):
+        p.window_forward(10, 5)
+    p.close()
