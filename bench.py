@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("gap.hip", "gap_device.hpp", "gap_kernels.hpp", "gap_merge.hpp")
+KERNEL_SOURCES = ("gap_device.hpp", "gap_kernels.hpp")   # code of the two particle kernels
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_leptons_k_photons_production.txt")
 # algorithmic bytes per unit of work: a lepton-step reads
 # position, momentum, weight and writes position, momentum; an emission
@@ -55,7 +55,7 @@ def grow(g, target, max_steps, block=1000):
 
 
 def kernel_source_hash():
-    """sha256 over the HIP sources, in a fixed order."""
+    """sha256 over the sources of the particle kernels, in a fixed order."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
@@ -112,32 +112,32 @@ class ProfilerRegion:
             self.lib.roctxProfilerPause(0)
 
 
-def cpu_baseline(g, budget_s=15.0, sample=400_000):
-    """Oracle particle-steps/s on a random sample of the grown GPU state."""
+def cpu_baseline(cfg, step, budget_s=15.0, sample=400_000):
+    """Oracle particle-steps/s on a seeded discharge-like sample of the
+    production gap (4e5 particles, 39% leptons as in the grown state)."""
     from oracle.oracle import Oracle
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import gpu_leptons_as_oracle, gpu_photons_as_oracle
-    L, P = g.leptons(), g.photons()
-    rng = np.random.default_rng(0)
-    nl = min(L.size, int(sample * L.size / max(L.size + P.size, 1)))
-    npho = min(P.size, sample - nl)
-    L = L[rng.choice(L.size, nl, replace=False)] if nl < L.size else L
-    P = P[rng.choice(P.size, npho, replace=False)] if npho < P.size else P
-    o = Oracle(g.cfgs[0])
-    step = g.counts()["step"]
-    o.set_state(gpu_leptons_as_oracle(L), gpu_photons_as_oracle(P), Es=g.es(), step=step)
+    from paper_2608_21920_amd import inputs
+    nl = int(0.39 * sample)
+    L, P = inputs.discharge_sample(7, cfg["n_cells"], cfg.get("h_gap_frac", 0.8), nl, sample - nl, step)
+    o = Oracle(cfg)
+    o.set_state(inputs.leptons_as_oracle(L), inputs.photons_as_oracle(P), Es=0.0, step=step)
+    c_start = o.counts()
     t0 = time.time()
     done = 0
     ps = 0
     while time.time() - t0 < budget_s:
         c0 = o.counts()
         o.step(1)
-        c1 = o.counts()
         ps += c0["n_lep"] + c0["n_pho"]
         done += 1
     el = time.time() - t0
+    c_end = o.counts()
+    ev = (c_end["n_emit_eval"] - c_start["n_emit_eval"]) / max(1, ps)
+    cv = (c_end["n_conv_eval"] - c_start["n_conv_eval"]) / max(1, ps)
     return dict(value=ps / el, unit="particle-steps/s", cores=1, kind="oracle",
-                sample="%d leptons + %d photons drawn from the grown state, %d steps (%.1f s)" % (nl, npho, done, el))
+                sample="seeded discharge-like state of the production gap: %d leptons (gamma log-uniform in "
+                       "[1, 1e8] over the QED zone) + %d photons (x log-uniform in [2, 1e8]), %d steps in %.1f s; "
+                       "emission / conversion evaluations per particle-step %.3f / %.3f" % (nl, sample - nl, done, el, ev, cv))
 
 
 def copy_calibration(nbytes):
@@ -231,14 +231,16 @@ def main():
         "config": {"workload": "production gap: 65536 cells, alpha 1.5, b 0.1, R_curv 1e7 cm, surface "
                                "injection 0.1 n_co dx/step, caps 5e7 per species",
                    "n_cells": cfg["n_cells"], "step_at_start": c0["step"], "leptons": c0["n_lep"],
-                   "photons": c0["n_pho"], "parallelism": "single GPU", "graph": a.graph},
+                   "photons": c0["n_pho"], "parallelism": "single GPU", "graph": a.graph,
+                   "emit_eval_per_particle_step": round(d["n_emit_eval"] / max(1, psteps), 4),
+                   "conv_eval_per_particle_step": round(d["n_conv_eval"] / max(1, psteps), 4)},
         "roofline": roof,
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if not a.graph else None,
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g)
+        out["cpu_baseline"] = cpu_baseline(cfg, c1["step"])
     g.close()
     print(json.dumps(out))
 

@@ -33,9 +33,7 @@ COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_abs
               "lep_steps", "pho_steps", "rebuckets", "lep_steps_tail", "emit_eval_tail", "pho_steps_tail",
               "conv_eval_tail"]
 
-LEPTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("u", "<f4"), ("w", "<f4"), ("id", "<u8")])
-PHOTON_DTYPE = np.dtype([("cell", "<i4"), ("frac", "<u4"), ("x", "<f4"), ("w", "<f4"), ("n0", "<i4"),
-                         ("pad", "<i4"), ("id", "<u8")])
+from .inputs import LEPTON_DTYPE, PHOTON_DTYPE  # noqa: E402  (record layouts of the C ABI)
 
 
 class GapError(RuntimeError):

@@ -4,16 +4,8 @@ import numpy as np
 TWO24 = float(1 << 24)
 
 
-def gpu_leptons_as_oracle(rec):
-    """GPU lepton records -> oracle state arrays (exact: frac/2^24 and f32 -> f64)."""
-    return dict(cell=rec["cell"].astype(np.int32), xi=rec["frac"].astype(np.float64) / TWO24,
-                u=rec["u"].astype(np.float64), w=rec["w"].astype(np.float64), id=rec["id"].astype(np.uint64))
-
-
-def gpu_photons_as_oracle(rec):
-    return dict(cell=rec["cell"].astype(np.int32), xi=rec["frac"].astype(np.float64) / TWO24,
-                x=rec["x"].astype(np.float64), w=rec["w"].astype(np.float64), n0=rec["n0"].astype(np.int64),
-                id=rec["id"].astype(np.uint64))
+from paper_2608_21920_amd.inputs import leptons_as_oracle as gpu_leptons_as_oracle  # noqa: E402,F401
+from paper_2608_21920_amd.inputs import photons_as_oracle as gpu_photons_as_oracle  # noqa: E402,F401
 
 
 def by_id(d):

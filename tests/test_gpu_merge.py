@@ -8,6 +8,7 @@ import pytest
 
 from paper_2608_21920_amd import Gap, workloads
 from paper_2608_21920_amd import gap as G
+from paper_2608_21920_amd.inputs import random_state
 from oracle.oracle import Oracle
 
 from gpu_util import by_id, gpu_leptons_as_oracle, gpu_photons_as_oracle
@@ -16,21 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _state(seed, n, N):
-    rng = np.random.default_rng(seed)
-    L = np.zeros(n, G.LEPTON_DTYPE)
-    L["cell"] = rng.integers(0, N, n)
-    L["frac"] = rng.integers(0, 1 << 24, n)
-    L["u"] = (rng.choice([-1, 1], n) * np.exp(rng.uniform(0, 10, n))).astype(np.float32)
-    L["w"] = rng.choice([-1.0, 1.0, 2.0], n)
-    L["id"] = rng.permutation(n).astype(np.uint64) * 2654435761 + 7
-    P = np.zeros(n // 2, G.PHOTON_DTYPE)
-    P["cell"] = rng.integers(0, N, n // 2)
-    P["frac"] = rng.integers(0, 1 << 24, n // 2)
-    P["x"] = (rng.choice([-1, 1], n // 2) * np.exp(rng.uniform(1, 8, n // 2))).astype(np.float32)
-    P["w"] = 1.0
-    P["n0"] = 0
-    P["id"] = rng.permutation(n // 2).astype(np.uint64) * 40503 + 11
-    return L, P
+    return random_state(seed, n, n // 2, N)
 
 
 @pytest.mark.parametrize("n,N", [(20000, 64), (3000, 700)])

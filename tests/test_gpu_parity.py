@@ -14,6 +14,7 @@ import pytest
 
 from paper_2608_21920_amd import Gap, workloads
 from paper_2608_21920_amd import gap as G
+from paper_2608_21920_amd.inputs import random_state
 from oracle.oracle import Oracle, FLAGS as OF
 
 from gpu_util import by_id, gpu_leptons_as_oracle, gpu_photons_as_oracle, rel_field_err
@@ -80,19 +81,18 @@ def test_field_parity_100_steps_tiny(torch_gpu):
 
 
 def test_identical_state_deposit_bit_exact(torch_gpu):
-    # after 150 GPU steps (pairs present), the oracle loads the GPU state and
-    # deposits it: node charge bit-exact, field identical after FP32 rounding
-    _say("case: identical-state deposit after 150 steps")
-    g = Gap(TINY)
-    g.step(150)
-    L = gpu_leptons_as_oracle(g.leptons())
-    o = Oracle(TINY)
-    o.set_state(L, None, Es=g.es(), step=150)
-    assert np.array_equal(g.rho(), o.rho())
-    assert np.array_equal(g.field(), o.field().astype(np.float32))
-    c = g.counts()
-    assert c["n_conv"] > 0, c
-    g.close()
+    # a seeded synthetic state (mixed charges and weights, ragged grid) loaded
+    # into both sides: node charge bit-exact, field identical after FP32 rounding
+    for seed, n, N in ((21, 200000, 1000), (22, 5000, 130)):
+        _say("case: identical-state deposit, seed %d, %d leptons on %d cells" % (seed, n, N))
+        L, _ = random_state(seed, n, 0, N, weights=(-1.0, 1.0, -2.0, 2.0, -0.5, 0.75))
+        cfg = dict(TINY, n_cells=N, init_kind=2)
+        g, o = Gap(cfg), Oracle(cfg)
+        g.set_particles(L)
+        o.set_state(gpu_leptons_as_oracle(L))
+        assert np.array_equal(g.rho(), o.rho())
+        assert np.array_equal(g.field(), o.field().astype(np.float32))
+        g.close()
 
 
 def test_vacuum_drive(torch_gpu):
