@@ -140,6 +140,97 @@ def cpu_baseline(cfg, step, budget_s=15.0, sample=400_000):
                        "emission / conversion evaluations per particle-step %.3f / %.3f" % (nl, sample - nl, done, el, ev, cv))
 
 
+def bench_batched(plain_value, steps=100, n_tubes=256):
+    """The batched ensemble (uneven tubes in one set of launches), autotuned,
+    timed over graph replays."""
+    import torch
+    from paper_2608_21920_amd import Gap, workloads
+    cfgs = workloads.batched_tubes(n_tubes, seed=1)
+    t0 = time.time()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = Gap(cfgs, stream=s)
+        g.sync()
+        t_init = time.time() - t0
+        tune = g.autotune(16)
+        log("batched: %d tubes built in %.1f s, autotune %s" % (n_tubes, t_init, tune))
+        g.step_graph(steps)          # capture and a first replay
+        g.sync()
+
+        def totals():
+            tot = dict(lep=0, pho=0, emit=0, conv=0, n_lep=0, n_pho=0)
+            for t in range(n_tubes):
+                c = g.counts(t)
+                tot["lep"] += c["lep_steps"]
+                tot["pho"] += c["pho_steps"]
+                tot["emit"] += c["n_emit_eval"]
+                tot["conv"] += c["n_conv_eval"]
+                tot["n_lep"] += c["n_lep"]
+                tot["n_pho"] += c["n_pho"]
+                assert c["err"] == 0, (t, c)
+            return tot
+        c0 = totals()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        g.step_graph(steps)
+        g.step_graph(steps)
+        e1.record(s)
+        g.sync()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        c1 = totals()
+        g.close()
+    n = 2 * steps
+    ps = (c1["lep"] - c0["lep"]) + (c1["pho"] - c0["pho"])
+    alg = (B_LEP * (c1["lep"] - c0["lep"]) + B_EMIT_EVAL * (c1["emit"] - c0["emit"]) +
+           B_PHO * (c1["pho"] - c0["pho"]) + B_CONV_EVAL * (c1["conv"] - c0["conv"]))
+    value = ps / (ms / 1e3)
+    return dict(value=value, unit="particle-steps/s", tubes=n_tubes, steps=n, ms_per_step=ms / n,
+                leptons=c0["n_lep"], photons=c0["n_pho"], graph=True, autotune=tune,
+                hbm_frac_whole_step=alg / (ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                vs_plain=value / plain_value if plain_value else None,
+                config="256 tubes: cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q log-uniform "
+                       "in [0.01, 0.3], ppc uniform in [4, 64] per species, seed 1; uniform e+- start, "
+                       "physical QED")
+
+
+def bench_adjoint(window=2000, ckpt=100):
+    """The differentiable window: forward (checkpoints) + reverse pass, and the
+    same number of plain steps of the same gap."""
+    import torch
+    from paper_2608_21920_amd import Gap, workloads
+    from paper_2608_21920_amd import gap as G
+    cfg = dict(workloads.ADJOINT, flags=G.INJ_FIXED)
+    g = Gap(cfg)
+    g.sync()
+    c0 = g.counts()
+    t0 = time.time()
+    loss = g.window_forward(window, ckpt)[0]
+    t1 = time.time()
+    da, dn = g.backward()
+    t2 = time.time()
+    c1 = g.counts()
+    assert c1["err"] == 0, c1
+    g.close()
+    p = Gap(cfg)
+    p.sync()
+    torch.cuda.synchronize()
+    t3 = time.time()
+    p.step(window)
+    p.sync()
+    t4 = time.time()
+    p.close()
+    ps = (c1["lep_steps"] - c0["lep_steps"]) + (c1["pho_steps"] - c0["pho_steps"])
+    fwd, bwd, plain = (t1 - t0) * 1e3, (t2 - t1) * 1e3, (t4 - t3) * 1e3
+    return dict(value=ps / ((fwd + bwd) / 1e3), unit="particle-steps/s (window forward + backward)",
+                window_steps=window, ckpt_every=ckpt, leptons_start=c0["n_lep"], particle_steps=ps,
+                forward_ms=fwd, backward_ms=bwd, plain_ms=plain, fwd_bwd_over_plain=(fwd + bwd) / plain,
+                loss=loss, dL_dalpha=float(da[0]), dL_dninj=float(dn[0]),
+                config="16384 cells, 122 e- + 122 e+ per cell, rescaled QED (tiny preset), injection 0.1 "
+                       "n_co dx per step, frozen QED, loss = time-averaged <E^2>")
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size, for scaling HBM traffic counters."""
     import torch
@@ -163,6 +254,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time graph replays instead of eager steps")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable window")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % a.gpus,
@@ -239,9 +332,13 @@ def main():
                     for k, v in kern.items()},
         "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if not a.graph else None,
     }
+    g.close()
+    if not a.no_batched:
+        out["batched"] = bench_batched(value)
+    if not a.no_adjoint:
+        out["adjoint"] = bench_adjoint()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, c1["step"])
-    g.close()
     print(json.dumps(out))
 
 

@@ -189,6 +189,19 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);
 
+/* Pick the launch shape of the particle passes and the re-sort interval for
+ * this handle's workload: a coordinate search over the workgroup counts of
+ * the sorted lepton pass, the sorted photon pass and the two tail passes (in
+ * multiples of one resident round, kept multiples of 8 for the XCD-aware
+ * range mapping) and over the re-sort interval (up to the longest the tile
+ * margin allows), each candidate timed with HIP events over `trial_steps`
+ * real steps of the simulation (at least two re-sorts for the interval).
+ * The steps are part of the run: every result is independent of the launch
+ * shape and of the re-sort interval.  chosen (host int32[4]) receives the
+ * lepton, photon and tail workgroup counts and the interval, which the
+ * handle keeps.  Discards a captured graph.  Blocks until done. */
+int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen);
+
 /* Differentiable window (frozen QED).
  *
  * gap_window_forward runs `window_steps` steps from the current state, as

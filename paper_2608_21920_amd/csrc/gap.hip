@@ -228,6 +228,8 @@ struct gap_t {
   double* thresh_l = nullptr;
   double* thresh_p = nullptr;
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
+  int round_lep = 2048, round_pho = 2048, cus = 256;        // one resident round of each pass; CUs
+  int rmax = 64;                                            // longest re-sort interval the tile margin allows
   bool any_periodic = false;
   int sticky = 0;
   // graph: replay is valid from the recorded start state and leaves the end state
@@ -879,6 +881,9 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : std::min(64, rmax));
   }
   g->R = rmin;
+  g->rmax = 1 << 30;
+  for (int t = 0; t < n_tubes; ++t)
+    g->rmax = std::min(g->rmax, std::max(1, (int)std::floor((MARGIN - 2) / g->P[t].cfl) - 1));
   g->n_fb = (int)g->fb_h.size();
   {
     // one resident round of workgroups for the persistent-range passes
@@ -890,6 +895,9 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     g->grid_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
     g->grid_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
     g->grid_tail = std::max(8, cus * 4);
+    g->round_lep = g->grid_lep;
+    g->round_pho = g->grid_pho;
+    g->cus = cus;
   }
   if (g->total_nodes > (1LL << 30)) return GAP_EINVAL;
 
@@ -1056,6 +1064,88 @@ int graph_capture(gap_t* g, int64_t n) {
   if (e != hipSuccess) { g->gexec = nullptr; return GAP_EDEVICE; }
   g->gsteps = n;
   return GAP_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Launch shapes and the re-sort interval change no result (the deposit is in
+// integers and every particle's arithmetic is independent of the grid and of
+// its slot), so candidates are timed on real steps of the simulation.
+int timed_steps(gap_t* g, int64_t n, double* kt, double* wall_ms) {
+  g->ev_marks.clear();
+  g->ev_used = 0;
+  hipEvent_t a = next_event(g), b = next_event(g);
+  if (!a || !b) return GAP_EDEVICE;
+  HIPCHK(hipEventRecord(a, g->s));
+  for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  HIPCHK(hipEventRecord(b, g->s));
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  *wall_ms = ms;
+  for (int i = 0; i < KT_N; ++i) kt[i] = 0.0;
+  for (auto& m : g->ev_marks) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, m.second.first, m.second.second));
+    kt[m.first] += t;
+  }
+  g->ev_marks.clear();
+  g->ev_used = 0;
+  return read_err(g);
+}
+
+int autotune(gap_t* g, int trial, int32_t* chosen) {
+  const bool was = g->timing;
+  g->timing = true;
+  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; g->gsteps = -1; }
+  double kt[KT_N], wall;
+  int e;
+  auto cands = [](int round, int lo) {
+    std::vector<int> v;
+    for (int m : {1, 2, 4, 8}) v.push_back(std::max(lo, (round * m / 2) / 8 * 8));
+    return v;
+  };
+  struct Knob { int* grid; std::vector<int> c; std::vector<int> ids; };
+  Knob knobs[3] = {{&g->grid_lep, cands(g->round_lep, 8), {KT_LEPTONS}},
+                   {&g->grid_pho, cands(g->round_pho, 8), {KT_PHOTONS}},
+                   {&g->grid_tail, {g->cus * 2, g->cus * 4, g->cus * 8, g->cus * 16}, {KT_LEPTAIL, KT_PHOTAIL}}};
+  if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }   // warm-up
+  for (Knob& k : knobs) {
+    double best = 1e300;
+    int arg = *k.grid;
+    for (int c : k.c) {
+      *k.grid = c;
+      if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }
+      double t = 0.0;
+      for (int id : k.ids) t += kt[id];
+      if (t < best) { best = t; arg = c; }
+    }
+    *k.grid = arg;
+  }
+  // re-sort interval: whole steps, each candidate over at least two re-sorts
+  {
+    std::vector<int> rc;
+    for (int r : {g->R / 4, g->R / 2, g->R, g->rmax}) {
+      r = std::max(4, std::min(r, g->rmax));
+      if (std::find(rc.begin(), rc.end(), r) == rc.end()) rc.push_back(r);
+    }
+    double best = 1e300;
+    int arg = g->R;
+    for (int r : rc) {
+      g->R = r;
+      g->since_rb = 0;
+      const int64_t n = std::max<int64_t>(trial, 2 * (int64_t)r);
+      if ((e = timed_steps(g, n, kt, &wall))) { g->timing = was; return e; }
+      const double per = wall / (double)n;
+      if (per < best) { best = per; arg = r; }
+    }
+    g->R = arg;
+  }
+  g->timing = was;
+  chosen[0] = g->grid_lep;
+  chosen[1] = g->grid_pho;
+  chosen[2] = g->grid_tail;
+  chosen[3] = g->R;
+  return g->sticky;
 }
 
 }  // namespace
@@ -1378,6 +1468,13 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     default:
       return GAP_EINVAL;
   }
+}
+
+int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen) {
+  if (!g || trial_steps < 1 || !chosen) return GAP_EINVAL;
+  int e = sync_and_err(g);
+  if (e) return e;
+  return autotune(g, trial_steps, chosen);
 }
 
 int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss) {

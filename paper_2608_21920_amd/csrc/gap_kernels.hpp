@@ -114,20 +114,42 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
   return incl - v;
 }
 
+// Append room of a store during a pass: the sorted-region size and the append
+// limit (neither changes while the particle passes run), read once per
+// workgroup and held wave-uniform.
+struct Room { long long S, L; };
+
+__device__ __forceinline__ long long rfl64(long long v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (long long)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ Room load_room(const Ctl* c) {
+  Room r;
+  r.S = rfl64(c->n_sorted_chunks * CHUNK);
+  r.L = rfl64(c->limit);
+  return r;
+}
+
 // Reserve `n` tail slots of a store (one atomic per wave); returns the first
-// slot index for this lane's records (or -1 with nothing reserved).
-__device__ __forceinline__ long long reserve_tail(Ctl* c, int n, int* dropped) {
+// slot index for this lane's records.  A wave whose reservation runs past the
+// room left before the limit clamps the tail back to that room, so the tail
+// never covers unwritten slots beyond the limit (every reservation made after
+// a clamp starts at the room and is dropped whole).
+__device__ __forceinline__ long long reserve_tail(Ctl* c, const Room& rm, int n, int* dropped) {
   int total;
   int ex = wave_excl_scan(n, &total);
   long long base = 0;
-  if (lane_id() == WAVE - 1 && total > 0) base = (long long)atomicAdd((unsigned long long*)&c->tail, (unsigned long long)total);
+  if (lane_id() == WAVE - 1 && total > 0) {
+    base = (long long)atomicAdd((unsigned long long*)&c->tail, (unsigned long long)total);
+    const long long room = rm.L > rm.S ? rm.L - rm.S : 0;
+    if (base + total > room) atomicMin((unsigned long long*)&c->tail, (unsigned long long)room);
+  }
   base = __shfl(base, WAVE - 1);
-  long long first = c->n_sorted_chunks * CHUNK + base + ex;
-  // appends beyond the limit are dropped (the tail never grows past it)
-  long long lim = c->limit;
+  const long long first = rm.S + base + ex;
+  // appends beyond the limit are dropped
   *dropped = 0;
-  if (n > 0 && first + n > lim) {
-    long long ok = lim - first;
+  if (n > 0 && first + n > rm.L) {
+    long long ok = rm.L - first;
     if (ok < 0) ok = 0;
     *dropped = n - (int)ok;
   }
@@ -137,8 +159,18 @@ __device__ __forceinline__ long long reserve_tail(Ctl* c, int n, int* dropped) {
 // ------------------------------------------------------------------ prologue
 // Surface injection (cold electrons in cell 0 at a deterministic rate) and
 // the snapshots of the tails that this step's passes will process.
+__device__ __forceinline__ void clamp_tail(Ctl* c) {
+  long long room = c->limit - c->n_sorted_chunks * CHUNK;
+  if (room < 0) room = 0;
+  if (c->tail > room) c->tail = room;
+}
+
 __global__ void k_pre(Ctx cx, int n_tubes) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // (appends never leave the tails past the limit; the passes below stay
+  // inside the stores whatever the tails hold)
+  clamp_tail(cx.lc);
+  clamp_tail(cx.pc);
   cx.lc->tail_pre = cx.lc->tail;
   for (int t = 0; t < n_tubes; ++t) {
     Tube& T = cx.tubes[t];
@@ -258,7 +290,8 @@ __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), 
 // own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
 template <bool UNI>
 __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
-                           LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out) {
+                           LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out,
+                           const Room& proom) {
   bool alive;
   KC k;
   if (UNI) {
@@ -372,9 +405,9 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   const int nst = keep ? ncand : 0;
   if (__ballot(nst > 0)) {
     int dropped = 0;
-    const long long first = reserve_tail(cx.pc, nst, &dropped);
+    const long long first = reserve_tail(cx.pc, proom, nst, &dropped);
+    const long long lim = proom.L;
     if (nst > 0) {
-      const long long lim = cx.pc->limit;
       float au = fabsf(upk);
       const float dir = upk >= 0.0f ? 1.0f : -1.0f;
       const float aw = fabsf(w);
@@ -470,6 +503,7 @@ __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long
 // pushed.  The chunk's tile constants sit in scalar registers; gather and
 // deposit go through an LDS window of the tile.
 __global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
+  const Room proom = load_room(cx.pc);
   __shared__ long long s_rho[WIN + 2];
   __shared__ float s_eb[WIN + 2];
   __shared__ long long s_cnt[8];
@@ -507,7 +541,7 @@ __global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float uo;
-      lepton_one<true>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo);
+      lepton_one<true>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
       w = make_float4(w.y, w.z, w.w, w.x);
       p = make_uint4(p.y, p.z, p.w, po);
       u = make_float4(u.y, u.z, u.w, uo);
@@ -523,6 +557,7 @@ __global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
 // Lepton pass over the tail (particles appended since the last re-sort):
 // one slot per thread, each lane with its own tile; global gather/deposit.
 __global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
+  const Room proom = load_room(cx.pc);
   LocalCounts lcn;
   lcn.clear();
   const long long nsc = cx.lc->n_sorted_chunks;
@@ -537,7 +572,7 @@ __global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
     const float w = cx.L.w[slot];
     const uint32_t pos = cx.L.pos[slot];
     const float u = cx.L.u[slot];
-    lepton_one<false>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr);
+    lepton_one<false>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
   }
 }
 
@@ -556,7 +591,7 @@ __device__ __forceinline__ float sin_small(float a) {
 // draw is needed and none is made.
 template <bool UNI>
 __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, LocalCounts& lcn, float x, uint32_t pos,
-                           int32_t n0, uint32_t* pos_out, float* x_out) {
+                           int32_t n0, uint32_t* pos_out, float* x_out, const Room& lroom) {
   bool alive;
   KC k;
   if (UNI) {
@@ -612,9 +647,9 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   // pair births: e- and e+ at the photon position, gamma = x/2 each, along the photon
   if (__ballot(conv)) {
     int dropped = 0;
-    const long long first = reserve_tail(cx.lc, conv ? 2 : 0, &dropped);
+    const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
+    const long long lim = lroom.L;
     if (conv) {
-      const long long lim = cx.lc->limit;
       const float gm = 0.5f * fabsf(x);
       const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
       for (int e = 0; e < 2; ++e) {
@@ -659,6 +694,7 @@ __device__ __forceinline__ Pho4 pho_load4(const Ctx& cx, long long c) {
 }
 
 __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
+  const Room lroom = load_room(cx.lc);
   const long long nsc = cx.pc->n_sorted_chunks;
   const int G = gridDim.x, bx = blockIdx.x;
   const int r = (bx & 7) * (G >> 3) + (bx >> 3);
@@ -690,7 +726,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float xo;
-      photon_one<true>(cx, cur.slot0 + j, held, kc, lcn, x.x, p.x, n0.x, &po, &xo);
+      photon_one<true>(cx, cur.slot0 + j, held, kc, lcn, x.x, p.x, n0.x, &po, &xo, lroom);
       xchg |= xo != x.x;
       x = make_float4(x.y, x.z, x.w, xo);
       p = make_uint4(p.y, p.z, p.w, po);
@@ -704,6 +740,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 }
 
 __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
+  const Room lroom = load_room(cx.lc);
   LocalCounts lcn;
   lcn.clear();
   const long long nsc = cx.pc->n_sorted_chunks;
@@ -718,7 +755,7 @@ __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
     const float x = cx.P.x[slot];
     const uint32_t pos = cx.P.pos[slot];
     const int32_t n0 = cx.P.n0[slot];
-    photon_one<false>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr);
+    photon_one<false>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr, lroom);
   }
 }
 

@@ -103,6 +103,8 @@ def load_library():
     lib.gap_free.argtypes = [C.c_void_p]
     lib.gap_strerror.restype = C.c_char_p
     lib.gap_strerror.argtypes = [C.c_int]
+    lib.gap_autotune.restype = C.c_int
+    lib.gap_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     lib.gap_window_forward.restype = C.c_int
     lib.gap_window_forward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
     lib.gap_backward.restype = C.c_int
@@ -257,6 +259,13 @@ class Gap:
     def set_drive(self, alpha: float, inj_weight: float, tube: int = 0):
         buf = np.array([alpha, inj_weight], np.float64)
         _check(self.lib.gap_set_state(self.h, STATE_DRIVE, int(tube), buf.ctypes.data, buf.nbytes), "set_drive")
+
+    def autotune(self, trial_steps: int = 32) -> dict:
+        """Tune the launch shapes and the re-sort interval on real steps
+        (they advance the simulation; results do not depend on the choice)."""
+        c = np.zeros(4, np.int32)
+        _check(self.lib.gap_autotune(self.h, int(trial_steps), c.ctypes.data), "gap_autotune")
+        return dict(grid_leptons=int(c[0]), grid_photons=int(c[1]), grid_tails=int(c[2]), resort_every=int(c[3]))
 
     # -- differentiable window (frozen QED)
     def window_forward(self, steps: int, ckpt_every: int = 100) -> np.ndarray:

@@ -38,9 +38,14 @@ FULL = dict(BASE, n_cells=262144, init_kind=0, ppc_init=16, alpha=1.5, b=0.2, r_
             merge=True)
 
 # Differentiable window: 16384 cells, 122 e- + 122 e+ per cell (4.0e6
-# leptons), rescaled QED as TINY, injection on, 2000 steps, checkpoints / 100.
+# leptons), injection on, 2000 steps, checkpoints every 100.  The QED is
+# rescaled (lambda~ x 1e3, R~ x 1e-2: lambda~/R~ = 1e5 times the physical
+# value) so that emission, photon transport and conversion all occur inside
+# the window while the population stays near 4e6 (about 7.8e6 emissions,
+# 5.7e6 photons and 4e5 conversions over the 2000 steps; the tiny gap's
+# stronger rescale makes this 16384-cell box run away, x27 in 200 steps).
 ADJOINT = dict(BASE, n_cells=16384, init_kind=1, ppc_init=122, ppc_ref=16, alpha=1.5, b=0.1,
-               r_curv_cm=1e7, r_curv_scale=1.4e-5, lambda_c_scale=1.7e5, inj_rate=0.1, seed=0,
+               r_curv_cm=1e7, r_curv_scale=1e-2, lambda_c_scale=1e3, inj_rate=0.1, seed=0,
                steps=2000, ckpt_every=100, cap_leptons=16_000_000, cap_photons=16_000_000)
 
 

@@ -1,0 +1,76 @@
+"""Batched form: an ensemble of uneven tubes in one set of launches, captured
+in a graph, with launch shapes from the autotuner; every tube's state is
+bitwise that of a plain single-tube run."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2608_21920_amd import Gap, workloads
+
+from gpu_util import by_id, gpu_leptons_as_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _same(ga, ta, gb, tb):
+    A, B = by_id(gpu_leptons_as_oracle(ga.leptons(ta))), by_id(gpu_leptons_as_oracle(gb.leptons(tb)))
+    for k in ("cell", "xi", "u", "w", "id"):
+        assert np.array_equal(A[k], B[k]), k
+    assert np.array_equal(ga.field(ta), gb.field(tb))
+    assert ga.es(ta) == gb.es(tb)
+
+
+def test_autotune_changes_no_result(torch_gpu):
+    _say("case: autotune on the tiny gap")
+    cfg = dict(workloads.TINY, n_cells=512)
+    a = Gap(cfg)
+    a.step(40)
+    ch = a.autotune(8)
+    _say("  chosen", ch)
+    assert ch["grid_leptons"] % 8 == 0 and ch["grid_photons"] % 8 == 0 and ch["resort_every"] >= 4
+    n = a.counts()["step"]
+    a.step(30)
+    b = Gap(cfg)
+    b.step(n + 30)
+    _same(a, 0, b, 0)
+    assert a.counts()["err"] == 0
+    a.close()
+    b.close()
+
+
+def test_ensemble_graph_equals_single_tubes(torch_gpu):
+    import torch
+    _say("case: 12-tube ensemble from the batched recipe, graph replays vs single tubes")
+    cfgs = [dict(c, n_cells=c["n_cells"] // 8, cap_leptons=c["cap_leptons"] // 8, cap_photons=c["cap_photons"] // 8)
+            for c in workloads.batched_tubes(12, seed=1)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        gb = Gap(cfgs, stream=s)
+        gb.autotune(4)
+        n0 = gb.counts(0)["step"]
+        for _ in range(3):
+            gb.step_graph(20)
+            gb.sync()
+        steps = gb.counts(0)["step"]
+        assert steps == n0 + 60
+        for t in (0, 5, 11):
+            g1 = Gap(cfgs[t], stream=s)
+            g1.step(steps)
+            _same(gb, t, g1, 0)
+            g1.close()
+        assert gb.counts(0)["err"] == 0
+        gb.close()

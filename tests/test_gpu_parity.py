@@ -247,3 +247,21 @@ def test_graph_replay_equals_eager(torch_gpu):
         assert np.array_equal(ga.field(), gb.field())
         ga.close()
         gb.close()
+
+
+def test_store_overflow_reports_ecap(torch_gpu):
+    # a photon store far too small for the cascade: births past the cap are
+    # dropped, the tail stays inside the store, the step reports GAP_ECAP
+    _say("case: photon store overflow (cap 3000)")
+    cfg = dict(TINY, n_cells=512, cap_photons=3000)
+    g = Gap(cfg)
+    with pytest.raises(G.GapError) as ei:
+        for _ in range(6):
+            g.step(50)
+            g.sync()
+    assert ei.value.code == -3
+    P = g.photons()
+    c = g.counts()
+    assert c["n_dropped"] > 0
+    assert P.size <= 3000 + 2 * 4 * 1024 + 1024
+    g.close()
