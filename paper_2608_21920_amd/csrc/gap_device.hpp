@@ -105,12 +105,23 @@ struct PhoBuf { uint32_t* pos; float* x; float* w; int32_t* n0; uint64_t* id; };
 // xors in the key, which is bumped by a Weyl increment between rounds.
 struct u4 { uint32_t a, b, c, d; };
 
+// Two equivalent forms of the same rounds: WIDE takes each product with one
+// 32x32 -> 64 multiply, otherwise with separate low and high multiplies (the
+// lepton pass keeps the latter: it needs fewer registers there).
+template <bool WIDE = false>
 __device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-    uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-    uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+    uint32_t hi0, lo0, hi1, lo1;
+    if (WIDE) {
+      const uint64_t p0 = (uint64_t)m0 * c0, p1 = (uint64_t)m1 * c2;
+      hi0 = (uint32_t)(p0 >> 32); lo0 = (uint32_t)p0;
+      hi1 = (uint32_t)(p1 >> 32); lo1 = (uint32_t)p1;
+    } else {
+      hi0 = __umulhi(m0, c0); lo0 = m0 * c0;
+      hi1 = __umulhi(m1, c2); lo1 = m1 * c2;
+    }
     uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
@@ -119,9 +130,10 @@ __device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 // counter = (id lo, id hi, step, tag << 16 | sub), key = seed
+template <bool WIDE = false>
 __device__ __forceinline__ u4 draw(uint64_t seed, uint64_t id, int64_t step, uint32_t tag, uint32_t sub) {
-  return philox((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, (tag << 16) | (sub & 0xFFFFu),
-                (uint32_t)seed, (uint32_t)(seed >> 32));
+  return philox<WIDE>((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, (tag << 16) | (sub & 0xFFFFu),
+                      (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 enum : uint32_t { T_INIT = 1, T_EMIT = 2, T_CONV = 3, T_INJ = 4, T_MERGE = 5, T_CHILD = 6 };

@@ -631,7 +631,7 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
       if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
         eval = true;
         id = cx.P.id[slot];
-        u4 r = draw(k.seed, id, step, T_CONV, 0);
+        u4 r = draw<true>(k.seed, id, step, T_CONV, 0);
         conv = bern(r.a, p);
         if (conv) w = cx.P.w[slot];
       }
@@ -693,6 +693,92 @@ __device__ __forceinline__ Pho4 pho_load4(const Ctx& cx, long long c) {
   return r;
 }
 
+// Sorted photon pass, first half for one photon: free streaming, exit, and
+// the conversion probability.  Gives the new position, the energy (0 once
+// the photon has left) and whether a conversion draw is due.
+__device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x, uint32_t pos, int32_t n0,
+                                            LocalCounts& lcn, uint32_t* pos_out, float* x_out, float* p_out,
+                                            bool* eval_out) {
+  const bool alive = x != 0.0f;
+  const uint32_t flags = (uint32_t)k.flags;
+  const bool per = (flags & F_PERIODIC) != 0;
+  const long long np = (long long)pos + (x >= 0.0f ? k.dpho : -k.dpho);
+  const int noff = (int)(np >> FRAC);
+  const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
+  const int ncell = k.base + noff;
+  bool dead = false;
+  if (alive && (np < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
+  const int ncg = per ? wrap_cell(ncell, k.N) : ncell;
+  bool exited = false;
+  if (alive && !dead) {
+    if ((!per && (ncell < 0 || ncell >= k.N)) || (((int64_t)ncg << FRAC) + nfrac >= k.hfix)) { exited = true; dead = true; }
+  }
+  bool eval = false;
+  float p = 0.0f;
+  if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
+    const float sp = fabsf(sin_small((float)(k.step + 1 - (int64_t)n0) * k.dt * k.inv_rc));
+    const float chi = fabsf(x) * k.b * sp;
+    if (chi > k.chi_skip) {
+      p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
+      eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
+    }
+  }
+  *pos_out = (uint32_t)np;
+  *x_out = dead ? 0.0f : x;
+  *p_out = p;
+  *eval_out = eval;
+  lcn.v[0] += alive ? 1 : 0;
+  lcn.v[1] += eval ? 1 : 0;
+  lcn.v[4] += exited ? 1 : 0;
+}
+
+// Second half for a photon that draws: the conversion, and the pair (e- and
+// e+ at the photon position, gamma = x/2 each, along the photon).  Every
+// lane of the wave calls it (act = false: nothing to do) so that the births
+// can be reserved with one atomic per wave.
+__device__ __forceinline__ bool photon_convert(const Ctx& cx, const KC& k, const Room& lroom, LocalCounts& lcn,
+                                               bool act, uint32_t slot, uint32_t np, float x, float p, int tile) {
+  bool conv = false;
+  uint64_t id = 0;
+  float w = 0.0f;
+  if (act) {
+    id = cx.P.id[slot];
+    const u4 r = draw<true>(k.seed, id, k.step, T_CONV, 0);
+    conv = bern(r.a, p);
+    if (conv) w = cx.P.w[slot];
+  }
+  if (__ballot(conv)) {
+    int dropped = 0;
+    const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
+    if (conv) {
+      const float dir = x >= 0.0f ? 1.0f : -1.0f;
+      const float gm = 0.5f * fabsf(x);
+      const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+      for (int e = 0; e < 2; ++e) {
+        const long long sl = first + e;
+        if (sl < lroom.L) {
+          const uint32_t s32 = (uint32_t)sl;
+          cx.L.pos[s32] = np;
+          cx.L.u[s32] = up;
+          cx.L.w[s32] = e == 0 ? -w : w;
+          cx.L.id[s32] = child_id(k.seed, id, k.step, (uint32_t)e);
+          cx.ltt[s32] = tile;
+        }
+      }
+    }
+    if (dropped) atomicOr(cx.err, E_CAP);
+    lcn.v[3] += dropped;
+  }
+  lcn.v[2] += conv ? 1 : 0;
+  return conv;
+}
+
+// Photon pass over the sorted region (ranges of chunks per workgroup, XCD-
+// aware, VEC slots per thread, next chunk prefetched).  Only a tenth or so
+// of the photons draw a conversion in a step, scattered over the lanes, so
+// each chunk runs in three phases: every thread moves its photons and queues
+// those that draw in LDS; the workgroup then runs the draws (and the pair
+// births) over the compacted queue; finally each thread stores its records.
 __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
   const Room lroom = load_room(cx.lc);
   const long long nsc = cx.pc->n_sorted_chunks;
@@ -700,6 +786,13 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
   const int r = (bx & 7) * (G >> 3) + (bx >> 3);
   const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
   __shared__ long long s_cnt[8];
+  __shared__ uint32_t q_slot[CHUNK];
+  __shared__ uint32_t q_pos[CHUNK];
+  __shared__ float q_x[CHUNK];
+  __shared__ float q_p[CHUNK];
+  __shared__ uint16_t q_own[CHUNK];     // thread * VEC + j of the photon's owner
+  __shared__ __align__(4) uint8_t s_conv[CHUNK];
+  __shared__ int q_n;
   LocalCounts lcn;
   lcn.clear();
   int ctube = -1;
@@ -718,19 +811,55 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
         ctube = kc.tube;
       }
     }
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
     float4 x = cur.x;
+    bool xchg = false;
     uint4 p = cur.pos;
     int4 n0 = cur.n0;
-    bool xchg = false;
 #pragma unroll 1
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
-      float xo;
-      photon_one<true>(cx, cur.slot0 + j, held, kc, lcn, x.x, p.x, n0.x, &po, &xo, lroom);
+      float xo, pr;
+      bool ev;
+      photon_move(cx, kc, x.x, p.x, n0.x, lcn, &po, &xo, &pr, &ev);
       xchg |= xo != x.x;
+      const uint64_t m = __ballot(ev);
+      int base = 0;
+      if (lane_id() == 0 && m) base = atomicAdd(&q_n, (int)__popcll(m));
+      base = __shfl(base, 0);
+      const int own = (int)threadIdx.x * VEC + j;
+      if (ev) {
+        const int i = base + rank_in(m);
+        q_slot[i] = cur.slot0 + j;
+        q_pos[i] = po;
+        q_x[i] = x.x;
+        q_p[i] = pr;
+        q_own[i] = (uint16_t)own;
+      }
+      s_conv[own] = 0;
       x = make_float4(x.y, x.z, x.w, xo);
       p = make_uint4(p.y, p.z, p.w, po);
       n0 = make_int4(n0.y, n0.z, n0.w, n0.x);
+    }
+    __syncthreads();
+    const int nq = q_n;
+    for (int i0 = 0; i0 < nq; i0 += TPB) {
+      const int i = i0 + (int)threadIdx.x;
+      const bool act = i < nq;
+      uint32_t qs = 0, qp = 0;
+      float qx = 0.0f, qpr = 0.0f;
+      if (act) { qs = q_slot[i]; qp = q_pos[i]; qx = q_x[i]; qpr = q_p[i]; }
+      if (photon_convert(cx, kc, lroom, lcn, act, qs, qp, qx, qpr, held)) s_conv[q_own[i]] = 1;
+    }
+    __syncthreads();
+    const uint32_t cv = *reinterpret_cast<const uint32_t*>(s_conv + (int)threadIdx.x * VEC);
+    if (cv) {
+      if (cv & 0xFFu) x.x = 0.0f;
+      if (cv & 0xFF00u) x.y = 0.0f;
+      if (cv & 0xFF0000u) x.z = 0.0f;
+      if (cv & 0xFF000000u) x.w = 0.0f;
+      xchg = true;
     }
     *reinterpret_cast<uint4*>(cx.P.pos + cur.slot0) = p;
     if (xchg) *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;   // only when a photon died
