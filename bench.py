@@ -8,9 +8,13 @@ stores hold at least --grow-to particles.  Then --warmup untimed steps and
 --steps timed steps; inputs are resident in HBM throughout.
 
 Prints one JSON line.  `value` is particle-steps/s (leptons + photons
-advanced by one step), `roofline` is the dominant kernel's algorithmic HBM
-bytes per launch over its average launch time (HIP events on the library's
-stream), `cpu_baseline` is the FP64 oracle on a bounded sample of the same
+advanced by one step) over the timed steps, which run without any
+instrumentation.  Right after them the same number of steps runs again with a
+HIP event pair around every kernel group (on the library's stream): that pass
+gives the per-kernel average launch times.  `roofline` is the dominant
+kernel's algorithmic HBM bytes per launch over its average launch time;
+`step_roofline` is the whole step's algorithmic bytes over the timed step
+time.  `cpu_baseline` is the FP64 oracle on a bounded sample of the same
 grown state, on this host.
 """
 from __future__ import annotations
@@ -30,11 +34,15 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("gap_device.hpp", "gap_kernels.hpp")   # code of the two particle kernels
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_leptons_k_photons_production.txt")
-# algorithmic bytes per unit of work: a lepton-step reads
-# position, momentum, weight and writes position, momentum; an emission
-# evaluation also reads the 8-byte id.  Photon-step reads position, energy,
-# birth step and writes position; a conversion evaluation also reads id, weight.
-B_LEP, B_EMIT_EVAL, B_PHO, B_CONV_EVAL = 20, 8, 16, 12
+# algorithmic bytes per unit of work: a lepton-step reads position, momentum
+# and weight and writes position and momentum (20 B); a lepton-step that
+# evaluates emission also reads the 8-byte id.  A photon-step reads position,
+# energy, weight, birth step and id and writes position (28 B).
+B_LEP, B_EMIT_EVAL, B_PHO = 20, 8, 28
+# bytes the photon kernel must move at least: position, energy and birth step
+# read and position written for every photon (16 B); id and weight only for
+# the photons that draw a conversion (12 B)
+B_PHO_MIN, B_CONV_EVAL_MIN = 16, 12
 
 
 def log(*a):
@@ -183,8 +191,7 @@ def bench_batched(plain_value, steps=100, n_tubes=256):
         g.close()
     n = 2 * steps
     ps = (c1["lep"] - c0["lep"]) + (c1["pho"] - c0["pho"])
-    alg = (B_LEP * (c1["lep"] - c0["lep"]) + B_EMIT_EVAL * (c1["emit"] - c0["emit"]) +
-           B_PHO * (c1["pho"] - c0["pho"]) + B_CONV_EVAL * (c1["conv"] - c0["conv"]))
+    alg = B_LEP * (c1["lep"] - c0["lep"]) + B_EMIT_EVAL * (c1["emit"] - c0["emit"]) + B_PHO * (c1["pho"] - c0["pho"])
     value = ps / (ms / 1e3)
     return dict(value=value, unit="particle-steps/s", tubes=n_tubes, steps=n, ms_per_step=ms / n,
                 leptons=c0["n_lep"], photons=c0["n_pho"], graph=True, autotune=tune,
@@ -273,49 +280,70 @@ def main():
     g.step(a.warmup)
     g.sync()
 
-    c0 = g.counts()
-    g.set_timing(not a.graph)
     s = g.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     region = ProfilerRegion()
-    torch.cuda.synchronize()
-    region.resume()
-    e0.record(s)
-    if a.graph:
-        g.step_graph(a.steps)
-    else:
-        g.step(a.steps)
-    e1.record(s)
-    g.sync()
-    torch.cuda.synchronize()
-    region.pause()
-    ms = e0.elapsed_time(e1)
-    tim = g.timing()
-    g.set_timing(False)
-    c1 = g.counts()
-    assert c1["err"] == 0, c1
 
-    d = {k: c1[k] - c0[k] for k in c1}
-    psteps = d["lep_steps"] + d["pho_steps"]
+    def run(steps, timing):
+        c_a = g.counts()
+        g.set_timing(timing)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        if not timing:
+            region.resume()
+        e0.record(s)
+        if a.graph:
+            g.step_graph(steps)
+        else:
+            g.step(steps)
+        e1.record(s)
+        g.sync()
+        torch.cuda.synchronize()
+        if not timing:
+            region.pause()
+        tim = g.timing() if timing else None
+        g.set_timing(False)
+        c_b = g.counts()
+        assert c_b["err"] == 0, c_b
+        return e0.elapsed_time(e1), {k: c_b[k] - c_a[k] for k in c_b}, tim, c_a
+
+    # timed steps (no instrumentation), then the same number with kernel events
+    ms, dA, _, c0 = run(a.steps, False)
+    c1 = g.counts()
+    psteps = dA["lep_steps"] + dA["pho_steps"]
     value = psteps / (ms / 1e3)
-    # algorithmic bytes of the sorted-region kernels and of the tail kernels
-    bytes_lep = B_LEP * (d["lep_steps"] - d["lep_steps_tail"]) + B_EMIT_EVAL * (d["n_emit_eval"] - d["emit_eval_tail"])
-    bytes_pho = B_PHO * (d["pho_steps"] - d["pho_steps_tail"]) + B_CONV_EVAL * (d["n_conv_eval"] - d["conv_eval_tail"])
-    bytes_lep_t = B_LEP * d["lep_steps_tail"] + B_EMIT_EVAL * d["emit_eval_tail"]
-    bytes_pho_t = B_PHO * d["pho_steps_tail"] + B_CONV_EVAL * d["conv_eval_tail"]
-    kern = {}
+    step_bytes = B_LEP * dA["lep_steps"] + B_EMIT_EVAL * dA["n_emit_eval"] + B_PHO * dA["pho_steps"]
+    step_roof = dict(bound="hbm", achieved=step_bytes / (ms / 1e3) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                     frac=step_bytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, bytes_per_step=step_bytes / a.steps)
+    kern, roof, tim, ms_i = {}, None, None, None
     if not a.graph:
-        for name, byt in (("leptons", bytes_lep), ("photons", bytes_pho), ("leptons_tail", bytes_lep_t),
-                          ("photons_tail", bytes_pho_t)):
+        ms_i, d, tim, _ = run(a.steps, True)
+        # algorithmic bytes of the sorted-region kernels and of the tail kernels
+        units = dict(leptons=(d["lep_steps"] - d["lep_steps_tail"], d["n_emit_eval"] - d["emit_eval_tail"]),
+                     photons=(d["pho_steps"] - d["pho_steps_tail"], d["n_conv_eval"] - d["conv_eval_tail"]),
+                     leptons_tail=(d["lep_steps_tail"], d["emit_eval_tail"]),
+                     photons_tail=(d["pho_steps_tail"], d["conv_eval_tail"]))
+        for name, (n_steps, n_eval) in units.items():
+            lep = name.startswith("leptons")
+            byt = B_LEP * n_steps + B_EMIT_EVAL * n_eval if lep else B_PHO * n_steps
+            byt_min = byt if lep else B_PHO_MIN * n_steps + B_CONV_EVAL_MIN * n_eval
             n, tms = tim[name]
-            kern[name] = dict(launches=n, avg_ms=tms / max(n, 1), bytes_per_launch=byt / max(n, 1),
-                              gbs=(byt / max(n, 1)) / (tms / max(n, 1) / 1e3) / 1e9 if tms > 0 else None)
-        dom = max(("leptons", "photons"), key=lambda k: tim[k][1])
+            if name == "photons":
+                # the sorted photon pass is two launches: streaming, then the
+                # conversion draws of the photons it queued
+                tms += tim["conversions"][1]
+            per = tms / max(n, 1)
+            kern[name] = dict(launches=n, avg_ms=per, bytes_per_launch=byt / max(n, 1),
+                              gbs=(byt / max(n, 1)) / (per / 1e3) / 1e9 if tms > 0 else None,
+                              min_bytes_per_launch=byt_min / max(n, 1))
+        dom = max(("leptons", "photons"), key=lambda k: kern[k]["avg_ms"])
+        kname = {"leptons": ("k_leptons",), "photons": ("k_photons", "k_conversions")}[dom]
+        tr = [measured_traffic(k) for k in kname]
         roof = dict(bound="hbm", achieved=kern[dom]["gbs"], peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=kern[dom]["gbs"] / PEAK_HBM_GBS, traffic=measured_traffic("k_" + dom), kernel="k_" + dom,
-                    bytes_per_launch=kern[dom]["bytes_per_launch"], avg_launch_ms=kern[dom]["avg_ms"])
-    else:
-        roof = None
+                    frac=kern[dom]["gbs"] / PEAK_HBM_GBS, traffic=None if None in tr else sum(tr),
+                    kernel="+".join(kname), bytes_per_launch=kern[dom]["bytes_per_launch"],
+                    avg_launch_ms=kern[dom]["avg_ms"])
+        kern["conversions"] = dict(launches=tim["conversions"][0],
+                                   avg_ms=tim["conversions"][1] / max(tim["conversions"][0], 1))
     out = {
         "metric": "particle-steps/s (leptons + photons), % of HBM roofline of the dominant kernel",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -325,12 +353,14 @@ def main():
                                "injection 0.1 n_co dx/step, caps 5e7 per species",
                    "n_cells": cfg["n_cells"], "step_at_start": c0["step"], "leptons": c0["n_lep"],
                    "photons": c0["n_pho"], "parallelism": "single GPU", "graph": a.graph,
-                   "emit_eval_per_particle_step": round(d["n_emit_eval"] / max(1, psteps), 4),
-                   "conv_eval_per_particle_step": round(d["n_conv_eval"] / max(1, psteps), 4)},
+                   "emit_eval_per_particle_step": round(dA["n_emit_eval"] / max(1, psteps), 4),
+                   "conv_eval_per_particle_step": round(dA["n_conv_eval"] / max(1, psteps), 4)},
         "roofline": roof,
+        "step_roofline": step_roof,
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
-        "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if not a.graph else None,
+        "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if tim else None,
+        "ms_per_step_with_kernel_events": ms_i / a.steps if ms_i else None,
     }
     g.close()
     if not a.no_batched:

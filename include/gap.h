@@ -137,10 +137,10 @@ int gap_sync(gap_t* g);
                                      int32 pad, uint64 id}                                 */
 #define GAP_DIAG_NODE_E   6  /* float[N+1]: node field used by the gather                   */
 #define GAP_DIAG_DERIVED  7  /* double[8]: d_cm, lambda~, R~, dt, H, w0, s_co, N            */
-#define GAP_DIAG_TIMING   8  /* double[14]: (launches, summed ms) of the lepton pass, photon
-                                pass, field, re-sort, prologue, lepton tail pass and photon
-                                tail pass since timing was enabled or last read (tube
-                                ignored; resets the record)                                 */
+#define GAP_DIAG_TIMING   8  /* double[16]: (launches, summed ms) of the lepton pass, photon
+                                pass, field, re-sort, prologue, lepton tail pass, photon
+                                tail pass and conversion draws since timing was enabled or
+                                last read (tube ignored; resets the record)                 */
 
 /* indices of GAP_DIAG_COUNTS */
 #define GAP_C_LEPTONS     0   /* live leptons                      */

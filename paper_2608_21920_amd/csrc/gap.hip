@@ -227,6 +227,15 @@ struct gap_t {
   uint32_t* merge_start = nullptr;
   double* thresh_l = nullptr;
   double* thresh_p = nullptr;
+  double tmin_l = 0.0, tmin_p = 0.0;   // smallest tube threshold of each store
+  // conversion queue of the sorted photon pass (one entry per photon slot at
+  // most) and its per-workgroup entry counts
+  uint32_t* pq_slot = nullptr;
+  float* pq_p = nullptr;
+  int32_t* pq_tile = nullptr;
+  int32_t* pq_tube = nullptr;
+  int* pq_count = nullptr;
+  int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
   int round_lep = 2048, round_pho = 2048, cus = 256;        // one resident round of each pass; CUs
   int rmax = 64;                                            // longest re-sort interval the tile margin allows
@@ -336,6 +345,11 @@ Ctx make_ctx(gap_t* g) {
   c.tab = g->tab;
   c.err = g->err;
   c.shard = g->shard;
+  c.pq_slot = g->pq_slot;
+  c.pq_p = g->pq_p;
+  c.pq_tile = g->pq_tile;
+  c.pq_tube = g->pq_tube;
+  c.pq_count = g->pq_count;
   return c;
 }
 
@@ -349,7 +363,8 @@ hipEvent_t next_event(gap_t* g) {
 }
 
 // kernel ids of the timing diagnostic
-enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_LEPTAIL = 5, KT_PHOTAIL = 6, KT_N = 7 };
+enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_LEPTAIL = 5, KT_PHOTAIL = 6,
+       KT_CONV = 7, KT_N = 8 };
 
 struct Timer {
   gap_t* g; int id; hipEvent_t a = nullptr, b = nullptr;
@@ -433,11 +448,13 @@ void rebuild_field(gap_t* g) {
 }
 
 template <class B>
-void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh) {
+void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, double thresh_min) {
   const int t1 = (g->n_tubes + 255) / 256;
+  k_merge_gate<<<1, 64, 0, g->s>>>(st.ctl, thresh_min, sb.gate);
   k_fill_i64<<<std::max(1, t1), 256, 0, g->s>>>(g->live, g->n_tubes, 0);
-  k_count_live<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->live, g->n_tubes);
-  k_merge_flags<<<t1, 256, 0, g->s>>>(g->live, thresh, sb.flags, g->n_tubes);
+  k_count_live<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->live, g->n_tubes,
+                                           sb.gate);
+  k_merge_flags<<<t1, 256, 0, g->s>>>(g->live, thresh, sb.flags, g->n_tubes, sb.gate);
   k_fill_i64<<<1, 64, 0, g->s>>>(sb.n, 1, 0);
   k_merge_keys<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->tubes, sb);
   int src = 0;
@@ -454,8 +471,8 @@ void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh) 
 }
 
 void merge_all(gap_t* g) {
-  merge_store<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->sort_l, g->thresh_l);
-  merge_store<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->sort_p, g->thresh_p);
+  merge_store<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->sort_l, g->thresh_l, g->tmin_l);
+  merge_store<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->sort_p, g->thresh_p, g->tmin_p);
   // merged-away records are dead slots until the next scheduled re-sort
 }
 
@@ -492,6 +509,7 @@ void enqueue_window_step(gap_t* g) {
   k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
   k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
+  k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx);
   k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   field_pass(g, 0);
   ++g->host_step;
@@ -675,6 +693,7 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
       k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
       k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
       k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
+      k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx);
       k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
       field_pass(g, 0);
       ++g->host_step;
@@ -748,6 +767,7 @@ void enqueue_step(gap_t* g) {
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_PHOTONS); k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_CONV); k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
   if (++g->since_rb >= g->R) {
@@ -921,6 +941,13 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   int e;
   if ((e = alloc_store(g, g->lep, cap_l, false))) return e;
   if ((e = alloc_store(g, g->pho, cap_p, true))) return e;
+  g->pq_groups = 8 * g->round_pho + 64;   // the autotuner tries grids up to 4 resident rounds
+  g->pq_slot = (uint32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
+  g->pq_p = (float*)dalloc(g, (size_t)g->pho.capacity * 4);
+  g->pq_tile = (int32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
+  g->pq_tube = (int32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
+  g->pq_count = (int*)dalloc(g, (size_t)g->pq_groups * 4);
+  if (!g->pq_slot || !g->pq_p || !g->pq_tile || !g->pq_tube || !g->pq_count) return GAP_ENOMEM;
   for (int t = 0; t < n_tubes; ++t) if (g->P[t].flags & GAP_MERGE_ON) g->merge_on = true;
   if (g->merge_on) {
     g->merge_every = std::max(1, g->P[0].merge_every);
@@ -936,8 +963,9 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
       }
       sb.bhist = (uint32_t*)dalloc(g, (size_t)256 * sb.max_blocks * 4);
       sb.flags = (uint32_t*)dalloc(g, (size_t)n_tubes * 4);
+      sb.gate = (uint32_t*)dalloc(g, 4);
       sb.n = (long long*)dalloc(g, 8);
-      if (!sb.bhist || !sb.flags || !sb.n) return GAP_ENOMEM;
+      if (!sb.bhist || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
     }
     g->merge_start = (uint32_t*)dalloc(g, (size_t)std::max(g->lep.capacity, g->pho.capacity) * 4);
     g->thresh_l = (double*)dalloc(g, sizeof(double) * n_tubes);
@@ -949,6 +977,8 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
       tl[t] = on ? g->P[t].merge_frac * (double)g->P[t].cap_leptons : 1e300;
       tp[t] = on ? g->P[t].merge_frac * (double)g->P[t].cap_photons : 1e300;
     }
+    g->tmin_l = *std::min_element(tl.begin(), tl.end());
+    g->tmin_p = *std::min_element(tp.begin(), tp.end());
     HIPCHK(hipStreamSynchronize(g->s));
     HIPCHK(hipMemcpy(g->thresh_l, tl.data(), sizeof(double) * n_tubes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(g->thresh_p, tp.data(), sizeof(double) * n_tubes, hipMemcpyHostToDevice));
@@ -1106,7 +1136,7 @@ int autotune(gap_t* g, int trial, int32_t* chosen) {
   };
   struct Knob { int* grid; std::vector<int> c; std::vector<int> ids; };
   Knob knobs[3] = {{&g->grid_lep, cands(g->round_lep, 8), {KT_LEPTONS}},
-                   {&g->grid_pho, cands(g->round_pho, 8), {KT_PHOTONS}},
+                   {&g->grid_pho, cands(g->round_pho, 8), {KT_PHOTONS, KT_CONV}},
                    {&g->grid_tail, {g->cus * 2, g->cus * 4, g->cus * 8, g->cus * 16}, {KT_LEPTAIL, KT_PHOTAIL}}};
   if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }   // warm-up
   for (Knob& k : knobs) {

@@ -162,7 +162,8 @@ __device__ __forceinline__ float t_syn(float chi) {
 // 0.23 exp(-8/(3 chi)) (1 + 0.22 chi)^(-1/3)
 __device__ __forceinline__ float t_bw(float chi) {
   if (!(chi > 0.0f)) return 0.0f;
-  const float e = -3.8471206f / chi - __builtin_amdgcn_logf(1.0f + 0.22f * chi) * (1.0f / 3.0f);   // 8/3 log2(e)
+  const float e = -3.8471206f * __builtin_amdgcn_rcpf(chi) -
+                  __builtin_amdgcn_logf(1.0f + 0.22f * chi) * (1.0f / 3.0f);   // 8/3 log2(e)
   return 0.23f * __builtin_amdgcn_exp2f(e);
 }
 

@@ -24,6 +24,14 @@ struct Ctx {
   const float* tab;       // photon spectrum table
   int* err;
   long long* shard;       // event counters [tube][NSHARD][C_N], summed by the host
+  // conversion queue of the sorted photon pass: workgroup b of the photon
+  // kernel writes its entries (slot, probability) from slot c0(b) * CHUNK on,
+  // c0(b) being the first chunk of its range, and their number to pq_count[b]
+  uint32_t* pq_slot;
+  float* pq_p;
+  int32_t* pq_tile;
+  int32_t* pq_tube;
+  int* pq_count;
 };
 
 constexpr int NSHARD = 64;
@@ -224,6 +232,9 @@ __device__ void flush_window(const Ctx& cx, int tile, long long* s_rho) {
 struct KC {
   int tile, tube, base, N, node_off, flags, nsub_max, dpho;
   int64_t step, hfix;
+  // a non-periodic tube's photon at tile-local position q (fixed point from
+  // the window base) is outside [0, L) or above H when q < xlo or q >= xhi
+  int64_t xlo, xhi;
   float dt, lr, inv_rc, b, xc_floor, x_thr, emit_k, conv_k, cfl24, chi_skip;
   uint64_t seed;
 };
@@ -250,6 +261,8 @@ __device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
   k.dpho = rfl(T.dpho);
   k.step = rfl((int64_t)T.step);
   k.hfix = rfl((int64_t)T.hfix);
+  k.xlo = -((int64_t)k.base << FRAC);
+  k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
   k.dt = rfl(T.dt);
   k.lr = rfl(T.lr);
   k.inv_rc = rfl(T.inv_rc);
@@ -271,6 +284,8 @@ __device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
   const Tube& T = cx.tubes[tl.tube];
   k.tile = tile; k.tube = tl.tube; k.base = tl.base; k.N = T.N; k.node_off = T.node_off; k.flags = T.flags;
   k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = T.step; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
+  k.xlo = -((int64_t)k.base << FRAC);
+  k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
   k.inv_rc = T.inv_rc; k.b = T.b; k.xc_floor = T.xc_floor; k.x_thr = T.x_thr; k.emit_k = T.emit_k;
   k.conv_k = T.conv_k; k.cfl24 = T.cfl24; k.chi_skip = T.chi_skip; k.seed = T.seed;
   return k;
@@ -279,7 +294,10 @@ __device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
 // Small-argument forms used on the hot path (relative error < 1e-12 where
 // they are selected, far below FP32 rounding).
 __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), x >= 0
-  if (x < 1e-2f) return x * (1.0f - 0.5f * x * (1.0f - (1.0f / 3.0f) * x * (1.0f - 0.25f * x)));
+  // Taylor series to x^7 below 1/8 (truncation x^8/8! < 1.2e-11 relative)
+  if (x <= 0.125f)
+    return x * (1.0f - 0.5f * x * (1.0f - (1.0f / 3.0f) * x * (1.0f - 0.25f * x * (1.0f - 0.2f * x *
+                (1.0f - (1.0f / 6.0f) * x * (1.0f - (1.0f / 7.0f) * x))))));
   return -expm1f(-x);
 }
 
@@ -585,6 +603,19 @@ __device__ __forceinline__ float sin_small(float a) {
   return sinf(a);
 }
 
+// Conversion probability of a photon in this step: rate alpha_em (b/lambda~)
+// sin(psi) T_BW(x b sin psi), sin(psi) = |sin(s/R~)| with s the path since
+// birth.  Below chi_skip the fit gives p < 2^-27, under every 24-bit uniform:
+// 0 is returned and no draw is made.  The age is taken in 32 bits, wrapping
+// like the stored 32-bit birth step.
+__device__ __forceinline__ float photon_prob(const KC& k, float x, int32_t n0) {
+  const int32_t age = (int32_t)((uint32_t)k.step + 1u - (uint32_t)n0);
+  const float sp = fabsf(sin_small((float)age * k.dt * k.inv_rc));
+  const float chi = fabsf(x) * k.b * sp;
+  if (!(chi > k.chi_skip)) return 0.0f;
+  return one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
+}
+
 // One photon: free streaming at c, exit above H, conversion with
 // rate alpha_em (b/lambda~) sin(psi) T_BW(x b sin psi), sin(psi) = |sin(s/R~)|.
 // Below chi_skip the fit gives p < 2^-27, under every 24-bit uniform: no
@@ -624,17 +655,13 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   float w = 0.0f;
   uint64_t id = 0;
   if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
-    const float sp = fabsf(sin_small((float)(step + 1 - (int64_t)n0) * k.dt * k.inv_rc));
-    const float chi = fabsf(x) * k.b * sp;
-    if (chi > k.chi_skip) {
-      const float p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
-      if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
-        eval = true;
-        id = cx.P.id[slot];
-        u4 r = draw<true>(k.seed, id, step, T_CONV, 0);
-        conv = bern(r.a, p);
-        if (conv) w = cx.P.w[slot];
-      }
+    const float p = photon_prob(k, x, n0);
+    if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
+      eval = true;
+      id = cx.P.id[slot];
+      u4 r = draw<true>(k.seed, id, step, T_CONV, 0);
+      conv = bern(r.a, p);
+      if (conv) w = cx.P.w[slot];
     }
   }
   if (UNI) {           // the caller stores the chunk's records with vector stores
@@ -702,28 +729,30 @@ __device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x,
   const bool alive = x != 0.0f;
   const uint32_t flags = (uint32_t)k.flags;
   const bool per = (flags & F_PERIODIC) != 0;
-  const long long np = (long long)pos + (x >= 0.0f ? k.dpho : -k.dpho);
-  const int noff = (int)(np >> FRAC);
-  const uint32_t nfrac = (uint32_t)np & 0xFFFFFFu;
-  const int ncell = k.base + noff;
+  // new tile-local position; leaving the 256-cell window (a tile error) is
+  // the 32-bit add or subtract wrapping around
+  const uint32_t d = (uint32_t)k.dpho;
+  const uint32_t np = x >= 0.0f ? pos + d : pos - d;
+  const bool oob = x >= 0.0f ? np < pos : pos < d;
   bool dead = false;
-  if (alive && (np < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
-  const int ncg = per ? wrap_cell(ncell, k.N) : ncell;
+  if (alive && oob) { atomicOr(cx.err, E_TILE); dead = true; }
   bool exited = false;
   if (alive && !dead) {
-    if ((!per && (ncell < 0 || ncell >= k.N)) || (((int64_t)ncg << FRAC) + nfrac >= k.hfix)) { exited = true; dead = true; }
+    if (per) {
+      const int ncg = wrap_cell(k.base + (int)(np >> FRAC), k.N);
+      exited = ((int64_t)ncg << FRAC) + (np & 0xFFFFFFu) >= k.hfix;
+    } else {
+      exited = (int64_t)np < k.xlo || (int64_t)np >= k.xhi;
+    }
+    dead = exited;
   }
   bool eval = false;
   float p = 0.0f;
   if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
-    const float sp = fabsf(sin_small((float)(k.step + 1 - (int64_t)n0) * k.dt * k.inv_rc));
-    const float chi = fabsf(x) * k.b * sp;
-    if (chi > k.chi_skip) {
-      p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
-      eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
-    }
+    p = photon_prob(k, x, n0);
+    eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
   }
-  *pos_out = (uint32_t)np;
+  *pos_out = np;
   *x_out = dead ? 0.0f : x;
   *p_out = p;
   *eval_out = eval;
@@ -732,67 +761,33 @@ __device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x,
   lcn.v[4] += exited ? 1 : 0;
 }
 
-// Second half for a photon that draws: the conversion, and the pair (e- and
-// e+ at the photon position, gamma = x/2 each, along the photon).  Every
-// lane of the wave calls it (act = false: nothing to do) so that the births
-// can be reserved with one atomic per wave.
-__device__ __forceinline__ bool photon_convert(const Ctx& cx, const KC& k, const Room& lroom, LocalCounts& lcn,
-                                               bool act, uint32_t slot, uint32_t np, float x, float p, int tile) {
-  bool conv = false;
-  uint64_t id = 0;
-  float w = 0.0f;
-  if (act) {
-    id = cx.P.id[slot];
-    const u4 r = draw<true>(k.seed, id, k.step, T_CONV, 0);
-    conv = bern(r.a, p);
-    if (conv) w = cx.P.w[slot];
-  }
-  if (__ballot(conv)) {
-    int dropped = 0;
-    const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
-    if (conv) {
-      const float dir = x >= 0.0f ? 1.0f : -1.0f;
-      const float gm = 0.5f * fabsf(x);
-      const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
-      for (int e = 0; e < 2; ++e) {
-        const long long sl = first + e;
-        if (sl < lroom.L) {
-          const uint32_t s32 = (uint32_t)sl;
-          cx.L.pos[s32] = np;
-          cx.L.u[s32] = up;
-          cx.L.w[s32] = e == 0 ? -w : w;
-          cx.L.id[s32] = child_id(k.seed, id, k.step, (uint32_t)e);
-          cx.ltt[s32] = tile;
-        }
-      }
-    }
-    if (dropped) atomicOr(cx.err, E_CAP);
-    lcn.v[3] += dropped;
-  }
-  lcn.v[2] += conv ? 1 : 0;
-  return conv;
+// First chunk of the range of workgroup `bx` of a grid of G over nsc chunks
+// (XCD-aware: consecutive ranges go to workgroups of the same XCD).
+__device__ __forceinline__ void chunk_range(long long nsc, int G, int bx, long long* c0, long long* c1) {
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  *c0 = nsc * r / G;
+  *c1 = nsc * (r + 1) / G;
 }
 
-// Photon pass over the sorted region (ranges of chunks per workgroup, XCD-
-// aware, VEC slots per thread, next chunk prefetched).  Only a tenth or so
-// of the photons draw a conversion in a step, scattered over the lanes, so
-// each chunk runs in three phases: every thread moves its photons and queues
-// those that draw in LDS; the workgroup then runs the draws (and the pair
-// births) over the compacted queue; finally each thread stores its records.
+// Photon pass over the sorted region, first kernel: free streaming, exits
+// and the conversion probability of every photon (a range of chunks per
+// workgroup, VEC slots per thread, the next chunk prefetched).  Only a tenth
+// or so of the photons must draw; they are queued, with their probability,
+// in the workgroup's own segment of the conversion queue (at most one entry
+// per slot of its range, so the segment cannot overflow), and the
+// conversion kernel works through the queue.  No barrier stands between
+// chunks.
 __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
-  const Room lroom = load_room(cx.lc);
-  const long long nsc = cx.pc->n_sorted_chunks;
-  const int G = gridDim.x, bx = blockIdx.x;
-  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
-  const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
+  long long c0, c1;
+  chunk_range(cx.pc->n_sorted_chunks, gridDim.x, blockIdx.x, &c0, &c1);
   __shared__ long long s_cnt[8];
-  __shared__ uint32_t q_slot[CHUNK];
-  __shared__ uint32_t q_pos[CHUNK];
-  __shared__ float q_x[CHUNK];
-  __shared__ float q_p[CHUNK];
-  __shared__ uint16_t q_own[CHUNK];     // thread * VEC + j of the photon's owner
-  __shared__ __align__(4) uint8_t s_conv[CHUNK];
   __shared__ int q_n;
+  if (threadIdx.x == 0) q_n = 0;
+  __syncthreads();
+  uint32_t* const qslot = cx.pq_slot + c0 * CHUNK;
+  float* const qprob = cx.pq_p + c0 * CHUNK;
+  int32_t* const qtile = cx.pq_tile + c0 * CHUNK;
+  int32_t* const qtube = cx.pq_tube + c0 * CHUNK;
   LocalCounts lcn;
   lcn.clear();
   int ctube = -1;
@@ -811,8 +806,6 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
         ctube = kc.tube;
       }
     }
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
     float4 x = cur.x;
     bool xchg = false;
     uint4 p = cur.pos;
@@ -825,47 +818,92 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
       photon_move(cx, kc, x.x, p.x, n0.x, lcn, &po, &xo, &pr, &ev);
       xchg |= xo != x.x;
       const uint64_t m = __ballot(ev);
-      int base = 0;
-      if (lane_id() == 0 && m) base = atomicAdd(&q_n, (int)__popcll(m));
-      base = __shfl(base, 0);
-      const int own = (int)threadIdx.x * VEC + j;
-      if (ev) {
-        const int i = base + rank_in(m);
-        q_slot[i] = cur.slot0 + j;
-        q_pos[i] = po;
-        q_x[i] = x.x;
-        q_p[i] = pr;
-        q_own[i] = (uint16_t)own;
+      if (m) {
+        int base = 0;
+        if (lane_id() == 0) base = atomicAdd(&q_n, (int)__popcll(m));
+        base = __shfl(base, 0);
+        if (ev) {
+          const int i = base + rank_in(m);
+          qslot[i] = cur.slot0 + j;
+          qprob[i] = pr;
+          qtile[i] = held;
+          qtube[i] = kc.tube;
+        }
       }
-      s_conv[own] = 0;
       x = make_float4(x.y, x.z, x.w, xo);
       p = make_uint4(p.y, p.z, p.w, po);
       n0 = make_int4(n0.y, n0.z, n0.w, n0.x);
     }
-    __syncthreads();
-    const int nq = q_n;
-    for (int i0 = 0; i0 < nq; i0 += TPB) {
-      const int i = i0 + (int)threadIdx.x;
-      const bool act = i < nq;
-      uint32_t qs = 0, qp = 0;
-      float qx = 0.0f, qpr = 0.0f;
-      if (act) { qs = q_slot[i]; qp = q_pos[i]; qx = q_x[i]; qpr = q_p[i]; }
-      if (photon_convert(cx, kc, lroom, lcn, act, qs, qp, qx, qpr, held)) s_conv[q_own[i]] = 1;
-    }
-    __syncthreads();
-    const uint32_t cv = *reinterpret_cast<const uint32_t*>(s_conv + (int)threadIdx.x * VEC);
-    if (cv) {
-      if (cv & 0xFFu) x.x = 0.0f;
-      if (cv & 0xFF00u) x.y = 0.0f;
-      if (cv & 0xFF0000u) x.z = 0.0f;
-      if (cv & 0xFF000000u) x.w = 0.0f;
-      xchg = true;
-    }
     *reinterpret_cast<uint4*>(cx.P.pos + cur.slot0) = p;
-    if (xchg) *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;   // only when a photon died
+    if (xchg) *reinterpret_cast<float4*>(cx.P.x + cur.slot0) = x;   // only when a photon left
     cur = nxt;
   }
   if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
+  __syncthreads();
+  if (threadIdx.x == 0) cx.pq_count[blockIdx.x] = q_n;
+}
+
+// Photon pass, second kernel: the conversion draws of the queued photons and
+// the pairs they create: e- and e+ at the photon's new position, gamma = x/2
+// each, moving along the photon; the converted photon is removed.  The grid
+// is CONV_SPLIT times the photon kernel's: workgroup b takes every
+// CONV_SPLIT-th block of TPB entries of the segment that workgroup
+// b / CONV_SPLIT of the photon kernel wrote.
+constexpr int CONV_SPLIT = 4;
+
+__global__ __launch_bounds__(TPB) void k_conversions(Ctx cx) {
+  const Room lroom = load_room(cx.lc);
+  const int seg = blockIdx.x / CONV_SPLIT, part = blockIdx.x % CONV_SPLIT;
+  long long c0, c1;
+  chunk_range(cx.pc->n_sorted_chunks, gridDim.x / CONV_SPLIT, seg, &c0, &c1);
+  const long long q0 = c0 * CHUNK;
+  const int n = __builtin_amdgcn_readfirstlane(cx.pq_count[seg]);
+  for (int i0 = part * TPB; i0 < n; i0 += CONV_SPLIT * TPB) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool act = i < n;
+    uint32_t slot = 0;
+    int tile = 0, tube = -1;
+    bool conv = false;
+    uint64_t id = 0, seed = 0;
+    int64_t step = 0;
+    if (act) {
+      slot = cx.pq_slot[q0 + i];
+      const float p = cx.pq_p[q0 + i];
+      tile = cx.pq_tile[q0 + i];
+      tube = cx.pq_tube[q0 + i];
+      id = cx.P.id[slot];
+      seed = cx.tubes[tube].seed;
+      step = cx.tubes[tube].step;
+      const u4 r = draw<true>(seed, id, step, T_CONV, 0);
+      conv = bern(r.a, p);
+    }
+    if (__ballot(conv)) {
+      int dropped = 0;
+      const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
+      if (conv) {
+        const float x = cx.P.x[slot], w = cx.P.w[slot];
+        const uint32_t np = cx.P.pos[slot];
+        const float dir = x >= 0.0f ? 1.0f : -1.0f;
+        const float gm = 0.5f * fabsf(x);
+        const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+        for (int e = 0; e < 2; ++e) {
+          const long long sl = first + e;
+          if (sl < lroom.L) {
+            const uint32_t s32 = (uint32_t)sl;
+            cx.L.pos[s32] = np;
+            cx.L.u[s32] = up;
+            cx.L.w[s32] = e == 0 ? -w : w;
+            cx.L.id[s32] = child_id(seed, id, step, (uint32_t)e);
+            cx.ltt[s32] = tile;
+          }
+        }
+        cx.P.x[slot] = 0.0f;
+      }
+      if (dropped) atomicOr(cx.err, E_CAP);
+      count_by_tube(cx.shard, conv ? tube : -1, C_CONV, 1);
+      if (__ballot(dropped != 0)) count_by_tube(cx.shard, dropped ? tube : -1, C_DROPPED, dropped);
+    }
+  }
 }
 
 __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
@@ -893,7 +931,7 @@ __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
 // charge (and, periodic, sum rho_i (N - i)), and the surface-field update
 //   E_s += dq w0 2^-24 + alpha s_co dt     (Ampere at the surface)
 // Pass B: inclusive scan (Gauss) and conversion to E and the node field.
-constexpr int FB_THREADS = 1024;
+constexpr int FB_THREADS = 256;
 constexpr int FB_PER = 4;
 constexpr int FB_NODES = FB_THREADS * FB_PER;
 
@@ -929,6 +967,20 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
   t = sh[0];
   __syncthreads();
   return t;
+}
+
+// Sum of v[first, last) taken by every wave of the workgroup, 64 entries per
+// load round.
+__device__ __forceinline__ long long wave_range_sum(const long long* v, int first, int last) {
+  long long acc = 0;
+  for (int j0 = first; j0 < last; j0 += WAVE) {
+    const int j = j0 + lane_id();
+    long long x = j < last ? v[j] : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    acc += x;
+  }
+  return acc;
 }
 
 __global__ __launch_bounds__(FB_THREADS) void k_field_a(FieldCtx f) {
@@ -970,12 +1022,10 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
   const bool per = (T.flags & F_PERIODIC) != 0;
   const bool frozen = (T.flags & F_FIELD_FROZEN) != 0;
   // carry from the tube's earlier blocks
-  long long carry = 0;
-  for (int j = b.first_blk; j < (int)blockIdx.x; ++j) carry += f.part[j];
+  const long long carry = wave_range_sum(f.part, b.first_blk, (int)blockIdx.x);
   double mean = 0.0;
   if (per) {
-    long long s2 = 0;
-    for (int j = b.first_blk; j < b.first_blk + b.nblk; ++j) s2 += f.part2[j];
+    const long long s2 = wave_range_sum(f.part2, b.first_blk, b.first_blk + b.nblk);
     mean = ((double)s2 + (double)T.bg_unit * 0.5 * (double)N * (double)N) / (double)N;
   }
   const int k = b.k0 + threadIdx.x * FB_PER;
@@ -1361,7 +1411,9 @@ __global__ __launch_bounds__(TPB) void k_deposit_all(Ctx cx) {
 // global add per workgroup and tube.
 template <class B>
 __global__ __launch_bounds__(TPB) void k_count_live(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
-                                                     const Tile* tiles, long long* out, int n_tubes) {
+                                                     const Tile* tiles, long long* out, int n_tubes,
+                                                     const uint32_t* gate = nullptr) {
+  if (gate != nullptr && *gate == 0) return;   // (a merge check that cannot merge)
   __shared__ int s_n[1024];
   for (int j = threadIdx.x; j < 1024; j += blockDim.x) s_n[j] = 0;
   __syncthreads();

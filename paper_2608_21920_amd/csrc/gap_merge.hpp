@@ -19,6 +19,7 @@ struct SortBuf {
   uint32_t* val[2];     // slot of the record
   uint32_t* bhist;      // [256][nblocks] digit counts per block
   uint32_t* flags;      // per tube: merge this step
+  uint32_t* gate;       // 0: no tube of the store can be over its threshold
   long long* n;         // number of items
   int max_blocks;
 };
@@ -39,10 +40,21 @@ __device__ __forceinline__ uint32_t rec_group(const PhoBuf& b, uint32_t slot, ui
   return (gcell << 9) | ((x >= 0.0f ? 1u : 0u) << 7) | lg2bin_d(fabs((double)x));
 }
 
+// Gate of a merge check: the occupied slots of a store (sorted region plus
+// tail) bound the live particles of all its tubes together, so a store whose
+// occupancy stays at or below the smallest tube threshold holds no tube over
+// its threshold.  The check's counting and gathering kernels then return at
+// once (and the sort passes find nothing to sort).
+__global__ void k_merge_gate(const Ctl* ctl, double thresh_min, uint32_t* gate) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    *gate = (double)(ctl->n_sorted_chunks * CHUNK + ctl->tail) > thresh_min ? 1u : 0u;
+}
+
 // Per-tube decision: merge when the live count exceeds merge_frac * cap.
-__global__ void k_merge_flags(const long long* live, const double* thresh, uint32_t* flags, int n_tubes) {
+__global__ void k_merge_flags(const long long* live, const double* thresh, uint32_t* flags, int n_tubes,
+                              const uint32_t* gate) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_tubes) flags[t] = (double)live[t] > thresh[t] ? 1u : 0u;
+  if (t < n_tubes) flags[t] = (*gate != 0 && (double)live[t] > thresh[t]) ? 1u : 0u;
 }
 
 // Gather the merge candidates (live particles of flagged tubes) with their
@@ -51,6 +63,7 @@ __global__ void k_merge_flags(const long long* live, const double* thresh, uint3
 template <class B>
 __global__ __launch_bounds__(TPB) void k_merge_keys(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
                                                     const Tile* tiles, const Tube* tubes, SortBuf sb) {
+  if (*sb.gate == 0) return;
   const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   for (long long q = blockIdx.x; q < nq; q += gridDim.x) {

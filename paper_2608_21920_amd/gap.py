@@ -26,7 +26,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
 
 DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING = range(9)
 STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE = range(6)
-TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail"]
+TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail", "conversions"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
               "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
@@ -236,7 +236,7 @@ class Gap:
 
     def timing(self) -> dict:
         """{kernel group: (launches, total ms)} since timing was enabled or last read."""
-        v = self._diag(DIAG_TIMING, 0, 112).view(np.float64)
+        v = self._diag(DIAG_TIMING, 0, 8 * 2 * len(TIMING_KEYS)).view(np.float64)
         return {k: (int(v[2 * i]), float(v[2 * i + 1])) for i, k in enumerate(TIMING_KEYS)}
 
     # -- state loading (single tube)
