@@ -24,8 +24,11 @@
  *  - return 0 on success, a negative GAP_E* code otherwise; no exceptions
  *    cross the ABI;
  *  - device work is enqueued on the HIP stream given to gap_init and runs
- *    asynchronously; errors raised on the device are sticky and reported by
- *    the next call that synchronises (gap_sync, gap_diag, gap_set_state);
+ *    asynchronously (a step forks its photon pass onto an internal stream
+ *    of default priority and joins it back before the step ends, so the
+ *    order seen on the caller's stream is unchanged); errors raised on the
+ *    device are sticky and reported by the next call that synchronises
+ *    (gap_sync, gap_diag, gap_set_state);
  *  - one handle must not be used from two host threads at once.
  */
 #ifndef GAP_H
@@ -97,7 +100,8 @@ typedef struct gap_params {
   uint32_t flags;         /* GAP_* flags                                               */
   int32_t nsub_max;       /* cap on Monte Carlo sub-steps per step (>= 1)               */
   int32_t merge_every;    /* steps between merge checks                                */
-  int32_t rebucket_every; /* steps between re-sorts of the stores (0 = automatic)       */
+  int32_t rebucket_every; /* steps between re-sorts of the stores (0 = the longest the
+                             tile margin allows, (64 - 2)/cfl - 1 steps)                */
 } gap_params;
 
 /* Optional device allocator (e.g. backed by torch's caching allocator). */
@@ -182,9 +186,16 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
 #define GAP_STATE_DRIVE     5  /* double alpha, then double inj_weight: the imposed current
                                   j_m = alpha j_co (Sect. 2.2) and the weight of one injected
                                   electron from the next step on; ends a pending window        */
+#define GAP_STATE_LAUNCH    6  /* int32[4]: workgroups of the sorted lepton pass, of the sorted
+                                  photon pass and of the tail passes, and the re-sort interval
+                                  (the values gap_autotune returns); grids must be multiples
+                                  of 8 between 8 and four resident rounds, the interval
+                                  between 1 and the longest the tile margin allows, else
+                                  GAP_EINVAL.  Changes no result, only the speed.             */
 
 /* Replace part of the state of tube `tube` (only valid when n_tubes == 1;
- * GAP_STATE_TIMING and GAP_STATE_DRIVE are valid for any handle).
+ * GAP_STATE_TIMING, GAP_STATE_DRIVE and GAP_STATE_LAUNCH are valid for any
+ * handle, the latter ignoring `tube`).
  * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);

@@ -143,6 +143,9 @@ struct Store {
   int32_t* chunk[2] = {nullptr, nullptr};
   int32_t* tcount = nullptr;
   int32_t* tcursor = nullptr;
+  int32_t* thot = nullptr;        // photons: hot particles per tile at a re-sort
+  int32_t* tcur_cold = nullptr;
+  uint8_t* hflag = nullptr;       // photons: hot flag per slot
   long long* tchunk = nullptr;
   int64_t capacity = 0, limit = 0, cap_live = 0;
   LepBuf lep(int b) const { return LepBuf{pos[b], a[b], w[b], id[b]}; }
@@ -188,6 +191,10 @@ struct WinState {
 struct gap_t {
   int n_tubes = 0;
   hipStream_t s = nullptr;
+  // second stream of a step: the photon pass runs on it beside the lepton
+  // pass and the field update (fork and join through the two events)
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   gap_allocator al{};
   bool custom_alloc = false;
   std::vector<void*> owned;
@@ -230,10 +237,7 @@ struct gap_t {
   double tmin_l = 0.0, tmin_p = 0.0;   // smallest tube threshold of each store
   // conversion queue of the sorted photon pass (one entry per photon slot at
   // most) and its per-workgroup entry counts
-  uint32_t* pq_slot = nullptr;
-  float* pq_p = nullptr;
-  int32_t* pq_tile = nullptr;
-  int32_t* pq_tube = nullptr;
+  uint4* pq = nullptr;
   int* pq_count = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
@@ -272,6 +276,9 @@ void win_release(gap_t* g);
 void release(gap_t* g) {
   if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
   if (g->s) (void)hipStreamSynchronize(g->s);
+  if (g->s2) { (void)hipStreamSynchronize(g->s2); (void)hipStreamDestroy(g->s2); g->s2 = nullptr; }
+  if (g->ev_fork) { (void)hipEventDestroy(g->ev_fork); g->ev_fork = nullptr; }
+  if (g->ev_join) { (void)hipEventDestroy(g->ev_join); g->ev_join = nullptr; }
   win_release(g);
   for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
   g->ev_pool.clear();
@@ -345,10 +352,7 @@ Ctx make_ctx(gap_t* g) {
   c.tab = g->tab;
   c.err = g->err;
   c.shard = g->shard;
-  c.pq_slot = g->pq_slot;
-  c.pq_p = g->pq_p;
-  c.pq_tile = g->pq_tile;
-  c.pq_tube = g->pq_tube;
+  c.pq = g->pq;
   c.pq_count = g->pq_count;
   return c;
 }
@@ -367,15 +371,16 @@ enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, 
        KT_CONV = 7, KT_N = 8 };
 
 struct Timer {
-  gap_t* g; int id; hipEvent_t a = nullptr, b = nullptr;
-  Timer(gap_t* gg, int i) : g(gg), id(i) {
+  gap_t* g; int id; hipStream_t st; hipEvent_t a = nullptr, b = nullptr;
+  Timer(gap_t* gg, int i, hipStream_t stream) : g(gg), id(i), st(stream) {
     if (g->timing && g->ev_pool.size() < 200000) {
       a = next_event(g); b = next_event(g);
-      if (a) (void)hipEventRecord(a, g->s);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
+  Timer(gap_t* gg, int i) : Timer(gg, i, gg->s) {}
   ~Timer() {
-    if (a && b) { (void)hipEventRecord(b, g->s); g->ev_marks.push_back({id, {a, b}}); }
+    if (a && b) { (void)hipEventRecord(b, st); g->ev_marks.push_back({id, {a, b}}); }
   }
 };
 
@@ -414,10 +419,15 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst) {
   cx.tt = st.tt;
   cx.tcount = st.tcount;
   cx.tcursor = st.tcursor;
+  cx.thot = st.thot;
+  cx.tcur_cold = st.tcur_cold;
+  cx.hflag = st.hflag;
+  cx.window = g->R;
   cx.tchunk = st.tchunk;
   cx.n_tiles = g->n_tiles;
   const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
   k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
+  if (st.thot) k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.thot, g->n_tiles, 0);
   k_rb_count<B><<<kGrid, TPB, 0, g->s>>>(cx);
   k_rb_scan<B><<<1, 1024, 0, g->s>>>(cx);
   k_rb_chunks<B><<<kGrid, 256, 0, g->s>>>(cx);
@@ -509,7 +519,7 @@ void enqueue_window_step(gap_t* g) {
   k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
   k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-  k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx);
+  k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
   k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   field_pass(g, 0);
   ++g->host_step;
@@ -693,7 +703,7 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
       k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
       k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
       k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-      k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx);
+      k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
       k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
       field_pass(g, 0);
       ++g->host_step;
@@ -764,12 +774,21 @@ void enqueue_step(gap_t* g) {
   if (g->merge_on && g->host_step % g->merge_every == 0) merge_all(g);
   Ctx cx = make_ctx(g);
   { Timer t(g, KT_PRE); k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes); }
+  // The two species' passes touch disjoint data: each reads its own store
+  // up to the tail snapshot of the prologue and appends the other species'
+  // births past that snapshot; only the leptons deposit charge.  The photon
+  // pass runs on the second stream while the lepton pass and the field
+  // update run on the caller's; the re-sort and the next step wait for both.
+  (void)hipEventRecord(g->ev_fork, g->s);
+  (void)hipStreamWaitEvent(g->s2, g->ev_fork, 0);
+  { Timer t(g, KT_PHOTONS, g->s2); k_photons<<<g->grid_pho, TPB, 0, g->s2>>>(cx); }
+  { Timer t(g, KT_CONV, g->s2); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s2>>>(cx, g->grid_pho); }
+  { Timer t(g, KT_PHOTAIL, g->s2); k_photons_tail<<<g->grid_tail, TPB, 0, g->s2>>>(cx); }
+  (void)hipEventRecord(g->ev_join, g->s2);
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
-  { Timer t(g, KT_PHOTONS); k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx); }
-  { Timer t(g, KT_CONV); k_conversions<<<g->grid_pho * CONV_SPLIT, TPB, 0, g->s>>>(cx); }
-  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
+  (void)hipStreamWaitEvent(g->s, g->ev_join, 0);
   if (++g->since_rb >= g->R) {
     Timer t(g, KT_RESORT);
     rebucket_all(g);
@@ -816,6 +835,12 @@ int alloc_store(gap_t* g, Store& st, int64_t cap, bool photon) {
   st.tt = (int32_t*)dalloc(g, n * 4);
   st.tcount = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
   st.tcursor = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+  if (photon) {
+    st.thot = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+    st.tcur_cold = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+    st.hflag = (uint8_t*)dalloc(g, (size_t)st.capacity);
+    if (!st.thot || !st.tcur_cold || !st.hflag) return GAP_ENOMEM;
+  }
   st.tchunk = (long long*)dalloc(g, ((size_t)g->n_tiles + 1) * 8);
   st.ctl = (Ctl*)dalloc(g, sizeof(Ctl));
   if (!st.tt || !st.tcount || !st.tcursor || !st.tchunk || !st.ctl) return GAP_ENOMEM;
@@ -898,7 +923,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     cap_p += q.cap_photons;
     if (q.flags & GAP_PERIODIC) g->any_periodic = true;
     const int rmax = std::max(1, (int)std::floor((MARGIN - 2) / q.cfl) - 1);
-    rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : std::min(64, rmax));
+    rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : rmax);
   }
   g->R = rmin;
   g->rmax = 1 << 30;
@@ -912,11 +937,15 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons, TPB, 0));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
-    g->grid_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
-    g->grid_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
-    g->grid_tail = std::max(8, cus * 4);
-    g->round_lep = g->grid_lep;
-    g->round_pho = g->grid_pho;
+    // defaults measured on the production gap (2e7 particles): one resident
+    // round for the lepton pass, four for the photon pass (short ranges keep
+    // its conversion queue segments small), eight workgroups per CU for the
+    // tail passes; gap_autotune or GAP_STATE_LAUNCH can change them
+    g->round_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
+    g->round_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
+    g->grid_lep = g->round_lep;
+    g->grid_pho = 4 * g->round_pho;
+    g->grid_tail = std::max(8, cus * 8);
     g->cus = cus;
   }
   if (g->total_nodes > (1LL << 30)) return GAP_EINVAL;
@@ -942,12 +971,9 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   if ((e = alloc_store(g, g->lep, cap_l, false))) return e;
   if ((e = alloc_store(g, g->pho, cap_p, true))) return e;
   g->pq_groups = 8 * g->round_pho + 64;   // the autotuner tries grids up to 4 resident rounds
-  g->pq_slot = (uint32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
-  g->pq_p = (float*)dalloc(g, (size_t)g->pho.capacity * 4);
-  g->pq_tile = (int32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
-  g->pq_tube = (int32_t*)dalloc(g, (size_t)g->pho.capacity * 4);
+  g->pq = (uint4*)dalloc(g, (size_t)g->pho.capacity * sizeof(uint4));
   g->pq_count = (int*)dalloc(g, (size_t)g->pq_groups * 4);
-  if (!g->pq_slot || !g->pq_p || !g->pq_tile || !g->pq_tube || !g->pq_count) return GAP_ENOMEM;
+  if (!g->pq || !g->pq_count) return GAP_ENOMEM;
   for (int t = 0; t < n_tubes; ++t) if (g->P[t].flags & GAP_MERGE_ON) g->merge_on = true;
   if (g->merge_on) {
     g->merge_every = std::max(1, g->P[0].merge_every);
@@ -1134,21 +1160,27 @@ int autotune(gap_t* g, int trial, int32_t* chosen) {
     for (int m : {1, 2, 4, 8}) v.push_back(std::max(lo, (round * m / 2) / 8 * 8));
     return v;
   };
-  struct Knob { int* grid; std::vector<int> c; std::vector<int> ids; };
-  Knob knobs[3] = {{&g->grid_lep, cands(g->round_lep, 8), {KT_LEPTONS}},
-                   {&g->grid_pho, cands(g->round_pho, 8), {KT_PHOTONS, KT_CONV}},
-                   {&g->grid_tail, {g->cus * 2, g->cus * 4, g->cus * 8, g->cus * 16}, {KT_LEPTAIL, KT_PHOTAIL}}};
+  struct Knob { int* grid; std::vector<int> c; };
+  Knob knobs[3] = {{&g->grid_lep, cands(g->round_lep, 8)},
+                   {&g->grid_pho, cands(g->round_pho, 8)},
+                   {&g->grid_tail, {g->cus * 2, g->cus * 4, g->cus * 8, g->cus * 16}}};
   if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }   // warm-up
   for (Knob& k : knobs) {
     double best = 1e300;
     int arg = *k.grid;
-    for (int c : k.c) {
-      *k.grid = c;
-      if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }
-      double t = 0.0;
-      for (int id : k.ids) t += kt[id];
-      if (t < best) { best = t; arg = c; }
+    // the passes of the two species overlap on two streams: the measure is
+    // the steps' wall time, less the re-sorts that fall into the trial, the
+    // better of two rounds over the candidates
+    std::vector<double> tbest(k.c.size(), 1e300);
+    for (int round = 0; round < 2; ++round) {
+      for (size_t ci = 0; ci < k.c.size(); ++ci) {
+        *k.grid = k.c[ci];
+        if ((e = timed_steps(g, trial, kt, &wall))) { g->timing = was; return e; }
+        tbest[ci] = std::min(tbest[ci], wall - kt[KT_RESORT]);
+      }
     }
+    for (size_t ci = 0; ci < k.c.size(); ++ci)
+      if (tbest[ci] < best) { best = tbest[ci]; arg = k.c[ci]; }
     *k.grid = arg;
   }
   // re-sort interval: whole steps, each candidate over at least two re-sorts
@@ -1161,8 +1193,10 @@ int autotune(gap_t* g, int trial, int32_t* chosen) {
     double best = 1e300;
     int arg = g->R;
     for (int r : rc) {
+      // the count of steps since the last re-sort carries over (a shorter
+      // interval re-sorts at once): the drift bound of the tile margin holds
+      // only for steps actually counted since a re-sort
       g->R = r;
-      g->since_rb = 0;
       const int64_t n = std::max<int64_t>(trial, 2 * (int64_t)r);
       if ((e = timed_steps(g, n, kt, &wall))) { g->timing = was; return e; }
       const double per = wall / (double)n;
@@ -1195,6 +1229,14 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GAP_EDEVICE;
   gap_t* g = new gap_t();
   g->s = (hipStream_t)stream;
+  // default priority, like every stream of the library
+  if (hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) {
+    release(g);
+    delete g;
+    return GAP_EDEVICE;
+  }
   if (alloc) { g->al = *alloc; g->custom_alloc = true; }
   int e = build(g, p, n_tubes);
   if (e) {
@@ -1363,6 +1405,21 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     g->timing = on != 0;
     g->ev_marks.clear();
     g->ev_used = 0;
+    return GAP_OK;
+  }
+  if (kind == GAP_STATE_LAUNCH) {
+    if (bytes < 16) return GAP_EINVAL;
+    int32_t v[4];
+    std::memcpy(v, host_buf, 16);
+    auto grid_ok = [](int x, int round) { return x >= 8 && x % 8 == 0 && x <= 4 * round; };
+    if (!grid_ok(v[0], g->round_lep) || !grid_ok(v[1], g->round_pho) || !grid_ok(v[2], 16 * g->cus / 4) ||
+        v[3] < 1 || v[3] > g->rmax)
+      return GAP_EINVAL;
+    g->grid_lep = v[0];
+    g->grid_pho = v[1];
+    g->grid_tail = v[2];
+    g->R = v[3];
+    if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; g->gsteps = -1; }
     return GAP_OK;
   }
   g->win.valid = false;     // any other state change ends a pending window

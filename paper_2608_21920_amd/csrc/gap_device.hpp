@@ -76,7 +76,8 @@ struct Tube {
   uint64_t seed;
   // mutable
   double Es, inj_acc;
-  int64_t dq, dcur, step;
+  int64_t dq, dcur, step;   // step: steps completed (the field update of a step adds one)
+  int64_t step_now;         // index of the step being taken (set by the prologue; read by the passes)
   uint64_t inj_count;
   int64_t cnt[C_N];
 };
@@ -160,8 +161,7 @@ __device__ __forceinline__ float t_syn(float chi) {
 }
 // pair-creation function of Sect. 3.2 (fit quoted with eq. tau_bw):
 // 0.23 exp(-8/(3 chi)) (1 + 0.22 chi)^(-1/3)
-__device__ __forceinline__ float t_bw(float chi) {
-  if (!(chi > 0.0f)) return 0.0f;
+__device__ __forceinline__ float t_bw(float chi) {   // (chi = 0 gives 0 through 1/chi = inf)
   const float e = -3.8471206f * __builtin_amdgcn_rcpf(chi) -
                   __builtin_amdgcn_logf(1.0f + 0.22f * chi) * (1.0f / 3.0f);   // 8/3 log2(e)
   return 0.23f * __builtin_amdgcn_exp2f(e);

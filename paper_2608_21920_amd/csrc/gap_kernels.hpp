@@ -2,6 +2,8 @@
 #pragma once
 #include "gap_device.hpp"
 
+#include <type_traits>
+
 namespace gap {
 
 // Everything a step kernel needs; passed by value.
@@ -25,12 +27,10 @@ struct Ctx {
   int* err;
   long long* shard;       // event counters [tube][NSHARD][C_N], summed by the host
   // conversion queue of the sorted photon pass: workgroup b of the photon
-  // kernel writes its entries (slot, probability) from slot c0(b) * CHUNK on,
-  // c0(b) being the first chunk of its range, and their number to pq_count[b]
-  uint32_t* pq_slot;
-  float* pq_p;
-  int32_t* pq_tile;
-  int32_t* pq_tube;
+  // kernel writes its entries {slot, probability bits, tile, tube} from
+  // entry c0(b) * CHUNK on, c0(b) being the first chunk of its range, and
+  // their number to pq_count[b]
+  uint4* pq;
   int* pq_count;
 };
 
@@ -175,6 +175,9 @@ __device__ __forceinline__ void clamp_tail(Ctl* c) {
 
 __global__ void k_pre(Ctx cx, int n_tubes) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // the passes of this step read its index from step_now: the field update
+  // (which counts the step) may run beside the photon pass
+  for (int t = 0; t < n_tubes; ++t) cx.tubes[t].step_now = cx.tubes[t].step;
   // (appends never leave the tails past the limit; the passes below stay
   // inside the stores whatever the tails hold)
   clamp_tail(cx.lc);
@@ -259,7 +262,7 @@ __device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
   k.flags = rfl(T.flags);
   k.nsub_max = rfl(T.nsub_max);
   k.dpho = rfl(T.dpho);
-  k.step = rfl((int64_t)T.step);
+  k.step = rfl((int64_t)T.step_now);
   k.hfix = rfl((int64_t)T.hfix);
   k.xlo = -((int64_t)k.base << FRAC);
   k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
@@ -283,7 +286,7 @@ __device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
   const Tile tl = cx.tiles[tile];
   const Tube& T = cx.tubes[tl.tube];
   k.tile = tile; k.tube = tl.tube; k.base = tl.base; k.N = T.N; k.node_off = T.node_off; k.flags = T.flags;
-  k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = T.step; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
+  k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = T.step_now; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
   k.xlo = -((int64_t)k.base << FRAC);
   k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
   k.inv_rc = T.inv_rc; k.b = T.b; k.xc_floor = T.xc_floor; k.x_thr = T.x_thr; k.emit_k = T.emit_k;
@@ -293,12 +296,17 @@ __device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
 
 // Small-argument forms used on the hot path (relative error < 1e-12 where
 // they are selected, far below FP32 rounding).
+// The rare branches are taken only by waves that have a lane needing them
+// (a wave-uniform test), so the common path runs without exec-mask changes.
 __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), x >= 0
-  // Taylor series to x^7 below 1/8 (truncation x^8/8! < 1.2e-11 relative)
-  if (x <= 0.125f)
-    return x * (1.0f - 0.5f * x * (1.0f - (1.0f / 3.0f) * x * (1.0f - 0.25f * x * (1.0f - 0.2f * x *
-                (1.0f - (1.0f / 6.0f) * x * (1.0f - (1.0f / 7.0f) * x))))));
-  return -expm1f(-x);
+  // Taylor series to x^7 up to 1/8 (truncation x^8/8! < 1.2e-11 relative)
+  float r = x * (1.0f - 0.5f * x * (1.0f - (1.0f / 3.0f) * x * (1.0f - 0.25f * x * (1.0f - 0.2f * x *
+            (1.0f - (1.0f / 6.0f) * x * (1.0f - (1.0f / 7.0f) * x))))));
+  const bool big = x > 0.125f;
+  if (__ballot(big)) {
+    if (big) r = -expm1f(-x);
+  }
+  return r;
 }
 
 // One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
@@ -599,8 +607,12 @@ __global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
 // (truncation a^7/5040 < 2e-13 relative).
 __device__ __forceinline__ float sin_small(float a) {
   const float a2 = a * a;
-  if (fabsf(a) < 0.05f) return a * (1.0f - a2 * (1.0f / 6.0f) * (1.0f - a2 * (1.0f / 20.0f)));
-  return sinf(a);
+  float s = a * (1.0f - a2 * (1.0f / 6.0f) * (1.0f - a2 * (1.0f / 20.0f)));
+  const bool big = !(fabsf(a) < 0.05f);
+  if (__ballot(big)) {
+    if (big) s = sinf(a);
+  }
+  return s;
 }
 
 // Conversion probability of a photon in this step: rate alpha_em (b/lambda~)
@@ -612,8 +624,8 @@ __device__ __forceinline__ float photon_prob(const KC& k, float x, int32_t n0) {
   const int32_t age = (int32_t)((uint32_t)k.step + 1u - (uint32_t)n0);
   const float sp = fabsf(sin_small((float)age * k.dt * k.inv_rc));
   const float chi = fabsf(x) * k.b * sp;
-  if (!(chi > k.chi_skip)) return 0.0f;
-  return one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
+  const float p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
+  return chi > k.chi_skip ? p : 0.0f;
 }
 
 // One photon: free streaming at c, exit above H, conversion with
@@ -733,25 +745,25 @@ __device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x,
   // the 32-bit add or subtract wrapping around
   const uint32_t d = (uint32_t)k.dpho;
   const uint32_t np = x >= 0.0f ? pos + d : pos - d;
-  const bool oob = x >= 0.0f ? np < pos : pos < d;
-  bool dead = false;
-  if (alive && oob) { atomicOr(cx.err, E_TILE); dead = true; }
-  bool exited = false;
-  if (alive && !dead) {
-    if (per) {
-      const int ncg = wrap_cell(k.base + (int)(np >> FRAC), k.N);
-      exited = ((int64_t)ncg << FRAC) + (np & 0xFFFFFFu) >= k.hfix;
-    } else {
-      exited = (int64_t)np < k.xlo || (int64_t)np >= k.xhi;
-    }
-    dead = exited;
+  const bool fwd = x >= 0.0f;
+  const bool oob = alive & ((fwd & (np < pos)) | (!fwd & (pos < d)));   // (no short-circuit: no branches)
+  if (__ballot(oob)) {
+    if (oob) atomicOr(cx.err, E_TILE);
   }
-  bool eval = false;
-  float p = 0.0f;
-  if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
-    p = photon_prob(k, x, n0);
-    eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
+  bool out;
+  if (per) {
+    const int ncg = wrap_cell(k.base + (int)(np >> FRAC), k.N);
+    out = ((int64_t)ncg << FRAC) + (np & 0xFFFFFFu) >= k.hfix;
+  } else {
+    out = ((int64_t)np < k.xlo) | ((int64_t)np >= k.xhi);
   }
+  const bool exited = alive & !oob & out;
+  const bool dead = oob | exited;
+  // the probability is taken for every lane (0 for an empty slot: chi = 0)
+  // and kept for the live ones
+  const float pr = photon_prob(k, x, n0);
+  const float p = (alive & !dead & !(flags & (F_QED_OFF | F_CONV_OFF))) ? pr : 0.0f;
+  const bool eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
   *pos_out = np;
   *x_out = dead ? 0.0f : x;
   *p_out = p;
@@ -784,10 +796,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
   __shared__ int q_n;
   if (threadIdx.x == 0) q_n = 0;
   __syncthreads();
-  uint32_t* const qslot = cx.pq_slot + c0 * CHUNK;
-  float* const qprob = cx.pq_p + c0 * CHUNK;
-  int32_t* const qtile = cx.pq_tile + c0 * CHUNK;
-  int32_t* const qtube = cx.pq_tube + c0 * CHUNK;
+  uint4* const q = cx.pq + c0 * CHUNK;
   LocalCounts lcn;
   lcn.clear();
   int ctube = -1;
@@ -822,13 +831,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
         int base = 0;
         if (lane_id() == 0) base = atomicAdd(&q_n, (int)__popcll(m));
         base = __shfl(base, 0);
-        if (ev) {
-          const int i = base + rank_in(m);
-          qslot[i] = cur.slot0 + j;
-          qprob[i] = pr;
-          qtile[i] = held;
-          qtube[i] = kc.tube;
-        }
+        if (ev) q[base + rank_in(m)] = make_uint4(cur.slot0 + j, __float_as_uint(pr), (uint32_t)held, (uint32_t)kc.tube);
       }
       x = make_float4(x.y, x.z, x.w, xo);
       p = make_uint4(p.y, p.z, p.w, po);
@@ -845,63 +848,82 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 
 // Photon pass, second kernel: the conversion draws of the queued photons and
 // the pairs they create: e- and e+ at the photon's new position, gamma = x/2
-// each, moving along the photon; the converted photon is removed.  The grid
-// is CONV_SPLIT times the photon kernel's: workgroup b takes every
-// CONV_SPLIT-th block of TPB entries of the segment that workgroup
-// b / CONV_SPLIT of the photon kernel wrote.
-constexpr int CONV_SPLIT = 4;
+// each, moving along the photon; the converted photon is removed.
+// Workgroup b takes the segments that workgroups CONV_SEGS b .. CONV_SEGS b
+// + CONV_SEGS - 1 of the photon kernel (a grid of nseg) wrote, one entry of
+// each segment per thread and round, with all loads issued before the draws.
+constexpr int CONV_SEGS = 4;
 
-__global__ __launch_bounds__(TPB) void k_conversions(Ctx cx) {
+__global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   const Room lroom = load_room(cx.lc);
-  const int seg = blockIdx.x / CONV_SPLIT, part = blockIdx.x % CONV_SPLIT;
-  long long c0, c1;
-  chunk_range(cx.pc->n_sorted_chunks, gridDim.x / CONV_SPLIT, seg, &c0, &c1);
-  const long long q0 = c0 * CHUNK;
-  const int n = __builtin_amdgcn_readfirstlane(cx.pq_count[seg]);
-  for (int i0 = part * TPB; i0 < n; i0 += CONV_SPLIT * TPB) {
-    const int i = i0 + (int)threadIdx.x;
-    const bool act = i < n;
-    uint32_t slot = 0;
-    int tile = 0, tube = -1;
-    bool conv = false;
-    uint64_t id = 0, seed = 0;
-    int64_t step = 0;
-    if (act) {
-      slot = cx.pq_slot[q0 + i];
-      const float p = cx.pq_p[q0 + i];
-      tile = cx.pq_tile[q0 + i];
-      tube = cx.pq_tube[q0 + i];
-      id = cx.P.id[slot];
-      seed = cx.tubes[tube].seed;
-      step = cx.tubes[tube].step;
-      const u4 r = draw<true>(seed, id, step, T_CONV, 0);
-      conv = bern(r.a, p);
+  const long long nsc = cx.pc->n_sorted_chunks;
+  long long q0[CONV_SEGS];
+  int n[CONV_SEGS];
+  int nmax = 0;
+#pragma unroll
+  for (int j = 0; j < CONV_SEGS; ++j) {
+    const int sg = (int)blockIdx.x * CONV_SEGS + j;
+    long long c0 = 0, c1 = 0;
+    n[j] = 0;
+    if (sg < nseg) {
+      chunk_range(nsc, nseg, sg, &c0, &c1);
+      n[j] = __builtin_amdgcn_readfirstlane(cx.pq_count[sg]);
     }
-    if (__ballot(conv)) {
-      int dropped = 0;
-      const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
-      if (conv) {
-        const float x = cx.P.x[slot], w = cx.P.w[slot];
-        const uint32_t np = cx.P.pos[slot];
-        const float dir = x >= 0.0f ? 1.0f : -1.0f;
-        const float gm = 0.5f * fabsf(x);
-        const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
-        for (int e = 0; e < 2; ++e) {
-          const long long sl = first + e;
-          if (sl < lroom.L) {
-            const uint32_t s32 = (uint32_t)sl;
-            cx.L.pos[s32] = np;
-            cx.L.u[s32] = up;
-            cx.L.w[s32] = e == 0 ? -w : w;
-            cx.L.id[s32] = child_id(seed, id, step, (uint32_t)e);
-            cx.ltt[s32] = tile;
-          }
-        }
-        cx.P.x[slot] = 0.0f;
+    q0[j] = c0 * CHUNK;
+    nmax = max(nmax, n[j]);
+  }
+  for (int i0 = 0; i0 < nmax; i0 += TPB) {
+    const int i = i0 + (int)threadIdx.x;
+    uint4 e[CONV_SEGS];
+    uint64_t id[CONV_SEGS], seed[CONV_SEGS];
+    int64_t step[CONV_SEGS];
+    bool act[CONV_SEGS];
+#pragma unroll
+    for (int j = 0; j < CONV_SEGS; ++j) {
+      act[j] = i < n[j];
+      e[j] = act[j] ? cx.pq[q0[j] + i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < CONV_SEGS; ++j) {
+      id[j] = act[j] ? cx.P.id[e[j].x] : 0;
+      seed[j] = act[j] ? cx.tubes[e[j].w].seed : 0;
+      step[j] = act[j] ? cx.tubes[e[j].w].step_now : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < CONV_SEGS; ++j) {
+      bool conv = false;
+      if (act[j]) {
+        const u4 r = draw<true>(seed[j], id[j], step[j], T_CONV, 0);
+        conv = bern(r.a, __uint_as_float(e[j].y));
       }
-      if (dropped) atomicOr(cx.err, E_CAP);
-      count_by_tube(cx.shard, conv ? tube : -1, C_CONV, 1);
-      if (__ballot(dropped != 0)) count_by_tube(cx.shard, dropped ? tube : -1, C_DROPPED, dropped);
+      if (__ballot(conv)) {
+        const uint32_t slot = e[j].x;
+        const int tube = conv ? (int)e[j].w : -1;
+        int dropped = 0;
+        const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
+        if (conv) {
+          const float x = cx.P.x[slot], w = cx.P.w[slot];
+          const uint32_t np = cx.P.pos[slot];
+          const float dir = x >= 0.0f ? 1.0f : -1.0f;
+          const float gm = 0.5f * fabsf(x);
+          const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+          for (int b = 0; b < 2; ++b) {
+            const long long sl = first + b;
+            if (sl < lroom.L) {
+              const uint32_t s32 = (uint32_t)sl;
+              cx.L.pos[s32] = np;
+              cx.L.u[s32] = up;
+              cx.L.w[s32] = b == 0 ? -w : w;
+              cx.L.id[s32] = child_id(seed[j], id[j], step[j], (uint32_t)b);
+              cx.ltt[s32] = (int32_t)e[j].z;
+            }
+          }
+          cx.P.x[slot] = 0.0f;
+        }
+        if (dropped) atomicOr(cx.err, E_CAP);
+        count_by_tube(cx.shard, tube, C_CONV, 1);
+        if (__ballot(dropped != 0)) count_by_tube(cx.shard, dropped ? tube : -1, C_DROPPED, dropped);
+      }
     }
   }
 }
@@ -1128,13 +1150,41 @@ struct RbCtx {
   const int32_t* tt;
   int32_t* tcount;       // live particles per tile
   int32_t* tcursor;
+  // photons only: within a tile the particles that can draw a conversion
+  // before the next re-sort are placed first (thot of them per tile, placed
+  // through tcursor; the others through tcur_cold after them), so that the
+  // conversion draws read their ids from few cache lines
+  int32_t* thot;
+  int32_t* tcur_cold;
+  uint8_t* hflag;        // per source slot: the hot flag the count kernel decided
+  int window;            // steps until the next re-sort
   long long* tchunk;     // first chunk of each tile in the new layout (n_tiles + 1)
   int n_tiles;
 };
 
+// A photon is hot when its conversion probability at the end of the coming
+// re-sort window is high enough to be drawn (p > 2^-25): chi, and with it p,
+// only grows with the photon's age while its angle stays below pi/2, so the
+// cold ones draw no conversion before the next re-sort.  (A layout choice
+// only: no result depends on slot order.)
+__device__ __forceinline__ bool rb_hot(const RbCtx<LepBuf>&, const Tube&, long long) { return false; }
+__device__ __forceinline__ bool rb_hot(const RbCtx<PhoBuf>& cx, const Tube& T, long long slot) {
+  const float x = cx.src.x[slot];
+  const int32_t age = (int32_t)((uint32_t)T.step + (uint32_t)cx.window - (uint32_t)cx.src.n0[slot]);
+  const float a = (float)age * T.dt * T.inv_rc;
+  const float sp = fabsf(a) < 1.5f ? fabsf(sinf(a)) : 1.0f;
+  const float chi = fabsf(x) * T.b * sp;
+  return chi > T.chi_skip && T.conv_k * sp * t_bw(chi) > 2.9802322e-8f;
+}
+
 // Tile (new) of the particle in `slot`, or -1 if the slot is dead/empty.
+// hot: computed (decide) or read back from the count kernel's decision; the
+// scatter must place exactly the particles the count kernel counted as hot
+// (a recomputed flag could differ in its last rounding between kernels).
 template <class B>
-__device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int tile_old, int* cell_out, uint32_t* frac_out) {
+__device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int tile_old, int* cell_out, uint32_t* frac_out,
+                                         bool* hot, bool decide) {
+  *hot = false;
   if (tile_old < 0 || !rec_alive<B>(cx.src, slot)) return -1;
   const Tile tl = cx.tiles[tile_old];
   const Tube& T = cx.tubes[tl.tube];
@@ -1143,6 +1193,14 @@ __device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int
   if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
   *cell_out = cell;
   *frac_out = pos & 0xFFFFFFu;
+  if (std::is_same<B, PhoBuf>::value) {
+    if (decide) {
+      *hot = rb_hot(cx, T, slot);
+      cx.hflag[slot] = *hot ? 1 : 0;
+    } else {
+      *hot = cx.hflag[slot] != 0;
+    }
+  }
   return T.tile_first + cell / TILE;
 }
 
@@ -1191,26 +1249,37 @@ __device__ __forceinline__ int rb_wave_add(int k, int* lds_bins, int dlo, int* g
 
 template <class B>
 __global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
+  constexpr bool PHO = std::is_same<B, PhoBuf>::value;
   __shared__ int s_h[RB_HW];
+  __shared__ int s_hot[PHO ? RB_HW : 1];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
   rb_range(nq, &c0, &c1);
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
+    s_h[j] = 0;
+    if (PHO) s_hot[j] = 0;
+  }
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell; uint32_t frac;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    int cell; uint32_t frac; bool hot;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, true);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
     rb_wave_add(inw ? nt : -1, s_h, dlo, cx.tcount, true, false);
     rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcount, false, false);
+    if (PHO) {
+      rb_wave_add((inw && hot) ? nt : -1, s_hot, dlo, cx.thot, true, false);
+      rb_wave_add((nt >= 0 && !inw && hot) ? nt : -1, s_hot, dlo, cx.thot, false, false);
+    }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
     if (s_h[j] > 0) atomicAdd(&cx.tcount[dlo + j], s_h[j]);
+    if (PHO && s_hot[j] > 0) atomicAdd(&cx.thot[dlo + j], s_hot[j]);
+  }
 }
 
 // Exclusive scan of the padded chunk counts over all tiles (one workgroup).
@@ -1221,7 +1290,11 @@ __global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
   for (int base = 0; base < cx.n_tiles; base += 1024) {
     const int t = base + threadIdx.x;
     long long v = 0;
-    if (t < cx.n_tiles) { v = (cx.tcount[t] + CHUNK - 1) / CHUNK; cx.tcursor[t] = 0; }
+    if (t < cx.n_tiles) {
+      v = (cx.tcount[t] + CHUNK - 1) / CHUNK;
+      cx.tcursor[t] = 0;
+      if (cx.tcur_cold) cx.tcur_cold[t] = 0;
+    }
     long long incl = v;
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) {
@@ -1272,32 +1345,40 @@ __global__ void k_rb_chunks(RbCtx<B> cx) {
 
 template <class B>
 __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
-  __shared__ int s_h[RB_HW];
-  __shared__ long long s_base[RB_HW];
+  constexpr bool PHO = std::is_same<B, PhoBuf>::value;
+  constexpr int NC = PHO ? 2 : 1;       // classes within a tile: hot first, then cold
+  __shared__ int s_h[NC][RB_HW];
+  __shared__ long long s_base[NC][RB_HW];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
   rb_range(nq, &c0, &c1);
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
+    for (int k = 0; k < NC; ++k) s_h[k][j] = 0;
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
-  // pass A: how many of this range go to each window tile
+  // pass A: how many of this range go to each window tile (per class)
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell; uint32_t frac;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    int cell; uint32_t frac; bool hot;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, false);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    rb_wave_add(inw ? nt : -1, s_h, dlo, nullptr, true, false);
+    const int k = (PHO && !hot) ? 1 : 0;
+    for (int kk = 0; kk < NC; ++kk) rb_wave_add((inw && k == kk) ? nt : -1, s_h[kk], dlo, nullptr, true, false);
   }
   __syncthreads();
-  // one reservation per (workgroup, tile)
+  // one reservation per (workgroup, tile, class)
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
-    const int n = s_h[j];
-    if (n > 0) {
-      const int t = dlo + j;
-      s_base[j] = cx.tchunk[t] * CHUNK + atomicAdd(&cx.tcursor[t], n);
-      s_h[j] = 0;
+    for (int k = 0; k < NC; ++k) {
+      const int n = s_h[k][j];
+      if (n > 0) {
+        const int t = dlo + j;
+        s_base[k][j] = cx.tchunk[t] * CHUNK +
+                       (k == 0 ? (long long)atomicAdd(&cx.tcursor[t], n)
+                               : (long long)cx.thot[t] + atomicAdd(&cx.tcur_cold[t], n));
+        s_h[k][j] = 0;
+      }
     }
   }
   __syncthreads();
@@ -1305,13 +1386,20 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   for (long long c = c0; c < c1; ++c) {
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell = 0; uint32_t frac = 0;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac);
+    int cell = 0; uint32_t frac = 0; bool hot;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, false);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    const int ri = rb_wave_add(inw ? nt : -1, s_h, dlo, nullptr, true, true);
-    const int ro = rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcursor, false, true);
+    const int k = (PHO && !hot) ? 1 : 0;
+    int ri = -1, ro = -1;
+    for (int kk = 0; kk < NC; ++kk) {
+      const int r1 = rb_wave_add((inw && k == kk) ? nt : -1, s_h[kk], dlo, nullptr, true, true);
+      const int r2 = rb_wave_add((nt >= 0 && !inw && k == kk) ? nt : -1, s_h[kk], dlo,
+                                 kk == 0 ? cx.tcursor : cx.tcur_cold, false, true);
+      if (k == kk) { ri = r1; ro = r2; }
+    }
     if (nt >= 0) {
-      const long long dst = inw ? s_base[nt - dlo] + ri : cx.tchunk[nt] * CHUNK + ro;
+      const long long dst = inw ? s_base[k][nt - dlo] + ri
+                                : cx.tchunk[nt] * CHUNK + (k == 0 ? 0 : (long long)cx.thot[nt]) + ro;
       const Tile tl = cx.tiles[nt];
       rec_copy(cx.src, slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
     }

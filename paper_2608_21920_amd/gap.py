@@ -25,7 +25,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING = range(9)
-STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE = range(6)
+STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH = range(7)
 TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail", "conversions"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
@@ -259,6 +259,11 @@ class Gap:
     def set_drive(self, alpha: float, inj_weight: float, tube: int = 0):
         buf = np.array([alpha, inj_weight], np.float64)
         _check(self.lib.gap_set_state(self.h, STATE_DRIVE, int(tube), buf.ctypes.data, buf.nbytes), "set_drive")
+
+    def set_launch(self, grid_leptons: int, grid_photons: int, grid_tails: int, resort_every: int):
+        """Launch shapes and re-sort interval (the keys autotune() returns)."""
+        buf = np.array([grid_leptons, grid_photons, grid_tails, resort_every], np.int32)
+        _check(self.lib.gap_set_state(self.h, STATE_LAUNCH, 0, buf.ctypes.data, buf.nbytes), "set_launch")
 
     def autotune(self, trial_steps: int = 32) -> dict:
         """Tune the launch shapes and the re-sort interval on real steps

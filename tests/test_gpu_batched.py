@@ -74,3 +74,35 @@ def test_ensemble_graph_equals_single_tubes(torch_gpu):
             g1.close()
         assert gb.counts(0)["err"] == 0
         gb.close()
+
+
+def test_launch_shapes_change_no_result(torch_gpu):
+    from paper_2608_21920_amd import gap as G
+    _say("case: explicit launch shapes on the tiny gap")
+    cfg = dict(workloads.TINY, n_cells=512)
+    a, b = Gap(cfg), Gap(cfg)
+    a.set_launch(8, 16, 64, 5)
+    a.step(70)
+    b.step(70)
+    _same(a, 0, b, 0)
+    for bad in ((0, 16, 64, 5), (12, 16, 64, 5), (8, 16, 64, 0), (8, 16, 64, 100000), (8, 1 << 20, 64, 5)):
+        with pytest.raises(G.GapError):
+            a.set_launch(*bad)
+    a.close()
+    b.close()
+
+
+def test_autotune_keeps_the_drift_bound(torch_gpu):
+    # the tuning trials leave many steps since the last re-sort when the
+    # re-sort interval candidates are tried; those steps must count toward
+    # the next re-sort (else particles drift out of their tile windows and
+    # the library reports GAP_ETILE)
+    _say("case: autotune with 16-step trials on the tiny gap")
+    g = Gap(dict(workloads.TINY))
+    g.step(50)
+    ch = g.autotune(16)
+    _say("  chosen", ch)
+    g.step(20)
+    g.sync()
+    assert g.counts()["err"] == 0
+    g.close()
