@@ -1,7 +1,7 @@
-"""Parity at the production size, in the launch configuration that the
-benchmark times: the production gap (65536 cells, caps 5e7 per species)
-grown by the simulation itself to 2e7 particles, then stepped by the plain
-eager path.
+"""Parity at full size, in the launch configuration that the benchmark
+times: the production gap (65536 cells, caps 5e7 per species) and the
+full-scale gap (262144 cells, b = 0.2, caps 2e8), each grown by the
+simulation itself to 2e7 particles, then stepped by the plain eager path.
 
  * One step from the grown state on both sides (the oracle loads the GPU's
    whole state, ~2e7 particles): the node charge of the loaded state is
@@ -30,7 +30,7 @@ from gpu_util import by_id, rel_field_err
 pytestmark = pytest.mark.gpu
 
 GROW_TO = 2.0e7
-CFG = dict(workloads.PRODUCTION)
+WORKLOADS = {"production": workloads.PRODUCTION, "full": workloads.FULL}
 
 
 def _say(*a):
@@ -38,23 +38,24 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def grown():
+@pytest.fixture(scope="module", params=sorted(WORKLOADS))
+def grown(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    _say("case: production gap grown to %.0e particles" % GROW_TO)
+    cfg = dict(WORKLOADS[request.param])
+    _say("case: %s gap (%d cells) grown to %.0e particles" % (request.param, cfg["n_cells"], GROW_TO))
     s = torch.cuda.Stream()
-    g = Gap(CFG, stream=s)
+    g = Gap(cfg, stream=s)
     while True:
         c = g.counts()
         if c["n_lep"] + c["n_pho"] >= GROW_TO:
             break
-        assert c["step"] < 90000 and c["err"] == 0
+        assert c["step"] < 200000 and c["err"] == 0
         g.step(2000)
         g.sync()
     _say("  grown: step %d, %d leptons, %d photons" % (c["step"], c["n_lep"], c["n_pho"]))
-    yield g, s
+    yield g, s, cfg
     g.close()
 
 
@@ -65,7 +66,7 @@ def _match(A, B):
 
 
 def test_one_step_from_grown_state_matches_oracle(grown):
-    g, _ = grown
+    g, _, CFG = grown
     c0 = g.counts()
     n = c0["step"]
     L0, P0 = g.leptons(), g.photons()
@@ -143,7 +144,7 @@ def test_one_step_from_grown_state_matches_oracle(grown):
 
 
 def test_counter_balance_and_unique_ids(grown):
-    g, _ = grown
+    g, _, CFG = grown
     c0 = g.counts()
     g.step(5)
     c1 = g.counts()
@@ -160,7 +161,7 @@ def test_counter_balance_and_unique_ids(grown):
 
 def test_graph_replay_on_reloaded_state_equals_eager(grown):
     import torch
-    g, s = grown
+    g, s, CFG = grown
     c0 = g.counts()
     L0, P0 = g.leptons(), g.photons()
     g.set_injection(0.0, c0["n_injected"])
