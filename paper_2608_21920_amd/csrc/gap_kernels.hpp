@@ -1225,6 +1225,19 @@ __device__ __forceinline__ void rb_range(long long nch, long long* c0, long long
   *c1 = nch * (r + 1) / G;
 }
 
+// Rows (256-slot pieces) of this workgroup in a re-sort pass: a contiguous
+// range [c0, c1) of the sorted rows (so that the LDS window of destination
+// tiles applies), then every G-th row of the tail.  Tail particles are in no
+// tile order and cost more per row; striding them over all workgroups keeps
+// the pass balanced.
+__device__ __forceinline__ long long rb_nrows(long long c0, long long c1, long long nsq, long long nq) {
+  const long long nt = nq - nsq - (long long)blockIdx.x;
+  return (c1 - c0) + (nt > 0 ? (nt + gridDim.x - 1) / gridDim.x : 0);
+}
+__device__ __forceinline__ long long rb_row(long long i, long long c0, long long c1, long long nsq) {
+  return i < c1 - c0 ? c0 + i : nsq + (long long)blockIdx.x + (i - (c1 - c0)) * (long long)gridDim.x;
+}
+
 // Wave-aggregated add of 1 per lane to bin `k` (k < 0: no-op).  `lds`: bins
 // are LDS entries relative to dlo, else global tile counters.  Returns this
 // lane's rank-based position (old value + rank) when `ret` is set.
@@ -1255,14 +1268,16 @@ __global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
-  rb_range(nq, &c0, &c1);
+  rb_range(nsq, &c0, &c1);
+  const long long nrow = rb_nrows(c0, c1, nsq, nq);
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
     s_h[j] = 0;
     if (PHO) s_hot[j] = 0;
   }
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
-  for (long long c = c0; c < c1; ++c) {
+  for (long long i = 0; i < nrow; ++i) {
+    const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell; uint32_t frac; bool hot;
@@ -1352,13 +1367,15 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
-  rb_range(nq, &c0, &c1);
+  rb_range(nsq, &c0, &c1);
+  const long long nrow = rb_nrows(c0, c1, nsq, nq);
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
     for (int k = 0; k < NC; ++k) s_h[k][j] = 0;
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   // pass A: how many of this range go to each window tile (per class)
-  for (long long c = c0; c < c1; ++c) {
+  for (long long i = 0; i < nrow; ++i) {
+    const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell; uint32_t frac; bool hot;
@@ -1383,7 +1400,8 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   }
   __syncthreads();
   // pass B: place the records
-  for (long long c = c0; c < c1; ++c) {
+  for (long long i = 0; i < nrow; ++i) {
+    const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
     int cell = 0; uint32_t frac = 0; bool hot;
