@@ -515,7 +515,7 @@ void win_release(gap_t* g) {
 // One step of a window: no merge, no re-sort (slots stay put).
 void enqueue_window_step(gap_t* g) {
   Ctx cx = make_ctx(g);
-  k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
+  k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
   k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
   k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
@@ -696,7 +696,7 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
     // recompute the segment, taping the lepton store before each step
     for (int64_t j = 0; j < Ks; ++j) {
       Ctx cx = make_ctx(g);
-      k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes);
+      k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
       k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + j * M, w.tu + j * M, w.wlast, w.meta + j,
                                       w.M, 0, g->err);
       D2D(w.teb + j * (size_t)g->total_nodes, g->ebar, sizeof(float) * g->total_nodes);
@@ -773,7 +773,7 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
 void enqueue_step(gap_t* g) {
   if (g->merge_on && g->host_step % g->merge_every == 0) merge_all(g);
   Ctx cx = make_ctx(g);
-  { Timer t(g, KT_PRE); k_pre<<<1, 64, 0, g->s>>>(cx, g->n_tubes); }
+  { Timer t(g, KT_PRE); k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes); }
   // The two species' passes touch disjoint data: each reads its own store
   // up to the tail snapshot of the prologue and appends the other species'
   // births past that snapshot; only the leptons deposit charge.  The photon

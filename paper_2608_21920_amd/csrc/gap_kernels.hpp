@@ -173,30 +173,40 @@ __device__ __forceinline__ void clamp_tail(Ctl* c) {
   if (c->tail > room) c->tail = room;
 }
 
-__global__ void k_pre(Ctx cx, int n_tubes) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  // the passes of this step read its index from step_now: the field update
-  // (which counts the step) may run beside the photon pass
-  for (int t = 0; t < n_tubes; ++t) cx.tubes[t].step_now = cx.tubes[t].step;
+constexpr int PRE_THREADS = 1024;
+
+// One workgroup; thread t handles tubes t, t + PRE_THREADS, ...  Each tube's
+// injected electrons take tail slots through one atomic reservation (the
+// order of tail slots changes no result).
+__global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
   // (appends never leave the tails past the limit; the passes below stay
   // inside the stores whatever the tails hold)
-  clamp_tail(cx.lc);
-  clamp_tail(cx.pc);
-  cx.lc->tail_pre = cx.lc->tail;
-  for (int t = 0; t < n_tubes; ++t) {
+  if (threadIdx.x == 0) {
+    clamp_tail(cx.lc);
+    clamp_tail(cx.pc);
+    cx.lc->tail_pre = cx.lc->tail;
+  }
+  __syncthreads();
+  const long long S = cx.lc->n_sorted_chunks * CHUNK;
+  const long long lim = cx.lc->limit;
+  for (int t = threadIdx.x; t < n_tubes; t += blockDim.x) {
     Tube& T = cx.tubes[t];
+    // the passes of this step read its index from step_now: the field
+    // update (which counts the step) may run beside the photon pass
+    T.step_now = T.step;
     if (T.inj_per_step <= 0.0 || (T.flags & F_PERIODIC)) continue;
     T.inj_acc += T.inj_per_step;
-    double fl = floor(T.inj_acc);
+    const double fl = floor(T.inj_acc);
     T.inj_acc -= fl;
-    int m = (int)fl;
+    const int m = (int)fl;
+    if (m <= 0) continue;
+    const long long first = S + (long long)atomicAdd((unsigned long long*)&cx.lc->tail, (unsigned long long)m);
     const Tile& tl = cx.tiles[T.tile_first];
     for (int j = 0; j < m; ++j) {
-      long long slot = cx.lc->n_sorted_chunks * CHUNK + cx.lc->tail;
-      if (slot >= cx.lc->limit) { T.cnt[C_DROPPED]++; atomicOr(cx.err, E_CAP); continue; }
-      cx.lc->tail++;
-      uint64_t id = (1ull << 62) + T.inj_count++;
-      u4 r = draw(T.seed, id, T.step, T_INJ, 0);
+      const long long slot = first + j;
+      if (slot >= lim) { T.cnt[C_DROPPED]++; atomicOr(cx.err, E_CAP); continue; }
+      const uint64_t id = (1ull << 62) + T.inj_count++;
+      const u4 r = draw(T.seed, id, T.step, T_INJ, 0);
       cx.L.pos[slot] = ((uint32_t)(0 - tl.base) << FRAC) | (r.a >> 8);
       cx.L.u[slot] = 0.0f;
       cx.L.w[slot] = -T.inj_w;
@@ -206,8 +216,12 @@ __global__ void k_pre(Ctx cx, int n_tubes) {
       T.cnt[C_INJECTED]++;
     }
   }
-  cx.lc->tail_snap = cx.lc->tail;
-  cx.pc->tail_snap = cx.pc->tail;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    clamp_tail(cx.lc);               // (reservations past the limit were dropped)
+    cx.lc->tail_snap = cx.lc->tail;
+    cx.pc->tail_snap = cx.pc->tail;
+  }
 }
 
 // ------------------------------------------------------------------ leptons
