@@ -195,6 +195,7 @@ struct gap_t {
   // pass and the field update (fork and join through the two events)
   hipStream_t s2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool capturing = false;   // graph capture: the photon pass stays on the caller's stream
   gap_allocator al{};
   bool custom_alloc = false;
   std::vector<void*> owned;
@@ -273,8 +274,19 @@ void* dalloc(gap_t* g, size_t bytes) {
 
 void win_release(gap_t* g);
 
+// A graph exec may only be destroyed once no launch of it is in flight: wait
+// for both streams of the handle first.
+void drop_graph(gap_t* g) {
+  if (!g->gexec) return;
+  if (g->s2) (void)hipStreamSynchronize(g->s2);
+  (void)hipStreamSynchronize(g->s);
+  (void)hipGraphExecDestroy(g->gexec);
+  g->gexec = nullptr;
+  g->gsteps = -1;
+}
+
 void release(gap_t* g) {
-  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
+  drop_graph(g);
   if (g->s) (void)hipStreamSynchronize(g->s);
   if (g->s2) { (void)hipStreamSynchronize(g->s2); (void)hipStreamDestroy(g->s2); g->s2 = nullptr; }
   if (g->ev_fork) { (void)hipEventDestroy(g->ev_fork); g->ev_fork = nullptr; }
@@ -779,16 +791,21 @@ void enqueue_step(gap_t* g) {
   // births past that snapshot; only the leptons deposit charge.  The photon
   // pass runs on the second stream while the lepton pass and the field
   // update run on the caller's; the re-sort and the next step wait for both.
-  (void)hipEventRecord(g->ev_fork, g->s);
-  (void)hipStreamWaitEvent(g->s2, g->ev_fork, 0);
-  { Timer t(g, KT_PHOTONS, g->s2); k_photons<<<g->grid_pho, TPB, 0, g->s2>>>(cx); }
-  { Timer t(g, KT_CONV, g->s2); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s2>>>(cx, g->grid_pho); }
-  { Timer t(g, KT_PHOTAIL, g->s2); k_photons_tail<<<g->grid_tail, TPB, 0, g->s2>>>(cx); }
-  (void)hipEventRecord(g->ev_join, g->s2);
+  // Captured graphs keep every kernel on the caller's stream (no fork and
+  // join inside a graph).
+  hipStream_t ps = g->capturing ? g->s : g->s2;
+  if (!g->capturing) {
+    (void)hipEventRecord(g->ev_fork, g->s);
+    (void)hipStreamWaitEvent(g->s2, g->ev_fork, 0);
+  }
+  { Timer t(g, KT_PHOTONS, ps); k_photons<<<g->grid_pho, TPB, 0, ps>>>(cx); }
+  { Timer t(g, KT_CONV, ps); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, ps>>>(cx, g->grid_pho); }
+  { Timer t(g, KT_PHOTAIL, ps); k_photons_tail<<<g->grid_tail, TPB, 0, ps>>>(cx); }
+  if (!g->capturing) (void)hipEventRecord(g->ev_join, g->s2);
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
-  (void)hipStreamWaitEvent(g->s, g->ev_join, 0);
+  if (!g->capturing) (void)hipStreamWaitEvent(g->s, g->ev_join, 0);
   if (++g->since_rb >= g->R) {
     Timer t(g, KT_RESORT);
     rebucket_all(g);
@@ -1105,11 +1122,13 @@ int export_store(gap_t* g, const Store& st, bool photon, int tube, std::vector<H
 }
 
 int graph_capture(gap_t* g, int64_t n) {
-  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
+  drop_graph(g);
   g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_since = g->since_rb; g->gs_step = g->host_step;
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal));
+  g->capturing = true;
   for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  g->capturing = false;
   hipError_t e = hipStreamEndCapture(g->s, &graph);
   g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_since = g->since_rb;
   // nothing ran yet: back to the start state
@@ -1152,7 +1171,7 @@ int timed_steps(gap_t* g, int64_t n, double* kt, double* wall_ms) {
 int autotune(gap_t* g, int trial, int32_t* chosen) {
   const bool was = g->timing;
   g->timing = true;
-  if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; g->gsteps = -1; }
+  drop_graph(g);
   double kt[KT_N], wall;
   int e;
   auto cands = [](int round, int lo) {
@@ -1419,7 +1438,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     g->grid_pho = v[1];
     g->grid_tail = v[2];
     g->R = v[3];
-    if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; g->gsteps = -1; }
+    drop_graph(g);
     return GAP_OK;
   }
   g->win.valid = false;     // any other state change ends a pending window

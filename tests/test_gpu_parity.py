@@ -265,3 +265,28 @@ def test_store_overflow_reports_ecap(torch_gpu):
     assert c["n_dropped"] > 0
     assert P.size <= 3000 + 2 * 4 * 1024 + 1024
     g.close()
+
+
+def test_graph_recapture_while_a_replay_is_in_flight(torch_gpu):
+    # one re-sort per 16-step replay flips the store buffers, so the second of
+    # two back-to-back replays captures a new graph while the first still
+    # runs; the old graph is released only after both streams are idle
+    _say("case: back-to-back graph replays that re-capture")
+    import torch
+    cfg = dict(TINY, n_cells=512)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ga = Gap(cfg, stream=s)
+        ga.set_launch(8, 16, 64, 16)
+        for _ in range(4):
+            ga.step_graph(16)
+        ga.sync()
+        gb = Gap(cfg, stream=s)
+        gb.step(64)
+        A, B = by_id(gpu_leptons_as_oracle(ga.leptons())), by_id(gpu_leptons_as_oracle(gb.leptons()))
+        for k in ("cell", "xi", "u", "w", "id"):
+            assert np.array_equal(A[k], B[k]), k
+        assert np.array_equal(ga.field(), gb.field())
+        assert ga.counts()["err"] == 0
+        ga.close()
+        gb.close()
