@@ -142,10 +142,11 @@ struct Store {
   int32_t* tt = nullptr;
   int32_t* chunk[2] = {nullptr, nullptr};
   int32_t* tcount = nullptr;
-  int32_t* tcursor = nullptr;
-  int32_t* thot = nullptr;        // photons: hot particles per tile at a re-sort
-  int32_t* tcur_cold = nullptr;
-  uint8_t* hflag = nullptr;       // photons: hot flag per slot
+  int nclass = 1;                 // placement classes within a tile at a re-sort
+  int32_t* ccount = nullptr;      // [nclass - 1][n_tiles]: particles of the leading classes per tile
+  int32_t* ccur = nullptr;        // [nclass][n_tiles]: placement cursors
+  uint8_t* cls = nullptr;         // class of each slot, decided by the count kernel
+  uint16_t* chot = nullptr;       // photons: hot slots at the start of each sorted chunk
   long long* tchunk = nullptr;
   int64_t capacity = 0, limit = 0, cap_live = 0;
   LepBuf lep(int b) const { return LepBuf{pos[b], a[b], w[b], id[b]}; }
@@ -358,6 +359,7 @@ Ctx make_ctx(gap_t* g) {
   c.P = g->pho.pho(g->pho.cur);
   c.pc = g->pho.ctl;
   c.pchunk = g->pho.chunk[g->pho.cur];
+  c.pchot = g->pho.chot;
   c.ptt = g->pho.tt;
   c.rho = g->rho;
   c.ebar = g->ebar;
@@ -411,6 +413,8 @@ FieldCtx make_fctx(gap_t* g, int mode) {
   return f;
 }
 
+__global__ void k_cold_off(Ctl* c) { c->cold_steps = -1; }
+
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -430,16 +434,16 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst) {
   cx.chunk_new = st.chunk[st.cur ^ 1];
   cx.tt = st.tt;
   cx.tcount = st.tcount;
-  cx.tcursor = st.tcursor;
-  cx.thot = st.thot;
-  cx.tcur_cold = st.tcur_cold;
-  cx.hflag = st.hflag;
+  cx.ccount = st.ccount;
+  cx.ccur = st.ccur;
+  cx.cls = st.cls;
+  cx.chot = st.chot;
   cx.window = g->R;
   cx.tchunk = st.tchunk;
   cx.n_tiles = g->n_tiles;
   const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
   k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
-  if (st.thot) k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.thot, g->n_tiles, 0);
+  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
   k_rb_count<B><<<kGrid, TPB, 0, g->s>>>(cx);
   k_rb_scan<B><<<1, 1024, 0, g->s>>>(cx);
   k_rb_chunks<B><<<kGrid, 256, 0, g->s>>>(cx);
@@ -593,8 +597,12 @@ int restore_ckpt(gap_t* g, const WinCkpt& c) {
     D2D(P.pos[bp], c.ppos, np * 4); D2D(P.a[bp], c.px, np * 4); D2D(P.w[bp], c.pw, np * 4);
     D2D(P.n0[bp], c.pn0, np * 4); D2D(P.id[bp], c.pid, np * 8); D2D(P.chunk[bp], c.pchunk, (size_t)c.nch_p * 4);
   }
-  HIPCHK(hipMemcpyAsync(L.ctl, &c.lctl, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
-  HIPCHK(hipMemcpyAsync(P.ctl, &c.pctl, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
+  // the saved layout's hot prefixes are not kept: no cold guarantee until
+  // the next re-sort
+  Ctl lc = c.lctl, pc = c.pctl;
+  lc.cold_steps = pc.cold_steps = -1;
+  HIPCHK(hipMemcpyAsync(L.ctl, &lc, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
+  HIPCHK(hipMemcpyAsync(P.ctl, &pc, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
   D2D(g->tubes, c.tubes, sizeof(Tube) * g->n_tubes);
   D2D(g->ebar, c.ebar, sizeof(float) * g->total_nodes);
   D2D(g->E, c.E, sizeof(float) * g->total_cells);
@@ -851,20 +859,23 @@ int alloc_store(gap_t* g, Store& st, int64_t cap, bool photon) {
   }
   st.tt = (int32_t*)dalloc(g, n * 4);
   st.tcount = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
-  st.tcursor = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
+  st.nclass = photon ? RbClasses<PhoBuf>::N : RbClasses<LepBuf>::N;
+  st.ccount = (int32_t*)dalloc(g, (size_t)(st.nclass - 1) * g->n_tiles * 4);
+  st.ccur = (int32_t*)dalloc(g, (size_t)st.nclass * g->n_tiles * 4);
+  st.cls = (uint8_t*)dalloc(g, (size_t)st.capacity);
+  if (!st.ccount || !st.ccur || !st.cls) return GAP_ENOMEM;
   if (photon) {
-    st.thot = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
-    st.tcur_cold = (int32_t*)dalloc(g, (size_t)g->n_tiles * 4);
-    st.hflag = (uint8_t*)dalloc(g, (size_t)st.capacity);
-    if (!st.thot || !st.tcur_cold || !st.hflag) return GAP_ENOMEM;
+    st.chot = (uint16_t*)dalloc(g, (n / CHUNK + 1) * 2);
+    if (!st.chot) return GAP_ENOMEM;
   }
   st.tchunk = (long long*)dalloc(g, ((size_t)g->n_tiles + 1) * 8);
   st.ctl = (Ctl*)dalloc(g, sizeof(Ctl));
-  if (!st.tt || !st.tcount || !st.tcursor || !st.tchunk || !st.ctl) return GAP_ENOMEM;
+  if (!st.tt || !st.tcount || !st.tchunk || !st.ctl) return GAP_ENOMEM;
   Ctl c{};
   c.capacity = st.capacity;
   c.limit = st.limit;
   c.cap_live = cap;
+  c.cold_steps = -1;
   if (hipMemcpyAsync(st.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, g->s) != hipSuccess) return GAP_EDEVICE;
   return GAP_OK;
 }
@@ -1078,6 +1089,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     c.limit = g->lep.limit;
     c.cap_live = g->lep.cap_live;
     c.tail = total;
+    c.cold_steps = -1;
     HIPCHK(hipMemcpyAsync(g->lep.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
   }
   rebucket_all(g);
@@ -1442,6 +1454,9 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     return GAP_OK;
   }
   g->win.valid = false;     // any other state change ends a pending window
+  // and the photon store's cold guarantee (a tube's step or parameters may
+  // change); the next re-sort restores it
+  k_cold_off<<<1, 1, 0, g->s>>>(g->pho.ctl);
   if (kind == GAP_STATE_DRIVE) {
     if (bytes < 16) return GAP_EINVAL;
     double v[2];

@@ -95,6 +95,10 @@ struct Ctl {                  // control block of one store
   int64_t total_chunks_new;   // written by the re-sort scan
   int64_t cap_live;           // live-particle cap (merge threshold reference)
   int64_t tail_pre;           // tail length before this step's injection
+  // photons: steps left in which no slot past a tile's hot prefix of the
+  // sorted region can draw a conversion (set by the re-sort, counted down by
+  // each step's prologue; < 0: no such guarantee)
+  int64_t cold_steps;
 };
 
 struct LepBuf { uint32_t* pos; float* u; float* w; uint64_t* id; };

@@ -19,6 +19,7 @@ struct Ctx {
   PhoBuf P;
   Ctl* pc;
   const int32_t* pchunk;
+  const uint16_t* pchot;  // hot slots at the start of each sorted chunk
   int32_t* ptt;
   // grid
   long long* rho;         // node charge accumulator, sum_t (N_t + 1)
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
     clamp_tail(cx.lc);
     clamp_tail(cx.pc);
     cx.lc->tail_pre = cx.lc->tail;
+    if (cx.pc->cold_steps >= 0) cx.pc->cold_steps -= 1;
   }
   __syncthreads();
   const long long S = cx.lc->n_sorted_chunks * CHUNK;
@@ -734,22 +736,26 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   }
 }
 
-struct Pho4 { float4 x; uint4 pos; int4 n0; int tile; uint32_t slot0; };
+struct Pho4 { float4 x; uint4 pos; int4 n0; int tile; int hot; uint32_t slot0; };
 
-__device__ __forceinline__ Pho4 pho_load4(const Ctx& cx, long long c) {
+// One chunk's records for this thread.  hot: the chunk's leading slots that
+// may draw (all of them without the re-sort's guarantee); a chunk with none
+// does not need the birth steps.
+__device__ __forceinline__ Pho4 pho_load4(const Ctx& cx, long long c, bool cold_ok) {
   Pho4 r;
   r.slot0 = (uint32_t)c * CHUNK + VEC * threadIdx.x;
   r.tile = cx.pchunk[c];
+  r.hot = cold_ok ? (int)cx.pchot[c] : CHUNK;
   r.x = *reinterpret_cast<const float4*>(cx.P.x + r.slot0);
   r.pos = *reinterpret_cast<const uint4*>(cx.P.pos + r.slot0);
-  r.n0 = *reinterpret_cast<const int4*>(cx.P.n0 + r.slot0);
+  r.n0 = r.hot > 0 ? *reinterpret_cast<const int4*>(cx.P.n0 + r.slot0) : make_int4(0, 0, 0, 0);
   return r;
 }
 
 // Sorted photon pass, first half for one photon: free streaming, exit, and
 // the conversion probability.  Gives the new position, the energy (0 once
 // the photon has left) and whether a conversion draw is due.
-__device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x, uint32_t pos, int32_t n0,
+__device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x, uint32_t pos, int32_t n0, bool may_draw,
                                             LocalCounts& lcn, uint32_t* pos_out, float* x_out, float* p_out,
                                             bool* eval_out) {
   const bool alive = x != 0.0f;
@@ -773,9 +779,10 @@ __device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x,
   }
   const bool exited = alive & !oob & out;
   const bool dead = oob | exited;
-  // the probability is taken for every lane (0 for an empty slot: chi = 0)
-  // and kept for the live ones
-  const float pr = photon_prob(k, x, n0);
+  // the probability is taken for every lane of a wave in which one may draw
+  // (0 for an empty slot: chi = 0) and kept for the live ones; a slot that
+  // cannot draw would get p <= 2^-25 and no draw
+  const float pr = __ballot(may_draw) ? photon_prob(k, x, n0) : 0.0f;
   const float p = (alive & !dead & !(flags & (F_QED_OFF | F_CONV_OFF))) ? pr : 0.0f;
   const bool eval = p > 2.9802322e-8f;   // below 2^-25 no 24-bit uniform can fall under p
   *pos_out = np;
@@ -816,11 +823,12 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
   int ctube = -1;
   KC kc;
   int held = -1;
+  const bool cold_ok = cx.pc->cold_steps >= 0;
   Pho4 cur;
-  if (c0 < c1) cur = pho_load4(cx, c0);
+  if (c0 < c1) cur = pho_load4(cx, c0, cold_ok);
   for (long long c = c0; c < c1; ++c) {
     Pho4 nxt;
-    if (c + 1 < c1) nxt = pho_load4(cx, c + 1);
+    if (c + 1 < c1) nxt = pho_load4(cx, c + 1, cold_ok);
     if (cur.tile != held) {
       held = cur.tile;
       kc = load_kc(cx, held);
@@ -838,7 +846,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
       uint32_t po;
       float xo, pr;
       bool ev;
-      photon_move(cx, kc, x.x, p.x, n0.x, lcn, &po, &xo, &pr, &ev);
+      photon_move(cx, kc, x.x, p.x, n0.x, (int)(VEC * threadIdx.x) + j < cur.hot, lcn, &po, &xo, &pr, &ev);
       xchg |= xo != x.x;
       const uint64_t m = __ballot(ev);
       if (m) {
@@ -1163,42 +1171,71 @@ struct RbCtx {
   int32_t* chunk_new;
   const int32_t* tt;
   int32_t* tcount;       // live particles per tile
-  int32_t* tcursor;
-  // photons only: within a tile the particles that can draw a conversion
-  // before the next re-sort are placed first (thot of them per tile, placed
-  // through tcursor; the others through tcur_cold after them), so that the
-  // conversion draws read their ids from few cache lines
-  int32_t* thot;
-  int32_t* tcur_cold;
-  uint8_t* hflag;        // per source slot: the hot flag the count kernel decided
+  // Within a tile the particles are placed by class (RbClasses<B>::N of
+  // them, class 0 first): photons that can draw a conversion before the next
+  // re-sort ahead of those that cannot, leptons by how close they are to
+  // the emission threshold.  Waves of the particle passes then meet the
+  // rare branches only where their particles need them.
+  int32_t* ccount;       // [N - 1][n_tiles]: particles of classes 0 .. N - 2 per tile
+  int32_t* ccur;         // [N][n_tiles]: placement cursor per class and tile
+  uint8_t* cls;          // per source slot: the class the count kernel decided
+  uint16_t* chot;        // photons, per chunk of the new layout: class-0 slots at its start
   int window;            // steps until the next re-sort
   long long* tchunk;     // first chunk of each tile in the new layout (n_tiles + 1)
   int n_tiles;
 };
 
-// A photon is hot when its conversion probability at the end of the coming
-// re-sort window is high enough to be drawn (p > 2^-25): chi, and with it p,
-// only grows with the photon's age while its angle stays below pi/2, so the
-// cold ones draw no conversion before the next re-sort.  (A layout choice
-// only: no result depends on slot order.)
-__device__ __forceinline__ bool rb_hot(const RbCtx<LepBuf>&, const Tube&, long long) { return false; }
+// A photon is cold when no step of the coming re-sort window can draw its
+// conversion.  Over the window its age runs from a1 to a2; |sin psi| is at
+// most the larger of its values at the two ends while both angles stay
+// within 1.5 rad, and at most 1 otherwise.  The step's exponent
+// alpha_em (b/lambda~) sin psi T_BW(x b sin psi) grows with |sin psi| (the
+// fit's log-derivative in chi stays above -1/3), so its value at that bound
+// caps every step's.  Cold needs the cap at or below 2^-27: a factor 4 under
+// the 2^-25 that a draw needs, far beyond the rounding differences between
+// this FP32 bound and the pass's FP32 probability.  The photon pass skips
+// the probability of cold slots only while the window lasts, so the
+// classification changes no result.
+template <class B> struct RbClasses;
+template <> struct RbClasses<PhoBuf> { static constexpr int N = 2; };
+template <> struct RbClasses<LepBuf> { static constexpr int N = 4; };
+
 __device__ __forceinline__ bool rb_hot(const RbCtx<PhoBuf>& cx, const Tube& T, long long slot) {
   const float x = cx.src.x[slot];
-  const int32_t age = (int32_t)((uint32_t)T.step + (uint32_t)cx.window - (uint32_t)cx.src.n0[slot]);
-  const float a = (float)age * T.dt * T.inv_rc;
-  const float sp = fabsf(a) < 1.5f ? fabsf(sinf(a)) : 1.0f;
+  const uint32_t n0 = (uint32_t)cx.src.n0[slot];
+  const int32_t a1 = (int32_t)((uint32_t)T.step + 1u - n0);
+  const int32_t a2 = (int32_t)((uint32_t)T.step + (uint32_t)cx.window - n0);
+  if (a2 < a1) return true;                 // the 32-bit age wraps inside the window
+  const float s1 = (float)a1 * T.dt * T.inv_rc, s2 = (float)a2 * T.dt * T.inv_rc;
+  const float sp = fmaxf(fabsf(s1), fabsf(s2)) < 1.5f ? fmaxf(fabsf(sinf(s1)), fabsf(sinf(s2))) : 1.0f;
   const float chi = fabsf(x) * T.b * sp;
-  return chi > T.chi_skip && T.conv_k * sp * t_bw(chi) > 2.9802322e-8f;
+  return T.conv_k * sp * t_bw(chi) > 7.4505806e-9f;   // 2^-27
+}
+__device__ __forceinline__ int rb_class(const RbCtx<PhoBuf>& cx, const Tube& T, long long slot, int, uint32_t) {
+  return rb_hot(cx, T, slot) ? 0 : 1;
+}
+// Leptons: class 0 evaluates emission now (x_c >= x_c,floor inside the QED
+// zone, the pass's test on the stored momentum), classes 1 and 2 are within
+// factors 4 and 64 of the threshold in x_c (gamma within 1.6 and 4), class 3
+// is the rest and everything outside the zone.  Those that cross the
+// threshold during the window sit next to the evaluating ones.
+__device__ __forceinline__ int rb_class(const RbCtx<LepBuf>& cx, const Tube& T, long long slot, int cell, uint32_t frac) {
+  if ((T.flags & (F_QED_OFF | F_EMIT_OFF)) || ((int64_t)cell << FRAC) + frac >= T.hfix) return 3;
+  const float u = cx.src.u[slot];
+  const float g = __builtin_amdgcn_sqrtf(1.0f + u * u);
+  const float xc = 1.5f * g * (g * g * T.lr);
+  return xc >= T.xc_floor ? 0 : xc >= 0.25f * T.xc_floor ? 1 : xc >= (1.0f / 64.0f) * T.xc_floor ? 2 : 3;
 }
 
 // Tile (new) of the particle in `slot`, or -1 if the slot is dead/empty.
-// hot: computed (decide) or read back from the count kernel's decision; the
-// scatter must place exactly the particles the count kernel counted as hot
-// (a recomputed flag could differ in its last rounding between kernels).
+// cls: computed (decide) or read back from the count kernel's decision; the
+// scatter must place exactly the particles the count kernel counted in each
+// class (a recomputed class could differ in its last rounding between
+// kernels).
 template <class B>
 __device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int tile_old, int* cell_out, uint32_t* frac_out,
-                                         bool* hot, bool decide) {
-  *hot = false;
+                                         int* cls, bool decide) {
+  *cls = 0;
   if (tile_old < 0 || !rec_alive<B>(cx.src, slot)) return -1;
   const Tile tl = cx.tiles[tile_old];
   const Tube& T = cx.tubes[tl.tube];
@@ -1207,13 +1244,11 @@ __device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int
   if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
   *cell_out = cell;
   *frac_out = pos & 0xFFFFFFu;
-  if (std::is_same<B, PhoBuf>::value) {
-    if (decide) {
-      *hot = rb_hot(cx, T, slot);
-      cx.hflag[slot] = *hot ? 1 : 0;
-    } else {
-      *hot = cx.hflag[slot] != 0;
-    }
+  if (decide) {
+    *cls = rb_class(cx, T, slot, cell, pos & 0xFFFFFFu);
+    cx.cls[slot] = (uint8_t)*cls;
+  } else {
+    *cls = cx.cls[slot];
   }
   return T.tile_first + cell / TILE;
 }
@@ -1276,42 +1311,38 @@ __device__ __forceinline__ int rb_wave_add(int k, int* lds_bins, int dlo, int* g
 
 template <class B>
 __global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
-  constexpr bool PHO = std::is_same<B, PhoBuf>::value;
+  constexpr int NC = RbClasses<B>::N;
   __shared__ int s_h[RB_HW];
-  __shared__ int s_hot[PHO ? RB_HW : 1];
+  __shared__ int s_c[RB_HW * (NC - 1)];     // (tile - dlo) (NC - 1) + class, classes 0 .. NC - 2
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
   rb_range(nsq, &c0, &c1);
   const long long nrow = rb_nrows(c0, c1, nsq, nq);
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
-    s_h[j] = 0;
-    if (PHO) s_hot[j] = 0;
-  }
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) s_h[j] = 0;
+  for (int j = threadIdx.x; j < RB_HW * (NC - 1); j += blockDim.x) s_c[j] = 0;
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   for (long long i = 0; i < nrow; ++i) {
     const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell; uint32_t frac; bool hot;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, true);
+    int cell; uint32_t frac; int k;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, true);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
     rb_wave_add(inw ? nt : -1, s_h, dlo, cx.tcount, true, false);
     rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcount, false, false);
-    if (PHO) {
-      rb_wave_add((inw && hot) ? nt : -1, s_hot, dlo, cx.thot, true, false);
-      rb_wave_add((nt >= 0 && !inw && hot) ? nt : -1, s_hot, dlo, cx.thot, false, false);
-    }
+    const bool ck = nt >= 0 && k < NC - 1;
+    rb_wave_add((ck && inw) ? (nt - dlo) * (NC - 1) + k : -1, s_c, 0, nullptr, true, false);
+    rb_wave_add((ck && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccount, false, false);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
+  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
     if (s_h[j] > 0) atomicAdd(&cx.tcount[dlo + j], s_h[j]);
-    if (PHO && s_hot[j] > 0) atomicAdd(&cx.thot[dlo + j], s_hot[j]);
-  }
+  for (int j = threadIdx.x; j < RB_HW * (NC - 1); j += blockDim.x)
+    if (s_c[j] > 0) atomicAdd(&cx.ccount[(j % (NC - 1)) * cx.n_tiles + dlo + j / (NC - 1)], s_c[j]);
 }
 
-// Exclusive scan of the padded chunk counts over all tiles (one workgroup).
 template <class B>
 __global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
   __shared__ long long sh[1024 / WAVE];
@@ -1321,8 +1352,7 @@ __global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
     long long v = 0;
     if (t < cx.n_tiles) {
       v = (cx.tcount[t] + CHUNK - 1) / CHUNK;
-      cx.tcursor[t] = 0;
-      if (cx.tcur_cold) cx.tcur_cold[t] = 0;
+      for (int k = 0; k < RbClasses<B>::N; ++k) cx.ccur[k * cx.n_tiles + t] = 0;
     }
     long long incl = v;
 #pragma unroll
@@ -1369,47 +1399,52 @@ __global__ void k_rb_chunks(RbCtx<B> cx) {
       if (cx.tchunk[mid] <= c) lo = mid; else hi = mid;
     }
     cx.chunk_new[c] = lo;
+    if (cx.chot) {
+      const long long h = (long long)cx.ccount[lo] - (c - cx.tchunk[lo]) * CHUNK;
+      cx.chot[c] = (uint16_t)(h < 0 ? 0 : (h > CHUNK ? CHUNK : h));
+    }
   }
+}
+
+// First slot of class k in tile t of the new layout.
+template <class B>
+__device__ __forceinline__ long long rb_class_start(const RbCtx<B>& cx, int t, int k) {
+  long long o = cx.tchunk[t] * CHUNK;
+  for (int j = 0; j < k; ++j) o += cx.ccount[j * cx.n_tiles + t];
+  return o;
 }
 
 template <class B>
 __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
-  constexpr bool PHO = std::is_same<B, PhoBuf>::value;
-  constexpr int NC = PHO ? 2 : 1;       // classes within a tile: hot first, then cold
-  __shared__ int s_h[NC][RB_HW];
-  __shared__ long long s_base[NC][RB_HW];
+  constexpr int NC = RbClasses<B>::N;
+  __shared__ int s_h[RB_HW * NC];            // (tile - dlo) NC + class
+  __shared__ uint32_t s_base[RB_HW * NC];
   const long long nsc = cx.ctl->n_sorted_chunks, S = nsc * CHUNK, tail = cx.ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
   long long c0, c1;
   rb_range(nsq, &c0, &c1);
   const long long nrow = rb_nrows(c0, c1, nsq, nq);
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
-    for (int k = 0; k < NC; ++k) s_h[k][j] = 0;
+  for (int j = threadIdx.x; j < RB_HW * NC; j += blockDim.x) s_h[j] = 0;
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
-  // pass A: how many of this range go to each window tile (per class)
+  // pass A: how many of this range go to each window tile and class
   for (long long i = 0; i < nrow; ++i) {
     const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell; uint32_t frac; bool hot;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, false);
+    int cell, k; uint32_t frac;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, false);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    const int k = (PHO && !hot) ? 1 : 0;
-    for (int kk = 0; kk < NC; ++kk) rb_wave_add((inw && k == kk) ? nt : -1, s_h[kk], dlo, nullptr, true, false);
+    rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, false);
   }
   __syncthreads();
   // one reservation per (workgroup, tile, class)
-  for (int j = threadIdx.x; j < RB_HW; j += blockDim.x) {
-    for (int k = 0; k < NC; ++k) {
-      const int n = s_h[k][j];
-      if (n > 0) {
-        const int t = dlo + j;
-        s_base[k][j] = cx.tchunk[t] * CHUNK +
-                       (k == 0 ? (long long)atomicAdd(&cx.tcursor[t], n)
-                               : (long long)cx.thot[t] + atomicAdd(&cx.tcur_cold[t], n));
-        s_h[k][j] = 0;
-      }
+  for (int j = threadIdx.x; j < RB_HW * NC; j += blockDim.x) {
+    const int n = s_h[j];
+    if (n > 0) {
+      const int t = dlo + j / NC, k = j % NC;
+      s_base[j] = (uint32_t)(rb_class_start(cx, t, k) + atomicAdd(&cx.ccur[k * cx.n_tiles + t], n));
+      s_h[j] = 0;
     }
   }
   __syncthreads();
@@ -1418,20 +1453,13 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
     const long long c = rb_row(i, c0, c1, nsq);
     long long slot; int tile;
     rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell = 0; uint32_t frac = 0; bool hot;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &hot, false);
+    int cell = 0, k; uint32_t frac = 0;
+    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, false);
     const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    const int k = (PHO && !hot) ? 1 : 0;
-    int ri = -1, ro = -1;
-    for (int kk = 0; kk < NC; ++kk) {
-      const int r1 = rb_wave_add((inw && k == kk) ? nt : -1, s_h[kk], dlo, nullptr, true, true);
-      const int r2 = rb_wave_add((nt >= 0 && !inw && k == kk) ? nt : -1, s_h[kk], dlo,
-                                 kk == 0 ? cx.tcursor : cx.tcur_cold, false, true);
-      if (k == kk) { ri = r1; ro = r2; }
-    }
+    const int ri = rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, true);
+    const int ro = rb_wave_add((nt >= 0 && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccur, false, true);
     if (nt >= 0) {
-      const long long dst = inw ? s_base[k][nt - dlo] + ri
-                                : cx.tchunk[nt] * CHUNK + (k == 0 ? 0 : (long long)cx.thot[nt]) + ro;
+      const long long dst = inw ? (long long)s_base[(nt - dlo) * NC + k] + ri : rb_class_start(cx, nt, k) + ro;
       const Tile tl = cx.tiles[nt];
       rec_copy(cx.src, slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
     }
@@ -1454,6 +1482,7 @@ __global__ void k_rb_finish(RbCtx<B> cx) {
     cx.ctl->n_sorted_chunks = cx.ctl->total_chunks_new;
     cx.ctl->tail = 0;
     cx.ctl->tail_snap = 0;
+    cx.ctl->cold_steps = cx.chot ? cx.window : -1;
   }
 }
 
