@@ -192,11 +192,14 @@ struct WinState {
 struct gap_t {
   int n_tubes = 0;
   hipStream_t s = nullptr;
-  // second stream of a step: the photon pass runs on it beside the lepton
-  // pass and the field update (fork and join through the two events)
+  // second stream: the photon side of each step (prologue, sorted photon
+  // pass, conversion draws) runs on it beside the lepton side.  ev_l: the
+  // caller's stream up to the start of a step; ev_pre: the prologue done;
+  // ev_p: the photon side of the last enqueued step done.
   hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool capturing = false;   // graph capture: the photon pass stays on the caller's stream
+  hipEvent_t ev_l = nullptr, ev_pre = nullptr, ev_p = nullptr;
+  bool s2_pending = false;  // photon-side work not yet joined into the caller's stream
+  bool capturing = false;   // graph capture: everything stays on the caller's stream
   gap_allocator al{};
   bool custom_alloc = false;
   std::vector<void*> owned;
@@ -290,8 +293,8 @@ void release(gap_t* g) {
   drop_graph(g);
   if (g->s) (void)hipStreamSynchronize(g->s);
   if (g->s2) { (void)hipStreamSynchronize(g->s2); (void)hipStreamDestroy(g->s2); g->s2 = nullptr; }
-  if (g->ev_fork) { (void)hipEventDestroy(g->ev_fork); g->ev_fork = nullptr; }
-  if (g->ev_join) { (void)hipEventDestroy(g->ev_join); g->ev_join = nullptr; }
+  for (hipEvent_t* e : {&g->ev_l, &g->ev_pre, &g->ev_p})
+    if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
   win_release(g);
   for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
   g->ev_pool.clear();
@@ -409,6 +412,7 @@ FieldCtx make_fctx(gap_t* g, int mode) {
   f.part = g->part;
   f.part2 = g->part2;
   f.err = g->err;
+  f.pc = g->pho.ctl;
   f.mode = mode;
   return f;
 }
@@ -790,31 +794,58 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
 
 #undef D2D
 
+// The caller's stream waits for the photon side of the steps enqueued so far.
+void join_photon_side(gap_t* g) {
+  if (!g->s2_pending) return;
+  (void)hipStreamWaitEvent(g->s, g->ev_p, 0);
+  g->s2_pending = false;
+}
+
+// One step.  Photon side (second stream): prologue (injection, lepton tail
+// snapshot, step index), sorted photon pass, conversion draws.  Lepton side
+// (caller's stream): sorted lepton pass, then, once the prologue is done,
+// the lepton and photon tail passes, the field update (which also takes the
+// photon tail snapshot of the next step) and the re-sort when due.
+//
+// The sides touch disjoint data: each pass reads its own store up to its
+// tail snapshot, births go past the snapshots, only leptons deposit charge,
+// and the prologue changes the surface charge only atomically.  The photon
+// side of a step starts when the caller's stream has finished the previous
+// step (its field update counts the step and snapshots the photon tail);
+// the lepton side needs the photon side only for its tail passes (the
+// prologue's snapshot) and for the re-sort and merging (everything).  So the
+// sorted lepton pass of a step starts without waiting, and one step costs
+// one wait on each stream.  Captured graphs keep every kernel on the
+// caller's stream, in an order that respects the same dependencies.
 void enqueue_step(gap_t* g) {
-  if (g->merge_on && g->host_step % g->merge_every == 0) merge_all(g);
-  Ctx cx = make_ctx(g);
-  { Timer t(g, KT_PRE); k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes); }
-  // The two species' passes touch disjoint data: each reads its own store
-  // up to the tail snapshot of the prologue and appends the other species'
-  // births past that snapshot; only the leptons deposit charge.  The photon
-  // pass runs on the second stream while the lepton pass and the field
-  // update run on the caller's; the re-sort and the next step wait for both.
-  // Captured graphs keep every kernel on the caller's stream (no fork and
-  // join inside a graph).
-  hipStream_t ps = g->capturing ? g->s : g->s2;
-  if (!g->capturing) {
-    (void)hipEventRecord(g->ev_fork, g->s);
-    (void)hipStreamWaitEvent(g->s2, g->ev_fork, 0);
+  const bool two = !g->capturing;
+  const bool merge = g->merge_on && g->host_step % g->merge_every == 0;
+  if (merge) {
+    if (two) join_photon_side(g);
+    merge_all(g);
   }
+  Ctx cx = make_ctx(g);
+  hipStream_t ps = g->s;
+  if (two) {
+    ps = g->s2;
+    (void)hipEventRecord(g->ev_l, g->s);
+    (void)hipStreamWaitEvent(g->s2, g->ev_l, 0);
+  }
+  { Timer t(g, KT_PRE, ps); k_pre<<<1, PRE_THREADS, 0, ps>>>(cx, g->n_tubes); }
+  if (two) (void)hipEventRecord(g->ev_pre, g->s2);
   { Timer t(g, KT_PHOTONS, ps); k_photons<<<g->grid_pho, TPB, 0, ps>>>(cx); }
   { Timer t(g, KT_CONV, ps); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, ps>>>(cx, g->grid_pho); }
-  { Timer t(g, KT_PHOTAIL, ps); k_photons_tail<<<g->grid_tail, TPB, 0, ps>>>(cx); }
-  if (!g->capturing) (void)hipEventRecord(g->ev_join, g->s2);
+  if (two) {
+    (void)hipEventRecord(g->ev_p, g->s2);
+    g->s2_pending = true;
+  }
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
+  if (two) (void)hipStreamWaitEvent(g->s, g->ev_pre, 0);
   { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
-  if (!g->capturing) (void)hipStreamWaitEvent(g->s, g->ev_join, 0);
   if (++g->since_rb >= g->R) {
+    if (two) join_photon_side(g);
     Timer t(g, KT_RESORT);
     rebucket_all(g);
     g->since_rb = 0;
@@ -1164,6 +1195,7 @@ int timed_steps(gap_t* g, int64_t n, double* kt, double* wall_ms) {
   if (!a || !b) return GAP_EDEVICE;
   HIPCHK(hipEventRecord(a, g->s));
   for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  join_photon_side(g);
   HIPCHK(hipEventRecord(b, g->s));
   HIPCHK(hipEventSynchronize(b));
   float ms = 0.0f;
@@ -1262,8 +1294,9 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
   g->s = (hipStream_t)stream;
   // default priority, like every stream of the library
   if (hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&g->ev_l, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_pre, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_p, hipEventDisableTiming) != hipSuccess) {
     release(g);
     delete g;
     return GAP_EDEVICE;
@@ -1282,6 +1315,7 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
 int gap_step(gap_t* g, int64_t n_steps) {
   if (!g || n_steps < 0) return GAP_EINVAL;
   for (int64_t i = 0; i < n_steps; ++i) enqueue_step(g);
+  join_photon_side(g);   // the caller's stream holds all the work again
   if (hipGetLastError() != hipSuccess) return GAP_EDEVICE;
   return g->sticky;
 }
@@ -1290,6 +1324,7 @@ int gap_step_graph(gap_t* g, int64_t n_steps) {
   if (!g || n_steps < 0) return GAP_EINVAL;
   if (n_steps == 0) return g->sticky;
   if (g->s == nullptr) return GAP_ESTATE;   // stream capture needs a non-default stream
+  join_photon_side(g);
   const bool valid = g->gexec && g->gsteps == n_steps && g->lep.cur == g->gs_l && g->pho.cur == g->gs_p &&
                      g->since_rb == g->gs_since &&
                      (!g->merge_on || (g->host_step - g->gs_step) % g->merge_every == 0);

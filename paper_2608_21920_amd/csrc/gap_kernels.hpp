@@ -178,13 +178,17 @@ constexpr int PRE_THREADS = 1024;
 
 // One workgroup; thread t handles tubes t, t + PRE_THREADS, ...  Each tube's
 // injected electrons take tail slots through one atomic reservation (the
-// order of tail slots changes no result).
+// order of tail slots changes no result).  The prologue belongs to the photon
+// side of the step: it runs before the photon passes, while the lepton pass
+// of the same step may already run, so it touches nothing that pass writes
+// except through atomics (the surface charge dq); the photon tail's snapshot
+// is taken by the field scan at the end of the previous step, after every
+// photon birth of that step.
 __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
   // (appends never leave the tails past the limit; the passes below stay
   // inside the stores whatever the tails hold)
   if (threadIdx.x == 0) {
     clamp_tail(cx.lc);
-    clamp_tail(cx.pc);
     cx.lc->tail_pre = cx.lc->tail;
     if (cx.pc->cold_steps >= 0) cx.pc->cold_steps -= 1;
   }
@@ -193,8 +197,8 @@ __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
   const long long lim = cx.lc->limit;
   for (int t = threadIdx.x; t < n_tubes; t += blockDim.x) {
     Tube& T = cx.tubes[t];
-    // the passes of this step read its index from step_now: the field
-    // update (which counts the step) may run beside the photon pass
+    // the photon passes of this step read its index from step_now: the
+    // field update (which counts the step) may run beside them
     T.step_now = T.step;
     if (T.inj_per_step <= 0.0 || (T.flags & F_PERIODIC)) continue;
     T.inj_acc += T.inj_per_step;
@@ -204,6 +208,7 @@ __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
     if (m <= 0) continue;
     const long long first = S + (long long)atomicAdd((unsigned long long*)&cx.lc->tail, (unsigned long long)m);
     const Tile& tl = cx.tiles[T.tile_first];
+    int64_t dq = 0;
     for (int j = 0; j < m; ++j) {
       const long long slot = first + j;
       if (slot >= lim) { T.cnt[C_DROPPED]++; atomicOr(cx.err, E_CAP); continue; }
@@ -214,15 +219,15 @@ __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
       cx.L.w[slot] = -T.inj_w;
       cx.L.id[slot] = id;
       cx.ltt[slot] = T.tile_first;
-      T.dq += T.inj_T;               // E_s -= q w0 of the injected electron (q < 0)
+      dq += T.inj_T;                 // E_s -= q w0 of the injected electron (q < 0)
       T.cnt[C_INJECTED]++;
     }
+    atomic_add_i64(&T.dq, dq);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     clamp_tail(cx.lc);               // (reservations past the limit were dropped)
     cx.lc->tail_snap = cx.lc->tail;
-    cx.pc->tail_snap = cx.pc->tail;
   }
 }
 
@@ -265,7 +270,10 @@ __device__ __forceinline__ int64_t rfl(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
+// pho: the photon passes take the step index from step_now (set by the
+// prologue), the lepton passes from step (they run on the stream of the field
+// scan that advances it)
+__device__ __forceinline__ KC load_kc(const Ctx& cx, int tile, bool pho) {
   KC k;
   tile = rfl(tile);
   const Tile tl = cx.tiles[tile];
@@ -278,7 +286,7 @@ __device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
   k.flags = rfl(T.flags);
   k.nsub_max = rfl(T.nsub_max);
   k.dpho = rfl(T.dpho);
-  k.step = rfl((int64_t)T.step_now);
+  k.step = rfl(pho ? (int64_t)T.step_now : (int64_t)T.step);
   k.hfix = rfl((int64_t)T.hfix);
   k.xlo = -((int64_t)k.base << FRAC);
   k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
@@ -297,12 +305,12 @@ __device__ __forceinline__ KC load_kc(const Ctx& cx, int tile) {
 }
 
 // The same constants for a lane's own tile (tail chunks: not uniform).
-__device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile) {
+__device__ __forceinline__ KC lane_kc(const Ctx& cx, int tile, bool pho) {
   KC k;
   const Tile tl = cx.tiles[tile];
   const Tube& T = cx.tubes[tl.tube];
   k.tile = tile; k.tube = tl.tube; k.base = tl.base; k.N = T.N; k.node_off = T.node_off; k.flags = T.flags;
-  k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = T.step_now; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
+  k.nsub_max = T.nsub_max; k.dpho = T.dpho; k.step = pho ? T.step_now : T.step; k.hfix = T.hfix; k.dt = T.dt; k.lr = T.lr;
   k.xlo = -((int64_t)k.base << FRAC);
   k.xhi = min(k.hfix - ((int64_t)k.base << FRAC), (int64_t)(k.N - k.base) << FRAC);
   k.inv_rc = T.inv_rc; k.b = T.b; k.xc_floor = T.xc_floor; k.x_thr = T.x_thr; k.emit_k = T.emit_k;
@@ -341,7 +349,7 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     alive = w != 0.0f;
   } else {
     alive = tile >= 0 && w != 0.0f;
-    k = lane_kc(cx, alive ? tile : 0);   // tile 0 always exists; no branch on the struct
+    k = lane_kc(cx, alive ? tile : 0, false);   // tile 0 always exists; no branch on the struct
   }
   if (!alive) { pos = 0; u = 0.0f; }
   const int tube = alive ? k.tube : -1;
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
     if (tile != held) {
       if (held >= 0) flush_window(cx, held, s_rho);
       held = tile;
-      kc = load_kc(cx, tile);
+      kc = load_kc(cx, tile, false);
       if (kc.tube != ctube) {
         if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
         ctube = kc.tube;
@@ -606,7 +614,7 @@ __global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
   const long long S = nsc * CHUNK;
   const long long tail = cx.lc->tail_snap;
   const long long nq = (tail + TPB - 1) / TPB;
-  const KC kc0 = load_kc(cx, 0);
+  const KC kc0 = load_kc(cx, 0, false);
   for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
     uint32_t slot;
     int tile;
@@ -658,7 +666,7 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     alive = x != 0.0f;
   } else {
     alive = tile >= 0 && x != 0.0f;
-    k = lane_kc(cx, alive ? tile : 0);
+    k = lane_kc(cx, alive ? tile : 0, true);
   }
   if (!alive) { x = 0.0f; pos = 0; n0 = 0; }
   const int tube = alive ? k.tube : -1;
@@ -831,7 +839,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
     if (c + 1 < c1) nxt = pho_load4(cx, c + 1, cold_ok);
     if (cur.tile != held) {
       held = cur.tile;
-      kc = load_kc(cx, held);
+      kc = load_kc(cx, held, true);
       if (kc.tube != ctube) {
         if (ctube >= 0) flush_counts<1>(cx.shard, ctube, lcn, s_cnt);
         ctube = kc.tube;
@@ -958,7 +966,7 @@ __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
   const long long S = nsc * CHUNK;
   const long long tail = cx.pc->tail_snap;
   const long long nq = (tail + TPB - 1) / TPB;
-  const KC kc0 = load_kc(cx, 0);
+  const KC kc0 = load_kc(cx, 0, true);
   for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
     uint32_t slot;
     int tile;
@@ -991,6 +999,7 @@ struct FieldCtx {
   long long* part;    // per block: sum rho
   long long* part2;   // per block: sum rho_i (N - i)
   int* err;
+  Ctl* pc;            // photon store: its tail snapshot for the next step is taken here
   int mode;           // 0: step (surface update, step += 1); 1: rebuild E only
 };
 
@@ -1134,6 +1143,12 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
     }
   }
   if (threadIdx.x == 0 && f.mode == 0 && b.k0 == 0) T.step += 1;
+  // the photon tail the next step's photon tail pass takes: every photon
+  // born in this step (the lepton passes, earlier on this stream) is in it
+  if (threadIdx.x == 0 && blockIdx.x == 0 && f.mode == 0) {
+    clamp_tail(f.pc);
+    f.pc->tail_snap = f.pc->tail;
+  }
 }
 
 // Periodic node 0 (= node N): average of E_{N-1/2} and E_{1/2}; runs after k_field_b.
