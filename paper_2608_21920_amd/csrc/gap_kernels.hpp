@@ -882,7 +882,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 // Workgroup b takes the segments that workgroups CONV_SEGS b .. CONV_SEGS b
 // + CONV_SEGS - 1 of the photon kernel (a grid of nseg) wrote, one entry of
 // each segment per thread and round, with all loads issued before the draws.
-constexpr int CONV_SEGS = 4;
+constexpr int CONV_SEGS = 2;
 
 __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   const Room lroom = load_room(cx.lc);
