@@ -290,3 +290,54 @@ def test_graph_recapture_while_a_replay_is_in_flight(torch_gpu):
         assert ga.counts()["err"] == 0
         ga.close()
         gb.close()
+
+
+def test_state_change_ends_the_cold_window(torch_gpu):
+    # Photons of x = 10 born at step 0 in a frozen zero field: their
+    # conversion probability is about 2e-27 at age 41, so the re-sort (every
+    # 40 steps) classes them as unable to draw before the next one; at age
+    # ~1000 it is about 0.15 per step.  Mid-window, jump the step index by
+    # 1000: the state change must end that classification (the photon pass
+    # then takes every probability), and the next steps equal those of a
+    # fresh handle loaded with the same state and step, whose re-sort
+    # classifies from scratch.
+    _say("case: step index jump mid re-sort window, 1e5 photons of x = 10")
+    from paper_2608_21920_amd.inputs import LEPTON_DTYPE, PHOTON_DTYPE
+    N, n = 8192, 100_000
+    cfg = dict(n_cells=N, init_kind=2, b=0.1, r_curv_cm=1e7, lambda_c_scale=1.7e5, r_curv_scale=1.4e-5,
+               h_gap_frac=1.0, flags=G.FIELD_FROZEN | G.EMIT_OFF, seed=9, cap_photons=1 << 20, cap_leptons=1 << 21,
+               rebucket_every=40)
+    P = np.zeros(n, PHOTON_DTYPE)
+    P["cell"] = np.arange(n) % 64
+    P["x"], P["w"], P["n0"] = 10.0, 1.0, 0
+    P["id"] = np.arange(1, n + 1, dtype=np.uint64) * np.uint64(2654435761)
+    g = Gap(cfg)
+    g.set_particles(np.zeros(0, LEPTON_DTYPE), P)
+    g.set_field(np.zeros(N, np.float32), 0.0)
+    g.step(5)
+    c0 = g.counts()
+    assert c0["n_conv"] == 0 and c0["n_pho"] == n
+    L0, P0, es = g.leptons(), g.photons(), g.es()
+    jump = c0["step"] + 1000
+    g.set_es_step(es, jump)
+    h = Gap(cfg)
+    h.set_particles(L0, P0)
+    h.set_field(np.zeros(N, np.float32), es)
+    h.set_es_step(es, jump)
+    hc0 = h.counts()
+    g.step(10)
+    h.step(10)
+    ga, ha = g.counts(), h.counts()
+    assert ga["err"] == 0 and ha["err"] == 0
+    _say("  conversions after the jump: %d" % (ga["n_conv"] - c0["n_conv"]))
+    assert ga["n_conv"] - c0["n_conv"] > 1000
+    for k in ("n_conv", "n_pho_exit", "n_conv_eval"):
+        assert ga[k] - c0[k] == ha[k] - hc0[k], k
+    A, B = by_id(gpu_leptons_as_oracle(g.leptons())), by_id(gpu_leptons_as_oracle(h.leptons()))
+    for k in ("cell", "xi", "u", "w", "id"):
+        assert np.array_equal(A[k], B[k]), k
+    A, B = by_id(gpu_photons_as_oracle(g.photons())), by_id(gpu_photons_as_oracle(h.photons()))
+    for k in ("cell", "xi", "x", "w", "n0", "id"):
+        assert np.array_equal(A[k], B[k]), k
+    g.close()
+    h.close()
