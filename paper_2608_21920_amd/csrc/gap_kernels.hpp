@@ -552,7 +552,9 @@ __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long
 // and the next chunk's records are prefetched while the current one is
 // pushed.  The chunk's tile constants sit in scalar registers; gather and
 // deposit go through an LDS window of the tile.
-__global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
+// (six waves per SIMD: the register cap spills one value, stored once on
+// entry and reloaded once per chunk)
+__global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
   const Room proom = load_room(cx.pc);
   __shared__ long long s_rho[WIN + 2];
   __shared__ float s_eb[WIN + 2];
@@ -1215,9 +1217,13 @@ template <class B> struct RbClasses;
 template <> struct RbClasses<PhoBuf> { static constexpr int N = 2; };
 template <> struct RbClasses<LepBuf> { static constexpr int N = 4; };
 
-__device__ __forceinline__ bool rb_hot(const RbCtx<PhoBuf>& cx, const Tube& T, long long slot) {
-  const float x = cx.src.x[slot];
-  const uint32_t n0 = (uint32_t)cx.src.n0[slot];
+// The loads of one slot of a re-sort row, issued before any use, so that a
+// group of rows keeps its loads in flight together.  a: the field that marks
+// a live record (photon x, lepton w); b: lepton u; n0: photon birth step;
+// cls: the class the count kernel decided (scatter).
+struct RbIn { long long slot; int tile; uint32_t pos; float a, b; uint32_t n0; int cls; };
+
+__device__ __forceinline__ bool rb_hot(const RbCtx<PhoBuf>& cx, const Tube& T, float x, uint32_t n0) {
   const int32_t a1 = (int32_t)((uint32_t)T.step + 1u - n0);
   const int32_t a2 = (int32_t)((uint32_t)T.step + (uint32_t)cx.window - n0);
   if (a2 < a1) return true;                 // the 32-bit age wraps inside the window
@@ -1226,17 +1232,17 @@ __device__ __forceinline__ bool rb_hot(const RbCtx<PhoBuf>& cx, const Tube& T, l
   const float chi = fabsf(x) * T.b * sp;
   return T.conv_k * sp * t_bw(chi) > 7.4505806e-9f;   // 2^-27
 }
-__device__ __forceinline__ int rb_class(const RbCtx<PhoBuf>& cx, const Tube& T, long long slot, int, uint32_t) {
-  return rb_hot(cx, T, slot) ? 0 : 1;
+__device__ __forceinline__ int rb_class(const RbCtx<PhoBuf>& cx, const Tube& T, const RbIn& r, int, uint32_t) {
+  return rb_hot(cx, T, r.a, r.n0) ? 0 : 1;
 }
 // Leptons: class 0 evaluates emission now (x_c >= x_c,floor inside the QED
 // zone, the pass's test on the stored momentum), classes 1 and 2 are within
 // factors 4 and 64 of the threshold in x_c (gamma within 1.6 and 4), class 3
 // is the rest and everything outside the zone.  Those that cross the
 // threshold during the window sit next to the evaluating ones.
-__device__ __forceinline__ int rb_class(const RbCtx<LepBuf>& cx, const Tube& T, long long slot, int cell, uint32_t frac) {
+__device__ __forceinline__ int rb_class(const RbCtx<LepBuf>&, const Tube& T, const RbIn& r, int cell, uint32_t frac) {
   if ((T.flags & (F_QED_OFF | F_EMIT_OFF)) || ((int64_t)cell << FRAC) + frac >= T.hfix) return 3;
-  const float u = cx.src.u[slot];
+  const float u = r.b;
   const float g = __builtin_amdgcn_sqrtf(1.0f + u * u);
   const float xc = 1.5f * g * (g * g * T.lr);
   return xc >= T.xc_floor ? 0 : xc >= 0.25f * T.xc_floor ? 1 : xc >= (1.0f / 64.0f) * T.xc_floor ? 2 : 3;
@@ -1248,33 +1254,53 @@ __device__ __forceinline__ int rb_class(const RbCtx<LepBuf>& cx, const Tube& T, 
 // class (a recomputed class could differ in its last rounding between
 // kernels).
 template <class B>
-__device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, long long slot, int tile_old, int* cell_out, uint32_t* frac_out,
-                                         int* cls, bool decide) {
+__device__ __forceinline__ int rb_locate(const RbCtx<B>& cx, const RbIn& r, int* cell_out, uint32_t* frac_out, int* cls,
+                                         bool decide) {
   *cls = 0;
-  if (tile_old < 0 || !rec_alive<B>(cx.src, slot)) return -1;
-  const Tile tl = cx.tiles[tile_old];
+  if (r.tile < 0 || r.a == 0.0f) return -1;
+  const Tile tl = cx.tiles[r.tile];
   const Tube& T = cx.tubes[tl.tube];
-  const uint32_t pos = cx.src.pos[slot];
-  int cell = tl.base + (int)(pos >> FRAC);
+  int cell = tl.base + (int)(r.pos >> FRAC);
   if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
   *cell_out = cell;
-  *frac_out = pos & 0xFFFFFFu;
+  *frac_out = r.pos & 0xFFFFFFu;
   if (decide) {
-    *cls = rb_class(cx, T, slot, cell, pos & 0xFFFFFFu);
-    cx.cls[slot] = (uint8_t)*cls;
+    *cls = rb_class(cx, T, r, cell, r.pos & 0xFFFFFFu);
+    cx.cls[r.slot] = (uint8_t)*cls;
   } else {
-    *cls = cx.cls[slot];
+    *cls = r.cls;
   }
   return T.tile_first + cell / TILE;
 }
 
+// Row q of a re-sort pass: the slot of this thread and its loads (a row past
+// the workgroup's last gives a dead slot).  Slots past the tail are inside
+// the store (it keeps a chunk of slack), so every load is in bounds.
 template <class B>
-__device__ __forceinline__ void rb_slot_iter(const RbCtx<B>& cx, long long q, long long nsq, long long S, long long tail,
-                                             long long* slot, int* tile) {
+__device__ __forceinline__ void rb_load(const RbCtx<B>& cx, bool have, long long q, long long nsq, long long S,
+                                        long long tail, bool decide, RbIn& r) {
+  r.slot = 0;
+  r.tile = -1;
+  r.pos = 0;
+  r.a = 0.0f;
+  r.b = 0.0f;
+  r.n0 = 0;
+  r.cls = 0;
+  if (!have) return;
   uint32_t s32;
-  piece_slot(q, nsq, S, tail, cx.chunk_old, cx.tt, &s32, tile);
-  *slot = s32;
+  piece_slot(q, nsq, S, tail, cx.chunk_old, cx.tt, &s32, &r.tile);
+  r.slot = s32;
+  r.pos = cx.src.pos[s32];
+  if constexpr (std::is_same<B, PhoBuf>::value) {
+    r.a = cx.src.x[s32];
+    if (decide) r.n0 = (uint32_t)cx.src.n0[s32];
+  } else {
+    r.a = cx.src.w[s32];
+    if (decide) r.b = cx.src.u[s32];
+  }
+  if (!decide) r.cls = cx.cls[s32];
 }
+constexpr int RB_U = 4;   // rows whose loads a thread keeps in flight together
 
 // Destination tiles of one workgroup's contiguous chunk range are counted in
 // an LDS histogram over a window of RB_HW tiles (a range of sorted chunks
@@ -1338,18 +1364,22 @@ __global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
   for (int j = threadIdx.x; j < RB_HW * (NC - 1); j += blockDim.x) s_c[j] = 0;
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
-  for (long long i = 0; i < nrow; ++i) {
-    const long long c = rb_row(i, c0, c1, nsq);
-    long long slot; int tile;
-    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell; uint32_t frac; int k;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, true);
-    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    rb_wave_add(inw ? nt : -1, s_h, dlo, cx.tcount, true, false);
-    rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcount, false, false);
-    const bool ck = nt >= 0 && k < NC - 1;
-    rb_wave_add((ck && inw) ? (nt - dlo) * (NC - 1) + k : -1, s_c, 0, nullptr, true, false);
-    rb_wave_add((ck && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccount, false, false);
+  for (long long i0 = 0; i0 < nrow; i0 += RB_U) {
+    RbIn in[RB_U];
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u)
+      rb_load(cx, i0 + u < nrow, rb_row(i0 + u, c0, c1, nsq), nsq, S, tail, true, in[u]);
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u) {
+      int cell; uint32_t frac; int k;
+      const int nt = rb_locate(cx, in[u], &cell, &frac, &k, true);
+      const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+      rb_wave_add(inw ? nt : -1, s_h, dlo, cx.tcount, true, false);
+      rb_wave_add((nt >= 0 && !inw) ? nt : -1, s_h, dlo, cx.tcount, false, false);
+      const bool ck = nt >= 0 && k < NC - 1;
+      rb_wave_add((ck && inw) ? (nt - dlo) * (NC - 1) + k : -1, s_c, 0, nullptr, true, false);
+      rb_wave_add((ck && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccount, false, false);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < RB_HW; j += blockDim.x)
@@ -1443,14 +1473,18 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   __syncthreads();
   const int dlo = c0 < nsq ? cx.chunk_old[c0 / PPC] - 1 : -(1 << 30);
   // pass A: how many of this range go to each window tile and class
-  for (long long i = 0; i < nrow; ++i) {
-    const long long c = rb_row(i, c0, c1, nsq);
-    long long slot; int tile;
-    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell, k; uint32_t frac;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, false);
-    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, false);
+  for (long long i0 = 0; i0 < nrow; i0 += RB_U) {
+    RbIn in[RB_U];
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u)
+      rb_load(cx, i0 + u < nrow, rb_row(i0 + u, c0, c1, nsq), nsq, S, tail, false, in[u]);
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u) {
+      int cell, k; uint32_t frac;
+      const int nt = rb_locate(cx, in[u], &cell, &frac, &k, false);
+      const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+      rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, false);
+    }
   }
   __syncthreads();
   // one reservation per (workgroup, tile, class)
@@ -1464,19 +1498,23 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   }
   __syncthreads();
   // pass B: place the records
-  for (long long i = 0; i < nrow; ++i) {
-    const long long c = rb_row(i, c0, c1, nsq);
-    long long slot; int tile;
-    rb_slot_iter(cx, c, nsq, S, tail, &slot, &tile);
-    int cell = 0, k; uint32_t frac = 0;
-    const int nt = rb_locate(cx, slot, tile, &cell, &frac, &k, false);
-    const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
-    const int ri = rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, true);
-    const int ro = rb_wave_add((nt >= 0 && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccur, false, true);
-    if (nt >= 0) {
-      const long long dst = inw ? (long long)s_base[(nt - dlo) * NC + k] + ri : rb_class_start(cx, nt, k) + ro;
-      const Tile tl = cx.tiles[nt];
-      rec_copy(cx.src, slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
+  for (long long i0 = 0; i0 < nrow; i0 += RB_U) {
+    RbIn in[RB_U];
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u)
+      rb_load(cx, i0 + u < nrow, rb_row(i0 + u, c0, c1, nsq), nsq, S, tail, false, in[u]);
+#pragma unroll
+    for (int u = 0; u < RB_U; ++u) {
+      int cell = 0, k; uint32_t frac = 0;
+      const int nt = rb_locate(cx, in[u], &cell, &frac, &k, false);
+      const bool inw = nt >= 0 && nt - dlo >= 0 && nt - dlo < RB_HW;
+      const int ri = rb_wave_add(inw ? (nt - dlo) * NC + k : -1, s_h, 0, nullptr, true, true);
+      const int ro = rb_wave_add((nt >= 0 && !inw) ? k * cx.n_tiles + nt : -1, nullptr, 0, cx.ccur, false, true);
+      if (nt >= 0) {
+        const long long dst = inw ? (long long)s_base[(nt - dlo) * NC + k] + ri : rb_class_start(cx, nt, k) + ro;
+        const Tile tl = cx.tiles[nt];
+        rec_copy(cx.src, in[u].slot, cx.dst, dst, ((uint32_t)(cell - tl.base) << FRAC) | frac);
+      }
     }
   }
 }
