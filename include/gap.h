@@ -145,6 +145,25 @@ int gap_sync(gap_t* g);
                                 pass, field, re-sort, prologue, lepton tail pass, photon
                                 tail pass and conversion draws since timing was enabled or
                                 last read (tube ignored; resets the record)                 */
+/* Discharge diagnostics (Sect. 5: Fig. 3 rows 5-7, Fig. 5, Fig. 7).  Bins are
+ * GAP_STATE_PROFILE_BIN cells wide (default 64), nb = ceil(N / bin).  Groups,
+ * in order: electrons moving up (u > 0), electrons moving down, positrons up,
+ * positrons down, photons with |x| > 2 moving up (x > 0), and down. */
+#define GAP_DIAG_PROFILE  9  /* double[nb][6][3]: per bin and group the multiplicity
+                                n/n_co = sum |w| / (bin ppc_ref), the mean Lorentz factor
+                                (photons: the mean |x|) and <gamma^-3> = sum |w| gamma^-3 /
+                                sum |w| (0 for photons and for empty groups)              */
+#define GAP_DIAG_PEAK    10  /* double[6]: over the bins whose centre lies below H, the
+                                largest pair multiplicity (both species and directions; ties
+                                to the lowest bin), the height of that bin's centre (skin
+                                depths; -1 if none), <gamma^-3> of the pairs there, the
+                                photon multiplicity (|x| > 2) there, then min E and max E
+                                over the cells                                              */
+#define GAP_DIAG_RETURN  11  /* double[66]: weight of the leptons absorbed at h = 0 since the
+                                last read, per bin of 1/8 decade of gamma (bin
+                                floor(8 log10 gamma), clamped to [0, 63], gamma from the
+                                leptons' momentum when they were absorbed, in FP64), then the
+                                total weight and the total weight x gamma; reading resets it */
 
 /* indices of GAP_DIAG_COUNTS */
 #define GAP_C_LEPTONS     0   /* live leptons                      */
@@ -186,6 +205,8 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
 #define GAP_STATE_DRIVE     5  /* double alpha, then double inj_weight: the imposed current
                                   j_m = alpha j_co (Sect. 2.2) and the weight of one injected
                                   electron from the next step on; ends a pending window        */
+#define GAP_STATE_PROFILE_BIN 7  /* int32 cells per bin >= 1 of GAP_DIAG_PROFILE and
+                                    GAP_DIAG_PEAK (all tubes)                                */
 #define GAP_STATE_LAUNCH    6  /* int32[4]: workgroups of the sorted lepton pass, of the sorted
                                   photon pass and of the tail passes, and the re-sort interval
                                   (the values gap_autotune returns); grids must be multiples
@@ -194,8 +215,8 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
                                   GAP_EINVAL.  Changes no result, only the speed.             */
 
 /* Replace part of the state of tube `tube` (only valid when n_tubes == 1;
- * GAP_STATE_TIMING, GAP_STATE_DRIVE and GAP_STATE_LAUNCH are valid for any
- * handle, the latter ignoring `tube`).
+ * GAP_STATE_TIMING, GAP_STATE_DRIVE, GAP_STATE_LAUNCH and GAP_STATE_PROFILE_BIN
+ * are valid for any handle, the last two ignoring `tube`).
  * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);

@@ -33,6 +33,7 @@
  * 2^F integer charge units. */
 #define ORC_FP_BITS 24
 #define ORC_FP_ONE  16777216.0
+#define ORC_RET_NB  64                 /* return-flux bins: 1/8 decade of gamma each */
 
 /* Flags (bit values are part of the interface between the two sides). */
 #define ORC_QED_OFF      1u
@@ -116,6 +117,9 @@ typedef struct {
   int64_t n_emit, n_pho_born, n_conv, n_absorbed, n_outflow, n_pho_exit, n_dropped, n_merged;
   int64_t n_emit_eval, n_conv_eval;
   double e_rad;  /* radiated energy (m_e c^2 units, weighted) */
+  /* return flux (Sect. 5, Fig. 7): weight of the leptons absorbed at h = 0
+   * per 1/8 decade of gamma in [1, 1e8), then total weight and weight x gamma */
+  double ret[ORC_RET_NB + 2];
   /* event log */
   oevent* ev; int64_t nev, ev_alloc;
   /* replay cursor (events sorted by step when replaying) */
@@ -664,6 +668,15 @@ static void step_once(orc_sim* s) {
     if (!periodic && l->cell < 0) {            /* absorbed by the star */
       s->dq += (int64_t)sg * wt_fixed(l->w);
       s->n_absorbed++;
+      {
+        double ga = sqrt(1.0 + l->u * l->u);
+        int b = (int)floor(log10(ga) * 8.0);
+        if (b < 0) b = 0;
+        if (b >= ORC_RET_NB) b = ORC_RET_NB - 1;
+        s->ret[b] += fabs(l->w);
+        s->ret[ORC_RET_NB] += fabs(l->w);
+        s->ret[ORC_RET_NB + 1] += fabs(l->w) * ga;
+      }
       l->w = 0.0;
       continue;
     }
@@ -781,6 +794,10 @@ void orc_counts(const orc_sim* s, int64_t out[16]) {
 }
 
 double orc_es(const orc_sim* s) { return s->Es; }
+/* the return flux since the last call, which clears it */
+void orc_return(orc_sim* s, double out[ORC_RET_NB + 2]) {
+  for (int i = 0; i < ORC_RET_NB + 2; ++i) { out[i] = s->ret[i]; s->ret[i] = 0.0; }
+}
 double orc_erad(const orc_sim* s) { return s->e_rad; }
 void orc_field(const orc_sim* s, double* E) { memcpy(E, s->E, sizeof(double) * s->N); }
 void orc_node_field(const orc_sim* s, double* Eb) { memcpy(Eb, s->Eb, sizeof(double) * (s->N + 1)); }

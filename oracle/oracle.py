@@ -81,6 +81,7 @@ def _load():
         lib.orc_es.argtypes = [C.c_void_p]
         lib.orc_erad.restype = C.c_double
         lib.orc_erad.argtypes = [C.c_void_p]
+        lib.orc_return.argtypes = [C.c_void_p, C.c_void_p]
         for f in ("orc_field", "orc_node_field"):
             getattr(lib, f).argtypes = [C.c_void_p, C.c_void_p]
         lib.orc_rho.argtypes = [C.c_void_p, C.c_void_p]
@@ -186,6 +187,13 @@ class Oracle:
     @property
     def e_rad(self) -> float:
         return self.lib.orc_erad(self.h)
+
+    def return_spectrum(self) -> np.ndarray:
+        """Weight absorbed at h = 0 per 1/8 decade of gamma since the last
+        call (which clears it), then the total weight and weight x gamma."""
+        out = np.zeros(66, np.float64)
+        self.lib.orc_return(self.h, _ptr(out))
+        return out
 
     def field(self) -> np.ndarray:
         E = np.empty(self.N, np.float64)

@@ -5,6 +5,7 @@
 #include "gap_kernels.hpp"
 #include "gap_merge.hpp"
 #include "gap_adjoint.hpp"
+#include "gap_diag.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -243,6 +244,12 @@ struct gap_t {
   // conversion queue of the sorted photon pass (one entry per photon slot at
   // most) and its per-workgroup entry counts
   uint4* pq = nullptr;
+  // discharge diagnostics: return spectra [n_tubes][RET_N]; profile sums and
+  // results for the largest tube at one cell per bin
+  double* ret = nullptr;
+  double* prof_acc = nullptr;
+  double* prof_out = nullptr;
+  int prof_bin = 64;                   // cells per profile bin
   int* pq_count = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
@@ -371,6 +378,7 @@ Ctx make_ctx(gap_t* g) {
   c.shard = g->shard;
   c.pq = g->pq;
   c.pq_count = g->pq_count;
+  c.ret = g->ret;
   return c;
 }
 
@@ -1033,6 +1041,12 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->pq = (uint4*)dalloc(g, (size_t)g->pho.capacity * sizeof(uint4));
   g->pq_count = (int*)dalloc(g, (size_t)g->pq_groups * 4);
   if (!g->pq || !g->pq_count) return GAP_ENOMEM;
+  int max_n = 1;
+  for (int t = 0; t < n_tubes; ++t) max_n = std::max(max_n, p[t].n_cells);
+  g->ret = (double*)dalloc(g, sizeof(double) * RET_N * (size_t)n_tubes);
+  g->prof_acc = (double*)dalloc(g, sizeof(double) * PROF_G * PROF_M * (size_t)max_n);
+  g->prof_out = (double*)dalloc(g, sizeof(double) * PROF_G * 3 * (size_t)max_n);
+  if (!g->ret || !g->prof_acc || !g->prof_out) return GAP_ENOMEM;
   for (int t = 0; t < n_tubes; ++t) if (g->P[t].flags & GAP_MERGE_ON) g->merge_on = true;
   if (g->merge_on) {
     g->merge_every = std::max(1, g->P[0].merge_every);
@@ -1409,6 +1423,38 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       std::memcpy(host_buf, &g->th[tube].Es, sizeof(double));
       return GAP_OK;
     }
+    case GAP_DIAG_PROFILE:
+    case GAP_DIAG_PEAK: {
+      const int B = g->prof_bin;
+      const int nb = (N + B - 1) / B;
+      if (kind == GAP_DIAG_PROFILE ? !fits(sizeof(double) * 3 * PROF_G * (size_t)nb) : !fits(sizeof(double) * 6))
+        return GAP_EINVAL;
+      const long long nacc = (long long)nb * PROF_G * PROF_M;
+      k_fill_i64<<<std::max(1, (int)std::min<long long>(1024, (nacc + 255) / 256)), 256, 0, g->s>>>(
+          (long long*)g->prof_acc, nacc, 0);
+      k_profile<<<kGrid, TPB, 0, g->s>>>(make_ctx(g), tube, B, nb, g->prof_acc);
+      const double bppc = (double)B * (double)g->P[tube].ppc_ref;
+      if (kind == GAP_DIAG_PROFILE) {
+        k_profile_finish<<<std::max(1, std::min(1024, (nb * PROF_G + 255) / 256)), 256, 0, g->s>>>(g->prof_acc, nb,
+                                                                                                 bppc, g->prof_out);
+        HIPCHK(hipStreamSynchronize(g->s));
+        HIPCHK(hipMemcpy(host_buf, g->prof_out, sizeof(double) * 3 * PROF_G * (size_t)nb, hipMemcpyDeviceToHost));
+      } else {
+        k_profile_peak<<<1, TPB, 0, g->s>>>(g->prof_acc, nb, B, g->P[tube].dx, g->D[tube].H, bppc,
+                                            g->E + Th.cell_off, N, g->prof_out);
+        HIPCHK(hipStreamSynchronize(g->s));
+        HIPCHK(hipMemcpy(host_buf, g->prof_out, sizeof(double) * 6, hipMemcpyDeviceToHost));
+      }
+      return sync_and_err(g);
+    }
+    case GAP_DIAG_RETURN: {
+      // double[RET_N]; reading resets the tube's record
+      if (!fits(sizeof(double) * RET_N)) return GAP_EINVAL;
+      double* r = g->ret + (size_t)tube * RET_N;
+      HIPCHK(hipMemcpy(host_buf, r, sizeof(double) * RET_N, hipMemcpyDeviceToHost));
+      k_fill_i64<<<1, 256, 0, g->s>>>((long long*)r, RET_N, 0);
+      return sync_and_err(g);
+    }
     case GAP_DIAG_TIMING: {
       // double[2 * KT_N]: launches and summed milliseconds per kernel group
       if (!fits(sizeof(double) * 2 * KT_N)) return GAP_EINVAL;
@@ -1471,6 +1517,14 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     g->timing = on != 0;
     g->ev_marks.clear();
     g->ev_used = 0;
+    return GAP_OK;
+  }
+  if (kind == GAP_STATE_PROFILE_BIN) {
+    if (bytes < 4) return GAP_EINVAL;
+    int32_t b;
+    std::memcpy(&b, host_buf, 4);
+    if (b < 1) return GAP_EINVAL;
+    g->prof_bin = b;
     return GAP_OK;
   }
   if (kind == GAP_STATE_LAUNCH) {

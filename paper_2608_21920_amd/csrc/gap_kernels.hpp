@@ -33,7 +33,26 @@ struct Ctx {
   // their number to pq_count[b]
   uint4* pq;
   int* pq_count;
+  // return spectrum per tube (RET_N doubles): absorbed weight per bin of
+  // log10 gamma, then the total weight and the total weight x gamma
+  double* ret;
 };
+
+constexpr int RET_NB = 64;            // bins of 1/8 decade over gamma in [1, 1e8)
+constexpr int RET_N = RET_NB + 2;
+
+// A lepton of weight w and momentum u absorbed at the surface (Fig. 7's
+// return flux): its bin of log10 gamma, taken in FP64 from the FP32 u.
+__device__ __forceinline__ void return_add(double* ret, int tube, float u, float w) {
+  const double g = sqrt(1.0 + (double)u * (double)u);
+  int b = (int)floor(log10(g) * 8.0);
+  b = b < 0 ? 0 : (b >= RET_NB ? RET_NB - 1 : b);
+  double* r = ret + (size_t)tube * RET_N;
+  const double aw = fabs((double)w);
+  atomicAdd(&r[b], aw);
+  atomicAdd(&r[RET_NB], aw);
+  atomicAdd(&r[RET_NB + 1], aw * g);
+}
 
 constexpr int NSHARD = 64;
 
@@ -429,7 +448,10 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     cx.L.pos[slot] = (uint32_t)npl;
     cx.L.u[slot] = u;
   }
-  if (absorbed) atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
+  if (absorbed) {
+    atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
+    return_add(cx.ret, tube, u, w);
+  }
   if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
 
   // deposit at the new position: node k gets s (T - A), node k+1 gets s A,

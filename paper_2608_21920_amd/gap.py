@@ -24,8 +24,13 @@ FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16,
 ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
-DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING = range(9)
-STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH = range(7)
+(DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN) = range(12)
+(STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
+ STATE_PROFILE_BIN) = range(8)
+# discharge diagnostics: profile groups and the return spectrum's bins
+PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
+RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
 TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail", "conversions"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
@@ -259,6 +264,28 @@ class Gap:
     def set_drive(self, alpha: float, inj_weight: float, tube: int = 0):
         buf = np.array([alpha, inj_weight], np.float64)
         _check(self.lib.gap_set_state(self.h, STATE_DRIVE, int(tube), buf.ctypes.data, buf.nbytes), "set_drive")
+
+    # -- discharge diagnostics
+    def set_profile_bin(self, cells: int):
+        buf = np.array([cells], np.int32)
+        _check(self.lib.gap_set_state(self.h, STATE_PROFILE_BIN, 0, buf.ctypes.data, buf.nbytes), "set_profile_bin")
+        self._prof_bin = int(cells)
+
+    def profile(self, tube=0) -> np.ndarray:
+        """[nb, 6, 3]: per bin and group (PROFILE_GROUPS) the multiplicity, the
+        mean Lorentz factor (photons: mean |x|) and <gamma^-3>."""
+        b = getattr(self, "_prof_bin", 64)
+        nb = (self.n_cells(tube) + b - 1) // b
+        return self._diag(DIAG_PROFILE, tube, 8 * nb * 18).view(np.float64).reshape(nb, 6, 3).copy()
+
+    def peak(self, tube=0) -> dict:
+        v = self._diag(DIAG_PEAK, tube, 48).view(np.float64)
+        return dict(m_pairs=v[0], h=v[1], g3=v[2], m_photons=v[3], e_min=v[4], e_max=v[5])
+
+    def return_spectrum(self, tube=0) -> np.ndarray:
+        """Absorbed weight per 1/8 decade of gamma since the last read, then the
+        total weight and the total weight x gamma (reading resets it)."""
+        return self._diag(DIAG_RETURN, tube, 8 * (RETURN_BINS + 2)).view(np.float64).copy()
 
     def set_launch(self, grid_leptons: int, grid_photons: int, grid_tails: int, resort_every: int):
         """Launch shapes and re-sort interval (the keys autotune() returns)."""

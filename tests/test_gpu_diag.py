@@ -1,0 +1,126 @@
+"""Discharge diagnostics of the HIP path (profile, peak, return flux; Sect. 5,
+Figs. 3, 5, 7) against the oracle's definitions on identical states."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2608_21920_amd import Gap, workloads
+from paper_2608_21920_amd import gap as G
+from paper_2608_21920_amd.inputs import LEPTON_DTYPE, leptons_as_oracle, photons_as_oracle
+from oracle import diag
+from oracle.oracle import Oracle, FLAGS as OF
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def grown(torch_gpu):
+    cfg = dict(workloads.TINY)
+    g = Gap(cfg)
+    g.step(300)
+    assert g.counts()["n_pho"] > 0
+    yield g, cfg
+    g.close()
+
+
+@pytest.mark.parametrize("bin_cells", [64, 37, 1])
+def test_profile_and_peak_match_oracle(grown, bin_cells):
+    g, cfg = grown
+    _say("case: profile and peak of the tiny gap at step 300, bins of %d cells" % bin_cells)
+    g.set_profile_bin(bin_cells)
+    L, P = leptons_as_oracle(g.leptons()), photons_as_oracle(g.photons())
+    N, ppc = cfg["n_cells"], int(cfg.get("ppc_ref", 16))
+    d = g.derived()
+    sums = diag.profile_sums(L, P, N, bin_cells)
+    ref = diag.profile(sums, bin_cells, ppc)
+    got = g.profile()
+    assert got.shape == ref.shape
+    assert np.array_equal(got[:, :, 0], ref[:, :, 0])          # sums of weights: exact in FP64
+    assert np.allclose(got[:, :, 1:], ref[:, :, 1:], rtol=1e-12, atol=0.0)
+    pk, rp = g.peak(), diag.peak(sums, g.field().astype(np.float64), bin_cells, cfg.get("dx", 0.25), d["H"], ppc)
+    _say("  peak m = %.4g at h = %.4g, <gamma^-3> = %.4g" % (pk["m_pairs"], pk["h"], pk["g3"]))
+    assert pk["h"] == rp["h"] and pk["m_pairs"] == rp["m_pairs"] and pk["m_photons"] == rp["m_photons"]
+    assert math.isclose(pk["g3"], rp["g3"], rel_tol=1e-12)
+    assert pk["e_min"] == rp["e_min"] and pk["e_max"] == rp["e_max"]
+
+
+def test_profile_of_one_tube_of_a_batch(torch_gpu):
+    _say("case: profile of each tube of a 3-tube handle vs plain handles")
+    cfgs = [dict(workloads.TINY, n_cells=384, seed=5), dict(workloads.TINY, n_cells=1000, alpha=-1.0, seed=6),
+            dict(workloads.TINY, n_cells=130, b=0.2, seed=7)]
+    gb = Gap(cfgs)
+    gb.step(120)
+    gb.set_profile_bin(32)
+    for t, c in enumerate(cfgs):
+        gp = Gap(c)
+        gp.step(120)
+        gp.set_profile_bin(32)
+        a, b = gb.profile(t), gp.profile()
+        assert np.array_equal(a[:, :, 0], b[:, :, 0]), t
+        assert np.allclose(a, b, rtol=1e-12, atol=0.0), t
+        gp.close()
+    gb.close()
+
+
+def test_return_flux_of_known_absorptions(torch_gpu):
+    # the oracle pin's state: six leptons in cell 0 moving down, zero frozen
+    # field, no QED; all are absorbed in step 1 with their initial momenta
+    _say("case: return flux of six known absorptions")
+    N = 256
+    cfg = dict(n_cells=N, init_kind=2, alpha=0.0, flags=G.FIELD_FROZEN | G.QED_OFF, seed=1, ppc_ref=4,
+               inj_rate=0.0)
+    gam = np.array([1.5, 10 ** 1.31, 10 ** 2.06, 10 ** 4.44, 10 ** 7.93, 10 ** 8.6])
+    L = np.zeros(6, LEPTON_DTYPE)
+    L["cell"], L["frac"] = 0, int(0.1 * (1 << 24))
+    L["u"] = (-np.sqrt(gam ** 2 - 1.0)).astype(np.float32)
+    L["w"] = [-1.0, 1.0, -2.0, 0.5, -1.0, 3.0]
+    L["id"] = np.arange(1, 7, dtype=np.uint64)
+    g = Gap(cfg)
+    g.set_particles(L)
+    g.set_field(np.zeros(N, np.float32), 0.0)
+    g.return_spectrum()                      # clear
+    g.step(1)
+    assert g.counts()["n_absorbed"] == 6
+    r = g.return_spectrum()
+    o = Oracle(dict(cfg, flags=OF["FIELD_FROZEN"] | OF["QED_OFF"]))
+    o.set_state(leptons_as_oracle(L), None, 0.0, 0)
+    o.set_field(np.zeros(N), 0.0)
+    o.step(1)
+    ro = o.return_spectrum()
+    assert np.array_equal(r[:65], ro[:65])
+    assert math.isclose(r[65], ro[65], rel_tol=1e-13)
+    assert np.array_equal(g.return_spectrum(), np.zeros(66))
+    g.close()
+
+
+def test_return_flux_counts_every_absorption(torch_gpu):
+    # tiny gap: every lepton weighs 1, so the returned weight over a run is
+    # the number of absorbed leptons, and the gamma moment is at least it
+    _say("case: return flux over 200 steps of the tiny gap")
+    g = Gap(dict(workloads.TINY, seed=4))
+    g.step(50)
+    c0 = g.counts()
+    g.return_spectrum()
+    g.step(200)
+    r, c1 = g.return_spectrum(), g.counts()
+    n_abs = c1["n_absorbed"] - c0["n_absorbed"]
+    _say("  absorbed %d, returned weight %.1f" % (n_abs, r[64]))
+    assert n_abs > 0
+    assert r[64] == float(n_abs) and r[:64].sum() == r[64]
+    assert r[65] >= r[64]
+    g.close()

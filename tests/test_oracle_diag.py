@@ -1,0 +1,123 @@
+"""Pins of the oracle's discharge diagnostics (oracle/diag.py and the return
+flux of oracle.c) against what their definitions fix (Sect. 5, Figs. 3, 5, 7):
+brute force over small states, closed forms for uniform and mono-energetic
+plasmas, and a return flux whose every absorbed lepton is known."""
+import math
+
+import numpy as np
+
+from oracle import diag
+from oracle.oracle import Oracle, FLAGS as OF
+
+
+def _brute(lep, pho, N, B):
+    nb = (N + B - 1) // B
+    acc = [[[0.0] * 3 for _ in range(6)] for _ in range(nb)]
+    for c, u, w in zip(lep["cell"], lep["u"], lep["w"]):
+        if w == 0.0:
+            continue
+        b = min(max(int(c), 0), N - 1) // B
+        grp = (0 if w < 0 else 2) + (0 if u > 0 else 1)
+        g = math.sqrt(1.0 + u * u)
+        acc[b][grp][0] += abs(w)
+        acc[b][grp][1] += abs(w) * g
+        acc[b][grp][2] += abs(w) / g ** 3
+    for c, x, w in zip(pho["cell"], pho["x"], pho["w"]):
+        if x == 0.0 or abs(x) <= 2.0:
+            continue
+        b = min(max(int(c), 0), N - 1) // B
+        grp = 4 if x > 0 else 5
+        acc[b][grp][0] += w
+        acc[b][grp][1] += w * abs(x)
+    return np.array(acc)
+
+
+def _state(rng, nl, npho, N):
+    lep = dict(cell=rng.integers(0, N, nl), u=rng.normal(0, 30, nl) * (rng.random(nl) < 0.9),
+               w=rng.choice([-2.0, -1.0, 0.0, 1.0, 0.5], nl))
+    pho = dict(cell=rng.integers(0, N, npho), x=rng.choice([-1, 1], npho) * 10 ** rng.uniform(-1, 4, npho),
+               w=rng.choice([1.0, 2.0], npho))
+    pho["x"][::17] = 0.0
+    return lep, pho
+
+
+def test_profile_sums_equal_brute_force():
+    rng = np.random.default_rng(3)
+    N, B = 300, 32   # a ragged last bin
+    lep, pho = _state(rng, 2000, 700, N)
+    got = diag.profile_sums(lep, pho, N, B)
+    ref = _brute(lep, pho, N, B)
+    assert got.shape == (10, 6, 3)
+    assert np.allclose(got, ref, rtol=1e-13, atol=0.0)
+
+
+def test_uniform_cold_plasma_closed_form():
+    # ppc_ref electrons and positrons of unit weight at rest in every cell:
+    # multiplicity 1 per species (u = 0 counts as moving down), gamma 1
+    N, B, ppc = 256, 64, 8
+    cell = np.repeat(np.arange(N), 2 * ppc)
+    w = np.tile(np.r_[-np.ones(ppc), np.ones(ppc)], N)
+    lep = dict(cell=cell, u=np.zeros(cell.size), w=w)
+    pho = dict(cell=np.zeros(0, int), x=np.zeros(0), w=np.zeros(0))
+    p = diag.profile(diag.profile_sums(lep, pho, N, B), B, ppc)
+    assert np.array_equal(p[:, 1, 0], np.ones(4)) and np.array_equal(p[:, 3, 0], np.ones(4))
+    assert np.array_equal(p[:, 0, 0], np.zeros(4)) and np.array_equal(p[:, 2, 0], np.zeros(4))
+    assert np.array_equal(p[:, 1, 1], np.ones(4)) and np.array_equal(p[:, 1, 2], np.ones(4))
+
+
+def test_monoenergetic_beam_moments():
+    # one gamma for every lepton: <gamma> = gamma, <gamma^-3> = gamma^-3
+    gam = 1234.5
+    u = math.sqrt(gam * gam - 1.0)
+    N, B, ppc = 128, 16, 4
+    lep = dict(cell=np.arange(N), u=np.full(N, u), w=np.full(N, 3.0))
+    pho = dict(cell=np.zeros(0, int), x=np.zeros(0), w=np.zeros(0))
+    p = diag.profile(diag.profile_sums(lep, pho, N, B), B, ppc)
+    assert np.allclose(p[:, 2, 0], 3.0 * 16 / (16 * 4), rtol=0, atol=0)
+    assert np.allclose(p[:, 2, 1], gam, rtol=1e-14)
+    assert np.allclose(p[:, 2, 2], gam ** -3, rtol=1e-12)
+
+
+def test_peak_in_zone_and_field_extremes():
+    N, B, ppc, dx = 512, 32, 4, 0.25
+    H = 0.5 * N * dx                        # zone: bins 0..7 (centres below H)
+    cell = np.r_[np.arange(N), np.full(50, 5 * B + 3), np.full(80, 12 * B)]   # bump in bin 5, a bigger one above H
+    u = np.r_[np.full(N, 10.0), np.full(50, -2.0), np.full(80, 1.0)]
+    w = np.r_[np.ones(N), -np.ones(50), np.ones(80)]
+    lep = dict(cell=cell, u=u, w=w)
+    pho = dict(cell=np.array([5 * B + 1, 5 * B + 2, 6 * B]), x=np.array([5.0, -300.0, 7.0]), w=np.array([1.0, 2.0, 4.0]))
+    E = np.sin(np.arange(N) * 0.1)
+    pk = diag.peak(diag.profile_sums(lep, pho, N, B), E, B, dx, H, ppc)
+    assert pk["h"] == (5 + 0.5) * B * dx
+    assert pk["m_pairs"] == (B + 50) / (B * ppc)
+    g_fast, g_slow = math.sqrt(101.0), math.sqrt(5.0)
+    assert math.isclose(pk["g3"], (B * g_fast ** -3 + 50 * g_slow ** -3) / (B + 50), rel_tol=1e-13)
+    assert pk["m_photons"] == 3.0 / (B * ppc)
+    assert pk["e_min"] == np.min(E) and pk["e_max"] == np.max(E)
+
+
+def test_return_flux_of_known_absorptions():
+    # leptons in cell 0 moving down fast enough to cross h = 0 in one step
+    # (|beta| 0.45 > xi), zero field: every one is absorbed in step 1 with its
+    # initial momentum, so the flux is fixed by their gammas and weights
+    N = 256
+    cfg = dict(n_cells=N, init_kind=2, alpha=0.0, flags=OF["FIELD_FROZEN"] | OF["QED_OFF"], seed=1,
+               ppc_ref=4, inj_rate=0.0)
+    o = Oracle(cfg)
+    gam = np.array([1.5, 10 ** 1.31, 10 ** 2.06, 10 ** 4.44, 10 ** 7.93, 10 ** 8.6])
+    u = -np.sqrt(gam ** 2 - 1.0)
+    w = np.array([-1.0, 1.0, -2.0, 0.5, -1.0, 3.0])
+    lep = dict(cell=np.zeros(6, np.int32), xi=np.full(6, 0.1), u=u, w=w, id=np.arange(1, 7, dtype=np.uint64))
+    o.set_state(lep, None, 0.0, 0)
+    o.set_field(np.zeros(N), 0.0)
+    o.step(1)
+    assert o.counts()["n_absorbed"] == 6
+    r = o.return_spectrum()
+    ref = np.zeros(66)
+    for gi, wi in zip(gam, w):
+        ref[min(int(math.floor(8 * math.log10(gi))), 63)] += abs(wi)
+    ref[64] = np.abs(w).sum()
+    ref[65] = float((np.abs(w) * gam).sum())
+    assert np.array_equal(r[:64], ref[:64])
+    assert r[64] == ref[64] and math.isclose(r[65], ref[65], rel_tol=1e-14)
+    assert np.array_equal(o.return_spectrum(), np.zeros(66))   # reading cleared it
