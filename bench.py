@@ -256,6 +256,25 @@ def bench_adjoint(window=2000, ckpt=100):
                        "n_co dx per step, frozen QED, loss = time-averaged <E^2>")
 
 
+def bench_diagnostics(g, calls=5):
+    """The discharge diagnostics on the grown production state: wall time of
+    one peak-multiplicity call (bins of 64 cells: zeroing the sums, the profile
+    pass over both stores, the peak kernel, the 48-byte copy back), with 12 B
+    per particle read (position, momentum or energy, weight) as its bytes."""
+    g.set_profile_bin(64)
+    pk = g.peak()
+    g.sync()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        g.peak()
+    ms = (time.perf_counter() - t0) * 1e3 / calls
+    c = g.counts()
+    n = c["n_lep"] + c["n_pho"]
+    return dict(peak_call_ms=ms, particles=n, gbs_at_12_bytes=12.0 * n / (ms / 1e3) / 1e9,
+                m_pairs_peak=pk["m_pairs"], h_peak=pk["h"], g3_at_peak=pk["g3"], e_min=pk["e_min"],
+                e_max=pk["e_max"])
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size, for scaling HBM traffic counters."""
     import torch
@@ -379,6 +398,7 @@ def main():
                     for k, v in kern.items()},
         "timing_ms": {k: round(v[1], 3) for k, v in tim.items()} if tim else None,
         "ms_per_step_with_kernel_events": ms_i / a.steps if ms_i else None,
+        "diagnostics": bench_diagnostics(g),
     }
     g.close()
     if not a.no_batched:

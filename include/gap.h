@@ -160,10 +160,12 @@ int gap_sync(gap_t* g);
                                 photon multiplicity (|x| > 2) there, then min E and max E
                                 over the cells                                              */
 #define GAP_DIAG_RETURN  11  /* double[66]: weight of the leptons absorbed at h = 0 since the
-                                last read, per bin of 1/8 decade of gamma (bin
-                                floor(8 log10 gamma), clamped to [0, 63], gamma from the
-                                leptons' momentum when they were absorbed, in FP64), then the
-                                total weight and the total weight x gamma; reading resets it */
+                                last read, per bin of 1/8 decade of gamma: bin b holds gamma
+                                in [10^(b/8), 10^((b+1)/8)) (the last bin everything above),
+                                decided on u^2 = gamma^2 - 1 of the absorbed lepton's FP32
+                                momentum, taken exactly in FP64 against edges 10^(b/4) - 1;
+                                then the total weight and the total weight x gamma (gamma in
+                                FP32); reading resets it                                    */
 
 /* indices of GAP_DIAG_COUNTS */
 #define GAP_C_LEPTONS     0   /* live leptons                      */

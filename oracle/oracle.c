@@ -669,13 +669,14 @@ static void step_once(orc_sim* s) {
       s->dq += (int64_t)sg * wt_fixed(l->w);
       s->n_absorbed++;
       {
-        double ga = sqrt(1.0 + l->u * l->u);
-        int b = (int)floor(log10(ga) * 8.0);
-        if (b < 0) b = 0;
-        if (b >= ORC_RET_NB) b = ORC_RET_NB - 1;
+        /* bin b holds gamma in [10^(b/8), 10^((b+1)/8)): the last b whose
+         * lower edge in u^2 = gamma^2 - 1, 10^(b/4) - 1, u^2 reaches */
+        double u2 = l->u * l->u;
+        int b = 0;
+        while (b + 1 < ORC_RET_NB && pow(10.0, (b + 1) / 4.0) - 1.0 <= u2) ++b;
         s->ret[b] += fabs(l->w);
         s->ret[ORC_RET_NB] += fabs(l->w);
-        s->ret[ORC_RET_NB + 1] += fabs(l->w) * ga;
+        s->ret[ORC_RET_NB + 1] += fabs(l->w) * sqrt(1.0 + u2);
       }
       l->w = 0.0;
       continue;

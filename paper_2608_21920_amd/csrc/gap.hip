@@ -247,6 +247,7 @@ struct gap_t {
   // discharge diagnostics: return spectra [n_tubes][RET_N]; profile sums and
   // results for the largest tube at one cell per bin
   double* ret = nullptr;
+  double* ret_thr = nullptr;           // [RET_NB]: lower bin edges in u^2
   double* prof_acc = nullptr;
   double* prof_out = nullptr;
   int prof_bin = 64;                   // cells per profile bin
@@ -379,6 +380,7 @@ Ctx make_ctx(gap_t* g) {
   c.pq = g->pq;
   c.pq_count = g->pq_count;
   c.ret = g->ret;
+  c.ret_thr = g->ret_thr;
   return c;
 }
 
@@ -1044,6 +1046,13 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   int max_n = 1;
   for (int t = 0; t < n_tubes; ++t) max_n = std::max(max_n, p[t].n_cells);
   g->ret = (double*)dalloc(g, sizeof(double) * RET_N * (size_t)n_tubes);
+  g->ret_thr = (double*)dalloc(g, sizeof(double) * RET_NB);
+  if (g->ret_thr) {
+    // bin b: gamma in [10^(b/8), 10^((b+1)/8)), i.e. u^2 = gamma^2 - 1 from 10^(b/4) - 1
+    std::vector<double> thr(RET_NB);
+    for (int b = 0; b < RET_NB; ++b) thr[b] = std::pow(10.0, b / 4.0) - 1.0;
+    HIPCHK(hipMemcpy(g->ret_thr, thr.data(), sizeof(double) * RET_NB, hipMemcpyHostToDevice));
+  }
   g->prof_acc = (double*)dalloc(g, sizeof(double) * PROF_G * PROF_M * (size_t)max_n);
   g->prof_out = (double*)dalloc(g, sizeof(double) * PROF_G * 3 * (size_t)max_n);
   if (!g->ret || !g->prof_acc || !g->prof_out) return GAP_ENOMEM;

@@ -34,24 +34,31 @@ struct Ctx {
   uint4* pq;
   int* pq_count;
   // return spectrum per tube (RET_N doubles): absorbed weight per bin of
-  // log10 gamma, then the total weight and the total weight x gamma
+  // log10 gamma, then the total weight and the total weight x gamma; the
+  // bins' lower edges in u^2 = gamma^2 - 1 (ret_thr[b] = 10^(b/4) - 1)
   double* ret;
+  const double* ret_thr;
 };
 
 constexpr int RET_NB = 64;            // bins of 1/8 decade over gamma in [1, 1e8)
 constexpr int RET_N = RET_NB + 2;
 
 // A lepton of weight w and momentum u absorbed at the surface (Fig. 7's
-// return flux): its bin of log10 gamma, taken in FP64 from the FP32 u.
-__device__ __forceinline__ void return_add(double* ret, int tube, float u, float w) {
-  const double g = sqrt(1.0 + (double)u * (double)u);
-  int b = (int)floor(log10(g) * 8.0);
-  b = b < 0 ? 0 : (b >= RET_NB ? RET_NB - 1 : b);
+// return flux): its bin is the last whose lower edge in u^2 it reaches, u^2
+// taken exactly in FP64 from the FP32 u (a binary search over the edges, so
+// that the lepton pass keeps its registers); gamma for the energy moment in
+// FP32.
+__device__ __forceinline__ void return_add(double* ret, const double* thr, int tube, float u, float w) {
+  const double u2 = (double)u * (double)u;
+  int b = 0;
+#pragma unroll
+  for (int st = RET_NB / 2; st >= 1; st >>= 1)
+    if (thr[b + st] <= u2) b += st;
   double* r = ret + (size_t)tube * RET_N;
-  const double aw = fabs((double)w);
-  atomicAdd(&r[b], aw);
-  atomicAdd(&r[RET_NB], aw);
-  atomicAdd(&r[RET_NB + 1], aw * g);
+  const float aw = fabsf(w);
+  atomicAdd(&r[b], (double)aw);
+  atomicAdd(&r[RET_NB], (double)aw);
+  atomicAdd(&r[RET_NB + 1], (double)(aw * __builtin_amdgcn_sqrtf(1.0f + u * u)));
 }
 
 constexpr int NSHARD = 64;
@@ -450,7 +457,7 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   }
   if (absorbed) {
     atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
-    return_add(cx.ret, tube, u, w);
+    return_add(cx.ret, cx.ret_thr, tube, u, w);
   }
   if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
 

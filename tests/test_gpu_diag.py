@@ -103,7 +103,7 @@ def test_return_flux_of_known_absorptions(torch_gpu):
     o.step(1)
     ro = o.return_spectrum()
     assert np.array_equal(r[:65], ro[:65])
-    assert math.isclose(r[65], ro[65], rel_tol=1e-13)
+    assert math.isclose(r[65], ro[65], rel_tol=1e-6)        # gamma in FP32 on the GPU
     assert np.array_equal(g.return_spectrum(), np.zeros(66))
     g.close()
 
