@@ -46,50 +46,111 @@ __device__ __forceinline__ void prof_wave_add(int key, double v0, double v1, dou
   }
 }
 
-// Moments of tube `tube`'s particles (sorted regions and tails of both
-// stores, one slot per thread and 256-slot row) into acc[nb][PROF_G][PROF_M],
-// which the caller has zeroed.
+// Profile moments of one slot: key = bin * PROF_G + group (-1: none).
+__device__ __forceinline__ int prof_moments(const Ctx& cx, bool lep, uint32_t slot, int tile, int tube, int B,
+                                            double* v0, double* v1, double* v2) {
+  *v0 = *v1 = *v2 = 0.0;
+  if (tile < 0) return -1;
+  const Tile tl = cx.tiles[tile];
+  const float a = lep ? cx.L.w[slot] : cx.P.x[slot];
+  if (tl.tube != tube || a == 0.0f) return -1;
+  const Tube& T = cx.tubes[tube];
+  const uint32_t pos = lep ? cx.L.pos[slot] : cx.P.pos[slot];
+  int cell = tl.base + (int)(pos >> FRAC);
+  if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
+  const int bin = min(max(cell, 0), T.N - 1) / B;
+  if (lep) {
+    const double u = (double)cx.L.u[slot];
+    const double w = fabs((double)a);
+    const double g = sqrt(1.0 + u * u);
+    *v0 = w;
+    *v1 = w * g;
+    *v2 = w / (g * g * g);
+    return bin * PROF_G + (a < 0.0f ? 0 : 2) + (u > 0.0 ? 0 : 1);
+  }
+  if (!(fabsf(a) > 2.0f)) return -1;
+  const double w = (double)cx.P.w[slot];
+  *v0 = w;
+  *v1 = w * fabs((double)a);
+  return bin * PROF_G + 4 + (a > 0.0f ? 0 : 1);
+}
+
+constexpr int PROF_LW = 80;   // LDS window of bins per workgroup (bins of >= 4 cells cover a tile's 256-cell window)
+
+// Moments of tube `tube`'s particles into acc[nb][PROF_G][PROF_M], which the
+// caller has zeroed.  Each workgroup takes a contiguous range of the sorted
+// rows of each store (one slot per thread and 256-slot row): their particles
+// lie within a tile's window, so with bins of at least 4 cells they are summed
+// into an LDS window of bins (FP64 LDS atomics), flushed to acc when the tile
+// changes and at the end; tail rows (and narrower bins) add to acc directly,
+// one atomic per distinct key of a wave.
 __global__ __launch_bounds__(TPB) void k_profile(Ctx cx, int tube, int B, int nb, double* acc) {
-  const long long Sl = cx.lc->n_sorted_chunks * CHUNK, tl_ = cx.lc->tail;
-  const long long Sp = cx.pc->n_sorted_chunks * CHUNK, tp_ = cx.pc->tail;
-  const long long nql = (Sl + tl_ + TPB - 1) / TPB, nqp = (Sp + tp_ + TPB - 1) / TPB;
-  for (long long q = blockIdx.x; q < nql + nqp; q += gridDim.x) {
-    const bool lep = q < nql;
-    const long long qq = lep ? q : q - nql;
-    const long long S = lep ? Sl : Sp, tail = lep ? tl_ : tp_;
-    uint32_t slot;
-    int tile;
-    piece_slot(qq, S / TPB, S, tail, lep ? cx.lchunk : cx.pchunk, lep ? cx.ltt : cx.ptt, &slot, &tile);
-    int key = -1;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-    if (tile >= 0) {
-      const Tile tl = cx.tiles[tile];
-      const float a = lep ? cx.L.w[slot] : cx.P.x[slot];
-      if (tl.tube == tube && a != 0.0f) {
-        const Tube& T = cx.tubes[tube];
-        const uint32_t pos = lep ? cx.L.pos[slot] : cx.P.pos[slot];
-        int cell = tl.base + (int)(pos >> FRAC);
-        if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
-        const int bin = min(max(cell, 0), T.N - 1) / B;
-        if (lep) {
-          const double u = (double)cx.L.u[slot];
-          const double w = fabs((double)a);
-          const double g = sqrt(1.0 + u * u);
-          const int grp = (a < 0.0f ? 0 : 2) + (u > 0.0 ? 0 : 1);
-          key = bin * PROF_G + grp;
-          v0 = w;
-          v1 = w * g;
-          v2 = w / (g * g * g);
-        } else if (fabsf(a) > 2.0f) {
-          const double w = (double)cx.P.w[slot];
-          key = bin * PROF_G + 4 + (a > 0.0f ? 0 : 1);
-          v0 = w;
-          v1 = w * fabs((double)a);
+  __shared__ double s_w[PROF_LW * PROF_G * PROF_M];
+  const bool win = B >= 4;
+  for (int j = threadIdx.x; j < PROF_LW * PROF_G * PROF_M; j += blockDim.x) s_w[j] = 0.0;
+  int lo = -1;                              // first bin of the LDS window (block-uniform)
+  __syncthreads();
+  for (int sp = 0; sp < 2; ++sp) {
+    const bool lep = sp == 0;
+    const Ctl* ctl = lep ? cx.lc : cx.pc;
+    const long long S = ctl->n_sorted_chunks * CHUNK, tail = ctl->tail;
+    const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+    const int32_t* chunk = lep ? cx.lchunk : cx.pchunk;
+    const int32_t* tt = lep ? cx.ltt : cx.ptt;
+    // sorted rows: a contiguous range per workgroup
+    const long long r0 = nsq * blockIdx.x / gridDim.x, r1 = nsq * (blockIdx.x + 1) / gridDim.x;
+    for (long long q = r0; q < r1; ++q) {
+      uint32_t slot;
+      int tile;
+      piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
+      double v0, v1, v2;
+      const int key = prof_moments(cx, lep, slot, tile, tube, B, &v0, &v1, &v2);
+      if (win) {
+        // the row's tile (uniform: a sorted row lies in one chunk) sets the window
+        const int wl = __builtin_amdgcn_readfirstlane(max(cx.tiles[tile].base, 0) / B);
+        if (wl != lo) {
+          __syncthreads();
+          if (lo >= 0)
+            for (int j = threadIdx.x; j < PROF_LW * PROF_G * PROF_M; j += blockDim.x) {
+              const double v = s_w[j];
+              if (v != 0.0) {
+                const int bb = lo + j / (PROF_G * PROF_M);
+                if (bb < nb) atomicAdd(&acc[(size_t)lo * PROF_G * PROF_M + j], v);
+                s_w[j] = 0.0;
+              }
+            }
+          lo = wl;
+          __syncthreads();
         }
+        const int kb = key >= 0 ? key / PROF_G - lo : -1;
+        const bool in = kb >= 0 && kb < PROF_LW;
+        if (in) {
+          double* e = &s_w[((size_t)kb * PROF_G + key % PROF_G) * PROF_M];
+          atomicAdd(&e[0], v0);
+          atomicAdd(&e[1], v1);
+          if (v2 != 0.0) atomicAdd(&e[2], v2);
+        }
+        prof_wave_add(in ? -1 : key, v0, v1, v2, acc);   // (every lane takes part)
+      } else {
+        prof_wave_add(key, v0, v1, v2, acc);
       }
     }
-    prof_wave_add(key, v0, v1, v2, acc);
+    // tail rows: strided over all workgroups
+    for (long long q = nsq + blockIdx.x; q < nq; q += gridDim.x) {
+      uint32_t slot;
+      int tile;
+      piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
+      double v0, v1, v2;
+      const int key = prof_moments(cx, lep, slot, tile, tube, B, &v0, &v1, &v2);
+      prof_wave_add(key, v0, v1, v2, acc);
+    }
   }
+  __syncthreads();
+  if (lo >= 0)
+    for (int j = threadIdx.x; j < PROF_LW * PROF_G * PROF_M; j += blockDim.x) {
+      const double v = s_w[j];
+      if (v != 0.0 && lo + j / (PROF_G * PROF_M) < nb) atomicAdd(&acc[(size_t)lo * PROF_G * PROF_M + j], v);
+    }
 }
 
 // Sums to the profile: out[nb][PROF_G][3] = multiplicity, <gamma> (photons
