@@ -355,14 +355,15 @@ def main():
     if not a.graph:
         ms_i, d, tim, _ = run(a.steps, True)
         # algorithmic bytes of the sorted-region kernels and of the tail kernels
-        units = dict(leptons=(d["lep_steps"] - d["lep_steps_tail"], d["n_emit_eval"] - d["emit_eval_tail"]),
-                     photons=(d["pho_steps"] - d["pho_steps_tail"], d["n_conv_eval"] - d["conv_eval_tail"]),
-                     leptons_tail=(d["lep_steps_tail"], d["emit_eval_tail"]),
-                     photons_tail=(d["pho_steps_tail"], d["conv_eval_tail"]))
-        for name, (n_steps, n_eval) in units.items():
-            lep = name.startswith("leptons")
-            byt = B_LEP * n_steps + B_EMIT_EVAL * n_eval if lep else B_PHO * n_steps
-            byt_min = byt if lep else B_PHO_MIN * n_steps + B_CONV_EVAL_MIN * n_eval
+        # (the tail passes of both species are one launch)
+        lep_b = lambda n_steps, n_eval: B_LEP * n_steps + B_EMIT_EVAL * n_eval
+        pho_b = lambda n_steps, n_eval: B_PHO * n_steps
+        pho_min = lambda n_steps, n_eval: B_PHO_MIN * n_steps + B_CONV_EVAL_MIN * n_eval
+        lt, pt = (d["lep_steps_tail"], d["emit_eval_tail"]), (d["pho_steps_tail"], d["conv_eval_tail"])
+        units = dict(leptons=(lep_b(d["lep_steps"] - lt[0], d["n_emit_eval"] - lt[1]),) * 2,
+                     photons=(pho_b(d["pho_steps"] - pt[0], 0), pho_min(d["pho_steps"] - pt[0], d["n_conv_eval"] - pt[1])),
+                     tails=(lep_b(*lt) + pho_b(*pt), lep_b(*lt) + pho_min(*pt)))
+        for name, (byt, byt_min) in units.items():
             n, tms = tim[name]
             if name == "photons":
                 # the sorted photon pass is two launches: streaming, then the

@@ -142,9 +142,10 @@ int gap_sync(gap_t* g);
 #define GAP_DIAG_NODE_E   6  /* float[N+1]: node field used by the gather                   */
 #define GAP_DIAG_DERIVED  7  /* double[8]: d_cm, lambda~, R~, dt, H, w0, s_co, N            */
 #define GAP_DIAG_TIMING   8  /* double[16]: (launches, summed ms) of the lepton pass, photon
-                                pass, field, re-sort, prologue, lepton tail pass, photon
-                                tail pass and conversion draws since timing was enabled or
-                                last read (tube ignored; resets the record)                 */
+                                pass, field, re-sort, prologue, tail passes of both
+                                species (one launch), an unused pair (always 0) and
+                                conversion draws since timing was enabled or last read
+                                (tube ignored; resets the record)                           */
 /* Discharge diagnostics (Sect. 5: Fig. 3 rows 5-7, Fig. 5, Fig. 7).  Bins are
  * GAP_STATE_PROFILE_BIN cells wide (default 64), nb = ceil(N / bin).  Groups,
  * in order: electrons moving up (u > 0), electrons moving down, positrons up,

@@ -394,7 +394,7 @@ hipEvent_t next_event(gap_t* g) {
 }
 
 // kernel ids of the timing diagnostic
-enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_LEPTAIL = 5, KT_PHOTAIL = 6,
+enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_TAILS = 5, KT_UNUSED = 6,
        KT_CONV = 7, KT_N = 8 };
 
 struct Timer {
@@ -542,15 +542,18 @@ void win_release(gap_t* g) {
   g->win = WinState{};
 }
 
+// Workgroups of the fused tail launch: each role takes the tail workgroup
+// count rounded up to a multiple of eight (the roles alternate in eights).
+int tails_grid(const gap_t* g) { return 2 * ((g->grid_tail + 7) / 8 * 8); }
+
 // One step of a window: no merge, no re-sort (slots stay put).
 void enqueue_window_step(gap_t* g) {
   Ctx cx = make_ctx(g);
   k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
   k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
-  k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
   k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
   k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
-  k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+  k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx);
   field_pass(g, 0);
   ++g->host_step;
 }
@@ -735,10 +738,9 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
                                       w.M, 0, g->err);
       D2D(w.teb + j * (size_t)g->total_nodes, g->ebar, sizeof(float) * g->total_nodes);
       k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
-      k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
       k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
       k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
-      k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx);
+      k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx);
       field_pass(g, 0);
       ++g->host_step;
       D2D(w.tE + (j + 1) * (size_t)g->total_cells, g->E, sizeof(float) * g->total_cells);
@@ -851,8 +853,7 @@ void enqueue_step(gap_t* g) {
   }
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
   if (two) (void)hipStreamWaitEvent(g->s, g->ev_pre, 0);
-  { Timer t(g, KT_LEPTAIL); k_leptons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
-  { Timer t(g, KT_PHOTAIL); k_photons_tail<<<g->grid_tail, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_TAILS); k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx); }
   { Timer t(g, KT_FIELD); field_pass(g, 0); }
   if (++g->since_rb >= g->R) {
     if (two) join_photon_side(g);
@@ -1315,11 +1316,13 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GAP_EDEVICE;
   gap_t* g = new gap_t();
   g->s = (hipStream_t)stream;
-  // default priority, like every stream of the library
+  // default priority, like every stream of the library; the events order the two
+  // streams on this device only, so they need no system-scope fence
+  constexpr unsigned kSyncEvent = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_l, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_pre, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_p, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&g->ev_l, kSyncEvent) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_pre, kSyncEvent) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_p, kSyncEvent) != hipSuccess) {
     release(g);
     delete g;
     return GAP_EDEVICE;

@@ -637,7 +637,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
 
 // Lepton pass over the tail (particles appended since the last re-sort):
 // one slot per thread, each lane with its own tile; global gather/deposit.
-__global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
+__device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
   const Room proom = load_room(cx.pc);
   LocalCounts lcn;
   lcn.clear();
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(TPB) void k_leptons_tail(Ctx cx) {
   const long long tail = cx.lc->tail_snap;
   const long long nq = (tail + TPB - 1) / TPB;
   const KC kc0 = load_kc(cx, 0, false);
-  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+  for (long long q = bid; q < nq; q += nblk) {
     uint32_t slot;
     int tile;
     piece_slot(S / TPB + q, S / TPB, S, tail, cx.lchunk, cx.ltt, &slot, &tile);
@@ -989,7 +989,7 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
+__device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
   const Room lroom = load_room(cx.lc);
   LocalCounts lcn;
   lcn.clear();
@@ -998,7 +998,7 @@ __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
   const long long tail = cx.pc->tail_snap;
   const long long nq = (tail + TPB - 1) / TPB;
   const KC kc0 = load_kc(cx, 0, true);
-  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+  for (long long q = bid; q < nq; q += nblk) {
     uint32_t slot;
     int tile;
     piece_slot(S / TPB + q, S / TPB, S, tail, cx.pchunk, cx.ptt, &slot, &tile);
@@ -1007,6 +1007,20 @@ __global__ __launch_bounds__(TPB) void k_photons_tail(Ctx cx) {
     const int32_t n0 = cx.P.n0[slot];
     photon_one<false>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr, lroom);
   }
+}
+
+// Both tail passes in one launch.  They touch disjoint data: each reads its
+// own store up to the snapshot taken before it, and its births (photons from
+// the leptons, pairs from the photons) go past the other store's snapshot.
+// Workgroups alternate roles in groups of eight, so both species spread over
+// every XCD; the grid is a multiple of 16, so each role gets half of it with
+// indexes 0 .. half - 1.
+__global__ __launch_bounds__(TPB) void k_tails(Ctx cx) {
+  const int bx = blockIdx.x;
+  const int bid = ((bx >> 4) << 3) | (bx & 7);
+  const int nblk = (int)(gridDim.x >> 1);
+  if ((bx >> 3) & 1) photons_tail(cx, bid, nblk);
+  else leptons_tail(cx, bid, nblk);
 }
 
 // ------------------------------------------------------------------ field

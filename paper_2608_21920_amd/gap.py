@@ -31,7 +31,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
 # discharge diagnostics: profile groups and the return spectrum's bins
 PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
 RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
-TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "leptons_tail", "photons_tail", "conversions"]
+TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "tails", "unused", "conversions"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
               "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
