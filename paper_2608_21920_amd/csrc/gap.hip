@@ -8,6 +8,7 @@
 #include "gap_diag.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -199,6 +200,7 @@ struct gap_t {
   // ev_p: the photon side of the last enqueued step done.
   hipStream_t s2 = nullptr;
   hipEvent_t ev_l = nullptr, ev_pre = nullptr, ev_p = nullptr;
+  bool ev_l_bound = false;   // ev_l is already the completion of the last field kernel on the caller's stream
   bool s2_pending = false;  // photon-side work not yet joined into the caller's stream
   bool capturing = false;   // graph capture: everything stays on the caller's stream
   gap_allocator al{};
@@ -221,6 +223,7 @@ struct gap_t {
   int n_fb = 0;
   long long* part = nullptr;
   long long* part2 = nullptr;
+  unsigned long long* fscan = nullptr;   // single-pass field: 4 words per block, epoch, done count
   float* tab = nullptr;
   int* err = nullptr;
   long long* live = nullptr;
@@ -423,6 +426,7 @@ FieldCtx make_fctx(gap_t* g, int mode) {
   f.part2 = g->part2;
   f.err = g->err;
   f.pc = g->pho.ctl;
+  f.fs = g->fscan;
   f.mode = mode;
   return f;
 }
@@ -472,11 +476,21 @@ void rebucket_all(gap_t* g) {
   rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1));
 }
 
-void field_pass(gap_t* g, int mode) {
+// With `done`, the single-pass kernel's own completion is recorded into that
+// event (no separate marker on the stream); returns whether it was.
+bool field_pass(gap_t* g, int mode, hipEvent_t done = nullptr) {
   FieldCtx f = make_fctx(g, mode);
+  if (!g->any_periodic) {
+    if (done) hipExtLaunchKernelGGL(k_field_1p, dim3(g->n_fb), dim3(FB_THREADS), 0, g->s, nullptr, done, 0, f);
+    else k_field_1p<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+    return done != nullptr;
+  }
+  // a periodic tube subtracts the mean field, which needs the whole tube's
+  // sums before any output: two passes
   k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
   k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
-  if (g->any_periodic) k_field_periodic_ends<<<(g->n_tubes + 63) / 64, 64, 0, g->s>>>(f, g->n_tubes);
+  k_field_periodic_ends<<<(g->n_tubes + 63) / 64, 64, 0, g->s>>>(f, g->n_tubes);
+  return false;
 }
 
 // Node charge and field from the current particles and E_s (no drive).
@@ -829,7 +843,7 @@ void join_photon_side(gap_t* g) {
 // sorted lepton pass of a step starts without waiting, and one step costs
 // one wait on each stream.  Captured graphs keep every kernel on the
 // caller's stream, in an order that respects the same dependencies.
-void enqueue_step(gap_t* g) {
+void enqueue_step(gap_t* g, bool more) {
   const bool two = !g->capturing;
   const bool merge = g->merge_on && g->host_step % g->merge_every == 0;
   if (merge) {
@@ -840,11 +854,16 @@ void enqueue_step(gap_t* g) {
   hipStream_t ps = g->s;
   if (two) {
     ps = g->s2;
-    (void)hipEventRecord(g->ev_l, g->s);
+    // the previous step's field kernel carries ev_l when nothing came after it
+    if (merge || !g->ev_l_bound) (void)hipEventRecord(g->ev_l, g->s);
     (void)hipStreamWaitEvent(g->s2, g->ev_l, 0);
   }
-  { Timer t(g, KT_PRE, ps); k_pre<<<1, PRE_THREADS, 0, ps>>>(cx, g->n_tubes); }
-  if (two) (void)hipEventRecord(g->ev_pre, g->s2);
+  g->ev_l_bound = false;
+  {
+    Timer t(g, KT_PRE, ps);
+    if (two) hipExtLaunchKernelGGL(k_pre, dim3(1), dim3(PRE_THREADS), 0, ps, nullptr, g->ev_pre, 0, cx, g->n_tubes);
+    else k_pre<<<1, PRE_THREADS, 0, ps>>>(cx, g->n_tubes);
+  }
   { Timer t(g, KT_PHOTONS, ps); k_photons<<<g->grid_pho, TPB, 0, ps>>>(cx); }
   { Timer t(g, KT_CONV, ps); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, ps>>>(cx, g->grid_pho); }
   if (two) {
@@ -854,7 +873,14 @@ void enqueue_step(gap_t* g) {
   { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
   if (two) (void)hipStreamWaitEvent(g->s, g->ev_pre, 0);
   { Timer t(g, KT_TAILS); k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx); }
-  { Timer t(g, KT_FIELD); field_pass(g, 0); }
+  {
+    // another step follows at once, with no re-sort or merge in between:
+    // its photon side can wait on the field kernel itself
+    const bool bind = two && more && g->since_rb + 1 < g->R &&
+                      !(g->merge_on && (g->host_step + 1) % g->merge_every == 0);
+    Timer t(g, KT_FIELD);
+    g->ev_l_bound = field_pass(g, 0, bind ? g->ev_l : nullptr);
+  }
   if (++g->since_rb >= g->R) {
     if (two) join_photon_side(g);
     Timer t(g, KT_RESORT);
@@ -869,6 +895,7 @@ int read_err(gap_t* g) {
   if (hipMemcpy(&e, g->err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return GAP_EDEVICE;
   if (e & E_TILE) g->sticky = GAP_ETILE;
   else if (e & E_NAN) g->sticky = GAP_ENAN;
+  else if (e & E_SCAN) g->sticky = GAP_EDEVICE;
   else if (e & E_CAP) g->sticky = GAP_ECAP;
   return g->sticky;
 }
@@ -1029,12 +1056,13 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->fb = (FBlk*)dalloc(g, sizeof(FBlk) * g->n_fb);
   g->part = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
   g->part2 = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
+  g->fscan = (unsigned long long*)dalloc(g, sizeof(unsigned long long) * (4 * (size_t)g->n_fb + 2));
   g->tab = (float*)dalloc(g, sizeof(float) * 2 * (NTAB + 1));
   g->err = (int*)dalloc(g, sizeof(int));
   g->live = (long long*)dalloc(g, sizeof(long long) * n_tubes);
   g->shard = (long long*)dalloc(g, sizeof(long long) * n_tubes * NSHARD * C_N);
   if (!g->shard) return GAP_ENOMEM;
-  if (!g->tubes || !g->tiles || !g->rho || !g->rho_last || !g->E || !g->ebar || !g->fb || !g->part || !g->part2 ||
+  if (!g->tubes || !g->tiles || !g->rho || !g->rho_last || !g->E || !g->ebar || !g->fb || !g->part || !g->part2 || !g->fscan ||
       !g->tab || !g->err || !g->live)
     return GAP_ENOMEM;
   int e;
@@ -1194,7 +1222,7 @@ int graph_capture(gap_t* g, int64_t n) {
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal));
   g->capturing = true;
-  for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  for (int64_t i = 0; i < n; ++i) enqueue_step(g, i + 1 < n);
   g->capturing = false;
   hipError_t e = hipStreamEndCapture(g->s, &graph);
   g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_since = g->since_rb;
@@ -1218,7 +1246,7 @@ int timed_steps(gap_t* g, int64_t n, double* kt, double* wall_ms) {
   hipEvent_t a = next_event(g), b = next_event(g);
   if (!a || !b) return GAP_EDEVICE;
   HIPCHK(hipEventRecord(a, g->s));
-  for (int64_t i = 0; i < n; ++i) enqueue_step(g);
+  for (int64_t i = 0; i < n; ++i) enqueue_step(g, i + 1 < n);
   join_photon_side(g);
   HIPCHK(hipEventRecord(b, g->s));
   HIPCHK(hipEventSynchronize(b));
@@ -1340,7 +1368,7 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
 
 int gap_step(gap_t* g, int64_t n_steps) {
   if (!g || n_steps < 0) return GAP_EINVAL;
-  for (int64_t i = 0; i < n_steps; ++i) enqueue_step(g);
+  for (int64_t i = 0; i < n_steps; ++i) enqueue_step(g, i + 1 < n_steps);
   join_photon_side(g);   // the caller's stream holds all the work again
   if (hipGetLastError() != hipSuccess) return GAP_EDEVICE;
   return g->sticky;

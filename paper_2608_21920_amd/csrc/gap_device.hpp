@@ -45,7 +45,7 @@ enum : uint32_t {
 };
 
 // sticky device error bits
-enum : int { E_CAP = 1, E_TILE = 2, E_NAN = 4 };
+enum : int { E_CAP = 1, E_TILE = 2, E_NAN = 4, E_SCAN = 8 };
 
 // Per-tube constants and mutable scalars (device memory).
 struct Tube {

@@ -1044,6 +1044,7 @@ struct FieldCtx {
   long long* part;    // per block: sum rho
   long long* part2;   // per block: sum rho_i (N - i)
   int* err;
+  unsigned long long* fs;   // single-pass form: a four-word record per block, then the epoch and a done count
   Ctl* pc;            // photon store: its tail snapshot for the next step is taken here
   int mode;           // 0: step (surface update, step += 1); 1: rebuild E only
 };
@@ -1193,6 +1194,177 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && f.mode == 0) {
     clamp_tail(f.pc);
     f.pc->tail_snap = f.pc->tail;
+  }
+}
+
+// Single-pass form of the two passes above, for grids without periodic tubes.
+// Each block publishes its charge sum, finds the sum over its tube's earlier
+// blocks by looking back over their records (a block's own sum, or its
+// inclusive prefix once known, the nearest such ending the search), publishes
+// its inclusive prefix, then scans.  A block waits only on blocks of lower
+// index, which every XCD dispatches before it, so each wait ends; a bounded
+// spin turns a record that never appears into an error rather than a hang.
+// The tube's first block updates E_s and every inclusive record carries it on.
+//
+// A record is four 64-bit words: the high half of each holds the record's
+// 32-bit tag (launch epoch and status), the low halves hold the sum and E_s
+// 32 bits at a time.  Each word is one single-copy-atomic, device-coherent
+// access, so a reader that finds one tag in all four words holds a whole
+// record, with no fence between the writer's stores.  The last block out
+// advances the epoch, so no record is cleared between launches.
+constexpr uint32_t FS_AGG = 1, FS_INCL = 2;
+constexpr int FS_SPIN = 1 << 18;
+
+__device__ __forceinline__ void fs_word_put(unsigned long long* p, uint32_t tag, uint32_t v) {
+  __hip_atomic_store(p, ((unsigned long long)tag << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fs_put(unsigned long long* r, uint32_t tag, long long v, double es) {
+  const unsigned long long e = __builtin_bit_cast(unsigned long long, es);
+  fs_word_put(r + 0, tag, (uint32_t)(unsigned long long)v);
+  fs_word_put(r + 1, tag, (uint32_t)((unsigned long long)v >> 32));
+  fs_word_put(r + 2, tag, (uint32_t)e);
+  fs_word_put(r + 3, tag, (uint32_t)(e >> 32));
+}
+// The record's tag if all four words agree, else 0 (no tag is 0).
+__device__ __forceinline__ uint32_t fs_get(const unsigned long long* r, long long* v, double* es) {
+  unsigned long long w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = __hip_atomic_load(r + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t t = (uint32_t)(w[0] >> 32);
+  if ((uint32_t)(w[1] >> 32) != t || (uint32_t)(w[2] >> 32) != t || (uint32_t)(w[3] >> 32) != t) return 0;
+  *v = (long long)((w[1] << 32) | (uint32_t)w[0]);
+  *es = __builtin_bit_cast(double, (w[3] << 32) | (uint32_t)w[2]);
+  return t;
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_field_1p(FieldCtx f) {
+  constexpr int NW = FB_THREADS / WAVE;
+  __shared__ long long sh[NW];
+  __shared__ long long s_carry;
+  __shared__ double s_es;
+  __shared__ unsigned long long s_ep;
+  const FBlk b = f.fb[blockIdx.x];
+  Tube& T = f.tubes[b.tube];
+  const int N = T.N;
+  const bool frozen = (T.flags & F_FIELD_FROZEN) != 0;
+  unsigned long long* rec = f.fs;                       // 4 words per block
+  unsigned long long* epoch = f.fs + 4 * gridDim.x;     // then the done count
+  const int k = b.k0 + threadIdx.x * FB_PER;
+  long long r[FB_PER];
+  long long loc = 0;
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    r[i] = (k + i < N) ? f.rho[T.node_off + k + i] : 0;
+    loc += r[i];
+  }
+  long long incl = loc;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    long long o = __shfl_up(incl, d);
+    if (lane_id() >= d) incl += o;
+  }
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == WAVE - 1) sh[wv] = incl;
+  if (threadIdx.x == 0) s_ep = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (threadIdx.x < WAVE) {
+    const long long v = threadIdx.x < NW ? sh[threadIdx.x] : 0;
+    long long iv = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      long long o = __shfl_up(iv, d);
+      if (lane_id() >= d) iv += o;
+    }
+    if (threadIdx.x < NW) sh[threadIdx.x] = iv - v;
+    const long long tot = __shfl(iv, NW - 1);
+    const uint32_t cur = (uint32_t)(s_ep + 1) << 2;   // the status bits are 1 or 2, so no tag is 0
+    const int bx = (int)blockIdx.x;
+    long long carry = 0;
+    double es = 0.0;
+    if (bx == b.first_blk) {
+      es = T.Es;
+      if (f.mode == 0 && !frozen) es += (double)T.dq * T.scale + T.drive;
+      if (lane_id() == 0) {
+        if (f.mode == 0) {
+          T.Es = es;
+          T.dq = 0;
+          T.dcur = 0;
+        }
+        fs_put(rec + 4 * bx, cur | FS_INCL, tot, es);
+      }
+    } else {
+      if (lane_id() == 0) fs_put(rec + 4 * bx, cur | FS_AGG, tot, 0.0);
+      for (int top = bx - 1; top >= b.first_blk; top -= WAVE) {
+        const int p = top - lane_id();
+        const bool in = p >= b.first_blk;
+        uint32_t t = 0;
+        long long pv = 0;
+        double pe = 0.0;
+        if (in) {
+          int spin = 0;
+          t = fs_get(rec + 4 * p, &pv, &pe);
+          while ((t & ~3u) != cur && ++spin < FS_SPIN) {
+            __builtin_amdgcn_s_sleep(2);
+            t = fs_get(rec + 4 * p, &pv, &pe);
+          }
+          if ((t & ~3u) != cur) atomicOr(f.err, E_SCAN);
+        }
+        const unsigned long long im = __ballot(in && t == (cur | FS_INCL));
+        const int stop = im ? __ffsll((long long)im) - 1 : WAVE;
+        long long x = (in && lane_id() <= stop && (t & ~3u) == cur) ? pv : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+        carry += x;
+        if (im) {
+          es = __shfl(pe, stop);
+          break;
+        }
+      }
+      if (lane_id() == 0) fs_put(rec + 4 * bx, cur | FS_INCL, carry + tot, es);
+    }
+    if (lane_id() == 0) {
+      s_carry = carry;
+      s_es = es;
+    }
+  }
+  __syncthreads();
+  long long run = s_carry + sh[wv] + (incl - loc);   // sum of rho over cells < k
+  const double Es = s_es;
+  const long long bgu = T.bg_unit;
+  double eprev = k == 0 ? Es : (double)(run + bgu * (long long)(k - 1) + bgu / 2) * T.scale + Es;
+#pragma unroll
+  for (int i = 0; i < FB_PER; ++i) {
+    const int kk = k + i;
+    if (kk >= N) break;
+    run += r[i];
+    const double e = (double)(run + bgu * (long long)kk + bgu / 2) * T.scale + Es;
+    if (!frozen) {
+      f.E[T.cell_off + kk] = (float)e;
+      f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+      if (!isfinite(e)) atomicOr(f.err, E_NAN);
+    }
+    f.rho_last[T.node_off + kk] = r[i];
+    f.rho[T.node_off + kk] = 0;
+    eprev = e;
+    if (kk == N - 1) {
+      if (!frozen) f.ebar[T.node_off + N] = (float)e;   // ghost E_{N+1/2} = E_{N-1/2}
+      f.rho_last[T.node_off + N] = f.rho[T.node_off + N];
+      f.rho[T.node_off + N] = 0;
+    }
+  }
+  if (threadIdx.x == 0 && f.mode == 0 && b.k0 == 0) T.step += 1;
+  if (threadIdx.x == 0 && blockIdx.x == 0 && f.mode == 0) {
+    clamp_tail(f.pc);
+    f.pc->tail_snap = f.pc->tail;
+  }
+  // the last block out advances the epoch (every block read it before this)
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    const unsigned long long d = __hip_atomic_fetch_add(epoch + 1, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == gridDim.x - 1) {
+      __hip_atomic_store(epoch + 1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(epoch, s_ep + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
