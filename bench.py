@@ -260,7 +260,8 @@ def bench_diagnostics(g, calls=5):
     """The discharge diagnostics on the grown production state: wall time of
     one peak-multiplicity call (bins of 64 cells: zeroing the sums, the profile
     pass over both stores, the peak kernel, the 48-byte copy back), with 12 B
-    per particle read (position, momentum or energy, weight) as its bytes."""
+    per particle read (position, momentum or energy, weight) as its bytes; and
+    the step time with the waterfall recorded after every step."""
     g.set_profile_bin(64)
     pk = g.peak()
     g.sync()
@@ -270,9 +271,28 @@ def bench_diagnostics(g, calls=5):
     ms = (time.perf_counter() - t0) * 1e3 / calls
     c = g.counts()
     n = c["n_lep"] + c["n_pho"]
+
+    # the E^2 waterfall (Fig. 4) recorded after every step in bins of 64
+    # cells: wall time per step with and without it, over two re-sort
+    # intervals each
+    def wall(k):
+        g.sync()
+        t0 = time.perf_counter()
+        g.step(k)
+        g.sync()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    k = 2 * 136
+    plain = wall(k)
+    g.set_waterfall(1, 64, 64)
+    rec = wall(k)
+    ws, we = g.waterfall()
+    g.set_waterfall(0)
     return dict(peak_call_ms=ms, particles=n, gbs_at_12_bytes=12.0 * n / (ms / 1e3) / 1e9,
                 m_pairs_peak=pk["m_pairs"], h_peak=pk["h"], g3_at_peak=pk["g3"], e_min=pk["e_min"],
-                e_max=pk["e_max"])
+                e_max=pk["e_max"], waterfall=dict(ms_per_step_without=plain, ms_per_step_with=rec,
+                                                  records_read=int(ws.size), bins=int(we.shape[1]),
+                                                  max_e2=float(we.max()) if we.size else None))
 
 
 def copy_calibration(nbytes):

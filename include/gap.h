@@ -167,6 +167,13 @@ int gap_sync(gap_t* g);
                                 momentum, taken exactly in FP64 against edges 10^(b/4) - 1;
                                 then the total weight and the total weight x gamma (gamma in
                                 FP32); reading resets it                                    */
+#define GAP_DIAG_WATERFALL 12  /* the space-time diagram of E^2 (Fig. 4), as recorded since the
+                                  last read (GAP_STATE_WATERFALL): int64 n, int64 nb, then n
+                                  step indices in ascending order, then n x nb doubles, the
+                                  mean of E^2 over each bin of cells after the field update
+                                  of that step (the last bin ragged).  Only the last
+                                  `capacity` records are kept.  Reading empties the tube's
+                                  record; GAP_ESTATE while recording is off               */
 
 /* indices of GAP_DIAG_COUNTS */
 #define GAP_C_LEPTONS     0   /* live leptons                      */
@@ -210,6 +217,13 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
                                   electron from the next step on; ends a pending window        */
 #define GAP_STATE_PROFILE_BIN 7  /* int32 cells per bin >= 1 of GAP_DIAG_PROFILE and
                                     GAP_DIAG_PEAK (all tubes)                                */
+#define GAP_STATE_WATERFALL 8  /* int32[3]: every, bin cells >= 1, capacity in 1..65536: record
+                                  GAP_DIAG_WATERFALL after every step whose index (counted
+                                  by the field update) is a multiple of `every`, keeping the
+                                  last `capacity` records per tube (all tubes); every = 0
+                                  stops recording and frees the record.  Allocates device
+                                  memory (GAP_ENOMEM if it cannot), drops a captured graph,
+                                  waits for queued work and empties the record              */
 #define GAP_STATE_LAUNCH    6  /* int32[4]: workgroups of the sorted lepton pass, of the sorted
                                   photon pass and of the tail passes, and the re-sort interval
                                   (the values gap_autotune returns); grids must be multiples
@@ -218,8 +232,8 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
                                   GAP_EINVAL.  Changes no result, only the speed.             */
 
 /* Replace part of the state of tube `tube` (only valid when n_tubes == 1;
- * GAP_STATE_TIMING, GAP_STATE_DRIVE, GAP_STATE_LAUNCH and GAP_STATE_PROFILE_BIN
- * are valid for any handle, the last two ignoring `tube`).
+ * GAP_STATE_TIMING, GAP_STATE_DRIVE, GAP_STATE_LAUNCH, GAP_STATE_PROFILE_BIN and
+ * GAP_STATE_WATERFALL are valid for any handle, the last three ignoring `tube`).
  * Loading particles rebuilds the node charge and, unless GAP_FIELD_FROZEN,
  * the field from the current E_s.  Waits for queued work. */
 int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, size_t bytes);

@@ -14,7 +14,9 @@ These are the quantities the paper reads off its kinetic simulations
  * the multiplicity of electrons, positrons and photons with x > 2, split
    by direction (Fig. 3, row 5);
  * the peak pair multiplicity in the gap zone and <gamma^-3> at its
-   location, and the extremes of E (Fig. 5).
+   location, and the extremes of E (Fig. 5);
+ * one row of the space-time diagram of E^2 (Fig. 4): the mean of E^2 over
+   each bin of cells, the last bin ragged.
 
 Groups, in order: electrons moving up (u > 0), down; positrons up, down;
 photons with |x| > 2 moving up (x > 0), down.  A lepton's species is the
@@ -83,3 +85,15 @@ def peak(sums: np.ndarray, E: np.ndarray, bin_cells: int, dx: float, H: float, p
     return dict(m_pairs=w / (bin_cells * ppc_ref), h=float(centre[b]), g3=float(g3),
                 m_photons=float((sums[b, 4, 0] + sums[b, 5, 0]) / (bin_cells * ppc_ref)),
                 e_min=float(np.min(E)), e_max=float(np.max(E)))
+
+
+def waterfall_row(E: np.ndarray, bin_cells: int) -> np.ndarray:
+    """[nb]: the mean of E^2 over each bin of `bin_cells` cells of the field at
+    cell centres (the last bin holds the remaining cells)."""
+    E = np.asarray(E, np.float64)
+    nb = (E.size + bin_cells - 1) // bin_cells
+    out = np.zeros(nb)
+    for b in range(nb):
+        seg = E[b * bin_cells:(b + 1) * bin_cells]
+        out[b] = np.sum(seg * seg) / seg.size
+    return out

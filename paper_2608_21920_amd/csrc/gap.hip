@@ -254,6 +254,11 @@ struct gap_t {
   double* prof_acc = nullptr;
   double* prof_out = nullptr;
   int prof_bin = 64;                   // cells per profile bin
+  // waterfall of E^2 (off while wf_every == 0): ring of records per tube
+  int wf_every = 0, wf_B = 64, wf_cap = 0, wf_nbmax = 0;
+  double* wf_ring = nullptr;
+  long long* wf_steps = nullptr;
+  std::vector<void*> wf_mem;
   int* pq_count = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
@@ -289,6 +294,19 @@ void* dalloc(gap_t* g, size_t bytes) {
 
 void win_release(gap_t* g);
 
+// Frees the waterfall ring (the caller has waited for queued work).
+void wf_release(gap_t* g) {
+  for (void* p : g->wf_mem) {
+    if (g->custom_alloc) g->al.free(p, g->al.ctx);
+    else (void)hipFree(p);
+  }
+  g->wf_mem.clear();
+  g->wf_ring = nullptr;
+  g->wf_steps = nullptr;
+  g->wf_every = 0;
+  g->wf_cap = 0;
+}
+
 // A graph exec may only be destroyed once no launch of it is in flight: wait
 // for both streams of the handle first.
 void drop_graph(gap_t* g) {
@@ -307,6 +325,7 @@ void release(gap_t* g) {
   for (hipEvent_t* e : {&g->ev_l, &g->ev_pre, &g->ev_p})
     if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
   win_release(g);
+  wf_release(g);
   for (hipEvent_t e : g->ev_pool) (void)hipEventDestroy(e);
   g->ev_pool.clear();
   for (void* p : g->owned) {
@@ -880,6 +899,10 @@ void enqueue_step(gap_t* g, bool more) {
                       !(g->merge_on && (g->host_step + 1) % g->merge_every == 0);
     Timer t(g, KT_FIELD);
     g->ev_l_bound = field_pass(g, 0, bind ? g->ev_l : nullptr);
+  }
+  if (g->wf_every > 0) {
+    WfCtx w{g->tubes, g->E, g->wf_ring, g->wf_steps, g->wf_every, g->wf_B, g->wf_cap, g->wf_nbmax};
+    k_waterfall<<<dim3((g->wf_nbmax + TPB / WAVE - 1) / (TPB / WAVE), g->n_tubes), TPB, 0, g->s>>>(w);
   }
   if (++g->since_rb >= g->R) {
     if (two) join_photon_side(g);
@@ -1495,6 +1518,33 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       k_fill_i64<<<1, 256, 0, g->s>>>((long long*)r, RET_N, 0);
       return sync_and_err(g);
     }
+    case GAP_DIAG_WATERFALL: {
+      // int64 n, int64 nb, n step indices (ascending), n x nb doubles;
+      // reading empties the tube's ring
+      if (g->wf_every <= 0) return GAP_ESTATE;
+      const int nb = (N + g->wf_B - 1) / g->wf_B;
+      std::vector<long long> st((size_t)g->wf_cap);
+      HIPCHK(hipMemcpy(st.data(), g->wf_steps + (size_t)tube * g->wf_cap, sizeof(long long) * st.size(),
+                       hipMemcpyDeviceToHost));
+      std::vector<int> order;
+      for (int i = 0; i < g->wf_cap; ++i) if (st[i] >= 0) order.push_back(i);
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return st[a] < st[b]; });
+      const size_t n = order.size();
+      if (!fits(sizeof(long long) * (2 + n) + sizeof(double) * n * (size_t)nb)) return GAP_EINVAL;
+      std::vector<double> ring((size_t)g->wf_cap * g->wf_nbmax);
+      HIPCHK(hipMemcpy(ring.data(), g->wf_ring + (size_t)tube * g->wf_cap * g->wf_nbmax, sizeof(double) * ring.size(),
+                       hipMemcpyDeviceToHost));
+      long long* h = (long long*)host_buf;
+      h[0] = (long long)n;
+      h[1] = nb;
+      double* v = (double*)(h + 2 + n);
+      for (size_t j = 0; j < n; ++j) {
+        h[2 + j] = st[order[j]];
+        std::memcpy(v + j * nb, ring.data() + (size_t)order[j] * g->wf_nbmax, sizeof(double) * nb);
+      }
+      k_fill_i64<<<1, 256, 0, g->s>>>(g->wf_steps + (size_t)tube * g->wf_cap, g->wf_cap, -1);
+      return sync_and_err(g);
+    }
     case GAP_DIAG_TIMING: {
       // double[2 * KT_N]: launches and summed milliseconds per kernel group
       if (!fits(sizeof(double) * 2 * KT_N)) return GAP_EINVAL;
@@ -1566,6 +1616,43 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     if (b < 1) return GAP_EINVAL;
     g->prof_bin = b;
     return GAP_OK;
+  }
+  if (kind == GAP_STATE_WATERFALL) {
+    if (bytes < 12) return GAP_EINVAL;
+    int32_t v[3];
+    std::memcpy(v, host_buf, 12);
+    if (v[0] < 0 || (v[0] > 0 && (v[1] < 1 || v[2] < 1 || v[2] > (1 << 16)))) return GAP_EINVAL;
+    // a captured graph holds the old record launch (or none): drop it
+    drop_graph(g);
+    join_photon_side(g);
+    HIPCHK(hipStreamSynchronize(g->s));
+    wf_release(g);
+    if (v[0] == 0) return GAP_OK;
+    int max_n = 1;
+    for (int t = 0; t < g->n_tubes; ++t) max_n = std::max(max_n, g->P[t].n_cells);
+    const int nbmax = (max_n + v[1] - 1) / v[1];
+    const size_t nrec = (size_t)g->n_tubes * (size_t)v[2];
+    auto get = [&](size_t bytes) -> void* {
+      bytes = (bytes + 255) & ~(size_t)255;
+      void* p = nullptr;
+      if (g->custom_alloc) p = g->al.alloc(bytes, g->al.ctx);
+      else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+      if (p) g->wf_mem.push_back(p);
+      return p;
+    };
+    g->wf_ring = (double*)get(sizeof(double) * nrec * (size_t)nbmax);
+    g->wf_steps = (long long*)get(sizeof(long long) * nrec);
+    if (!g->wf_ring || !g->wf_steps) {
+      wf_release(g);
+      return GAP_ENOMEM;
+    }
+    k_fill_i64<<<std::max(1, (int)std::min<size_t>(1024, (nrec + 255) / 256)), 256, 0, g->s>>>(g->wf_steps,
+                                                                                               (long long)nrec, -1);
+    g->wf_every = v[0];
+    g->wf_B = v[1];
+    g->wf_cap = v[2];
+    g->wf_nbmax = nbmax;
+    return sync_and_err(g);
   }
   if (kind == GAP_STATE_LAUNCH) {
     if (bytes < 16) return GAP_EINVAL;

@@ -14,6 +14,8 @@
 //    the extremes of E over the cells.
 //  * Return spectrum (Fig. 7): the weight of the leptons absorbed at the
 //    surface, binned in log10 gamma, filled by the lepton passes (gap_kernels).
+//  * Waterfall (Fig. 4): the space-time diagram of E^2, the mean of E^2 over
+//    bins of cells recorded after the field update of every k-th step.
 #pragma once
 #include "gap_kernels.hpp"
 
@@ -225,6 +227,42 @@ __global__ void k_profile_peak(const double* acc, int nb, int B, double dx, doub
     out[4] = N > 0 ? s_lo[0] : 0.0;
     out[5] = N > 0 ? s_hi[0] : 0.0;
   }
+}
+
+// Waterfall record of the step that the field update just counted, when
+// its index is a multiple of `every`: the mean of E^2 over each bin of B
+// cells (the last bin ragged) goes to ring slot (step / every) mod cap of
+// the tube, and the step index beside it.  One wave per bin, FP64 sums of
+// squares of the FP32 field; grid (ceil(nbmax / waves per block), tubes).
+struct WfCtx {
+  const Tube* tubes;
+  const float* E;
+  double* ring;        // [tube][cap][nbmax]
+  long long* steps;    // [tube][cap], -1 for an empty slot
+  int every, B, cap, nbmax;
+};
+
+__global__ __launch_bounds__(TPB) void k_waterfall(WfCtx w) {
+  const int t = blockIdx.y;
+  const Tube& T = w.tubes[t];
+  const long long step = T.step;
+  if (step < 0 || step % w.every != 0) return;
+  const int N = T.N;
+  const int nb = (N + w.B - 1) / w.B;
+  const long long slot = (step / w.every) % w.cap;
+  const int bin = blockIdx.x * (TPB / WAVE) + (int)(threadIdx.x / WAVE);
+  if (bin < nb) {
+    const int c0 = bin * w.B, c1 = min(N, c0 + w.B);
+    double s = 0.0;
+    for (int c = c0 + lane_id(); c < c1; c += WAVE) {
+      const double e = (double)w.E[T.cell_off + c];
+      s += e * e;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane_id() == 0) w.ring[((size_t)t * w.cap + slot) * w.nbmax + bin] = s / (double)(c1 - c0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) w.steps[(size_t)t * w.cap + slot] = step;
 }
 
 }  // namespace gap

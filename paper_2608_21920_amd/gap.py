@@ -25,9 +25,9 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
- DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN) = range(12)
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL) = range(13)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
- STATE_PROFILE_BIN) = range(8)
+ STATE_PROFILE_BIN, STATE_WATERFALL) = range(9)
 # discharge diagnostics: profile groups and the return spectrum's bins
 PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
 RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
@@ -286,6 +286,26 @@ class Gap:
         """Absorbed weight per 1/8 decade of gamma since the last read, then the
         total weight and the total weight x gamma (reading resets it)."""
         return self._diag(DIAG_RETURN, tube, 8 * (RETURN_BINS + 2)).view(np.float64).copy()
+
+    def set_waterfall(self, every: int, bin_cells: int = 64, capacity: int = 1024):
+        """Record the mean of E^2 per bin of `bin_cells` cells after every
+        `every`-th step, keeping the last `capacity` records per tube
+        (every = 0 stops recording)."""
+        buf = np.array([every, bin_cells, capacity], np.int32)
+        _check(self.lib.gap_set_state(self.h, STATE_WATERFALL, 0, buf.ctypes.data, buf.nbytes), "set_waterfall")
+        self._wf = (int(every), int(bin_cells), int(capacity))
+
+    def waterfall(self, tube=0):
+        """(steps [n], E2 [n, nb]) recorded since the last read, oldest first;
+        reading empties the record."""
+        every, b, cap = getattr(self, "_wf", (0, 64, 1))
+        nb = (self.n_cells(tube) + b - 1) // b
+        v = self._diag(DIAG_WATERFALL, tube, 16 + 8 * cap * (1 + nb))
+        head = v[:16].view(np.int64)
+        n, nbr = int(head[0]), int(head[1])
+        steps = v[16:16 + 8 * n].view(np.int64).copy()
+        e2 = v[16 + 8 * n:16 + 8 * n + 8 * n * nbr].view(np.float64).reshape(n, nbr).copy()
+        return steps, e2
 
     def set_launch(self, grid_leptons: int, grid_photons: int, grid_tails: int, resort_every: int):
         """Launch shapes and re-sort interval (the keys autotune() returns)."""

@@ -124,3 +124,64 @@ def test_return_flux_counts_every_absorption(torch_gpu):
     assert r[64] == float(n_abs) and r[:64].sum() == r[64]
     assert r[65] >= r[64]
     g.close()
+
+
+def test_waterfall_matches_definition_and_oracle(torch_gpu):
+    # every third step, bins of 37 cells (ragged): each record equals the
+    # definition applied to the field read back after that step, and follows
+    # the oracle's own run within the field tolerance
+    _say("case: waterfall of the tiny gap, every 3 steps, bins of 37 cells, 40 steps")
+    cfg = dict(workloads.TINY, seed=2)
+    g = Gap(cfg)
+    o = Oracle(cfg)
+    g.set_waterfall(3, 37, 64)
+    want, want_o = {}, {}
+    for _ in range(40):
+        g.step(1)
+        o.step(1)
+        s = g.counts()["step"]
+        if s % 3 == 0:
+            want[s] = diag.waterfall_row(g.field(), 37)
+            want_o[s] = diag.waterfall_row(o.field(), 37)
+    steps, e2 = g.waterfall()
+    assert list(steps) == sorted(want)
+    assert e2.shape == (len(want), (cfg["n_cells"] + 36) // 37)
+    for s, row in zip(steps, e2):
+        assert np.allclose(row, want[s], rtol=1e-12, atol=0.0), s
+        assert np.max(np.abs(row - want_o[s])) <= 1e-4 * np.max(want_o[s]), s
+    steps2, e22 = g.waterfall()                      # reading emptied it
+    assert steps2.size == 0 and e22.shape[0] == 0
+    g.close()
+
+
+def test_waterfall_ring_keeps_the_last_records(torch_gpu):
+    _say("case: waterfall ring of 4 records over 10 steps, then off")
+    g = Gap(dict(workloads.TINY, n_cells=256, seed=3))
+    s0 = g.counts()["step"]
+    g.set_waterfall(1, 64, 4)
+    g.step(10)
+    steps, e2 = g.waterfall()
+    assert list(steps) == [s0 + 7, s0 + 8, s0 + 9, s0 + 10]
+    assert e2.shape == (4, 4) and np.all(np.isfinite(e2)) and np.all(e2 >= 0.0)
+    g.set_waterfall(0)
+    with pytest.raises(G.GapError):
+        g.waterfall()
+    g.close()
+
+
+def test_waterfall_of_each_tube_of_a_batch(torch_gpu):
+    _say("case: waterfall of each tube of a 3-tube handle vs plain handles")
+    cfgs = [dict(workloads.TINY, n_cells=384, seed=5), dict(workloads.TINY, n_cells=1000, alpha=-1.0, seed=6),
+            dict(workloads.TINY, n_cells=130, b=0.2, seed=7)]
+    gb = Gap(cfgs)
+    gb.set_waterfall(2, 32, 16)
+    gb.step(20)
+    for t, c in enumerate(cfgs):
+        gp = Gap(c)
+        gp.set_waterfall(2, 32, 16)
+        gp.step(20)
+        sa, a = gb.waterfall(t)
+        sb, b = gp.waterfall()
+        assert np.array_equal(sa, sb) and np.array_equal(a, b), t
+        gp.close()
+    gb.close()

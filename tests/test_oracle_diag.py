@@ -121,3 +121,25 @@ def test_return_flux_of_known_absorptions():
     assert np.array_equal(r[:64], ref[:64])
     assert r[64] == ref[64] and math.isclose(r[65], ref[65], rel_tol=1e-14)
     assert np.array_equal(o.return_spectrum(), np.zeros(66))   # reading cleared it
+
+
+def test_waterfall_row_constant_and_linear_fields():
+    # constant E: every bin holds E0^2; E = cell index k: the mean of k^2 over
+    # k0 .. k1-1 is (S(k1-1) - S(k0-1)) / (k1 - k0) with S(n) = n(n+1)(2n+1)/6
+    N, B = 300, 64                           # bins of 64, 64, 64, 64, 44 cells
+    assert np.array_equal(diag.waterfall_row(np.full(N, -2.5), B), np.full(5, 6.25))
+    S = lambda n: n * (n + 1) * (2 * n + 1) / 6.0
+    ref = []
+    for b in range(5):
+        k0, k1 = b * B, min(N, (b + 1) * B)
+        ref.append((S(k1 - 1) - S(k0 - 1)) / (k1 - k0))
+    assert np.allclose(diag.waterfall_row(np.arange(N, dtype=np.float64), B), ref, rtol=1e-15, atol=0.0)
+
+
+def test_waterfall_row_brute_force_ragged():
+    rng = np.random.default_rng(11)
+    E = rng.normal(0, 50, 1000).astype(np.float32)
+    for B in (1, 7, 37, 1000, 4096):
+        nb = (E.size + B - 1) // B
+        ref = [sum(float(e) * float(e) for e in E[b * B:(b + 1) * B]) / len(E[b * B:(b + 1) * B]) for b in range(nb)]
+        assert np.allclose(diag.waterfall_row(E, B), ref, rtol=1e-13, atol=0.0)
