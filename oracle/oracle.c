@@ -49,6 +49,8 @@
 #define ORC_CONV_OFF     1024u
 #define ORC_EMIT_OFF     2048u
 #define ORC_INJ_FIXED    4096u   /* injection count independent of inj_weight */
+#define ORC_FILTER       8192u   /* binomial current filter, ORC_FILTER_PASSES passes per step */
+#define ORC_FILTER_PASSES 8
 
 /* Random-stream tags (upper 16 bits of the fourth counter word). */
 #define TAG_INIT  1u
@@ -104,6 +106,7 @@ typedef struct {
   olep* lep; int64_t nlep, lep_alloc;
   opho* pho; int64_t npho, pho_alloc;
   double* E;     /* E at cell centres k+1/2, k = 0..N-1 */
+  double* E0;    /* filtered runs: the field when the state was last set */
   double* Eb;    /* node field, nodes 0..N */
   int64_t* rho;  /* node charge, fixed point, nodes 0..N */
   double Es;
@@ -347,6 +350,39 @@ static void field_from_rho(orc_sim* s) {
   }
 }
 
+/* The digital filter of the current (Sect. 6.1: binomial 3-point shape,
+ * several passes per step).  One pass replaces x_i by (x_{i-1} + 2 x_i +
+ * x_{i+1}) / 4.  Ends: periodic boxes wrap; otherwise the missing neighbour
+ * is the end value itself (x_{-1} = x_0, x_n = x_{n-1}), so a uniform array
+ * is unchanged and the sum is kept. */
+void orc_filter(double* x, int32_t n, int32_t passes, int32_t periodic) {
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int32_t p = 0; p < passes; ++p) {
+    for (int32_t i = 0; i < n; ++i) {
+      double l = i > 0 ? x[i - 1] : (periodic ? x[n - 1] : x[0]);
+      double r = i < n - 1 ? x[i + 1] : (periodic ? x[0] : x[n - 1]);
+      y[i] = (l + 2.0 * x[i] + r) / 4.0;
+    }
+    memcpy(x, y, sizeof(double) * (size_t)n);
+  }
+  free(y);
+}
+
+/* Filtered Ampere update.  The field obeys E^{n+1} = E^n - dt (F[J] - j_m)
+ * with F linear and time-independent and j_m uniform (F keeps uniform
+ * arrays), so summed over steps E^n = E^0 + F[E_u^n - E^0], where E_u is the
+ * unfiltered field that Gauss's law gives for the same particles and E_s,
+ * and E^0 the field when the state was set. */
+static void filter_field(orc_sim* s) {
+  if (!(s->p.flags & ORC_FILTER)) return;
+  int N = s->N;
+  double* d = (double*)malloc(sizeof(double) * (size_t)N);
+  for (int k = 0; k < N; ++k) d[k] = s->E[k] - s->E0[k];
+  orc_filter(d, N, ORC_FILTER_PASSES, (s->p.flags & ORC_PERIODIC) != 0);
+  for (int k = 0; k < N; ++k) s->E[k] = s->E0[k] + d[k];
+  free(d);
+}
+
 /* Node field for the gather: average of the two adjacent cell fields.
  * Ghosts: E_{-1/2} = E_s (the surface value), E_{N+1/2} = E_{N-1/2}. */
 static void node_field(orc_sim* s) {
@@ -392,6 +428,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
   int e = derive(s);
   if (e) { free(s); if (err) *err = e; return NULL; }
   s->E = (double*)calloc(s->N, sizeof(double));
+  s->E0 = (double*)calloc(s->N, sizeof(double));
   s->Eb = (double*)calloc(s->N + 1, sizeof(double));
   s->rho = (int64_t*)calloc(s->N + 1, sizeof(int64_t));
   sync_nodes(s);
@@ -399,6 +436,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
   s->Es = 0.0;
   deposit_all(s);
   field_from_rho(s);
+  memcpy(s->E0, s->E, sizeof(double) * s->N);
   node_field(s);
   if (err) *err = s->err;
   return s;
@@ -406,7 +444,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
 
 void orc_free(orc_sim* s) {
   if (!s) return;
-  free(s->lep); free(s->pho); free(s->E); free(s->Eb); free(s->rho); free(s->ev);
+  free(s->lep); free(s->pho); free(s->E); free(s->E0); free(s->Eb); free(s->rho); free(s->ev);
   free(s->q_cosh); free(s->q_g);
   free(s);
 }
@@ -767,6 +805,7 @@ static void step_once(orc_sim* s) {
     if (!periodic) s->Es += (double)s->dq * s->w0 / ORC_FP_ONE + p->alpha * s->s_co * s->dt;
     else s->Es += -s->dcur * s->w0 * p->dx / (N * p->dx) + p->alpha * s->s_co * s->dt;
     field_from_rho(s);
+    filter_field(s);
     node_field(s);
   }
   s->dq = 0;
@@ -839,6 +878,7 @@ int32_t orc_set_state(orc_sim* s, int64_t nl, const int32_t* cell, const double*
   s->dq = 0;
   deposit_all(s);
   field_from_rho(s);
+  memcpy(s->E0, s->E, sizeof(double) * s->N);
   node_field(s);
   return s->err;
 }
@@ -846,6 +886,7 @@ int32_t orc_set_state(orc_sim* s, int64_t nl, const int32_t* cell, const double*
 /* Overwrite the cell field (FIELD_FROZEN tests). */
 void orc_set_field(orc_sim* s, const double* E, double Es) {
   memcpy(s->E, E, sizeof(double) * s->N);
+  memcpy(s->E0, E, sizeof(double) * s->N);
   s->Es = Es;
   node_field(s);
 }

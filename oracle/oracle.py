@@ -19,7 +19,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 FLAGS = dict(
     QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32,
     TRACK_ALL=64, ANTI_ALIGNED=128, RECORD=256, REPLAY=512, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096,
+    FILTER=8192,
 )
+FILTER_PASSES = 8
 
 
 def build_oracle(force: bool = False) -> str:
@@ -82,6 +84,7 @@ def _load():
         lib.orc_erad.restype = C.c_double
         lib.orc_erad.argtypes = [C.c_void_p]
         lib.orc_return.argtypes = [C.c_void_p, C.c_void_p]
+        lib.orc_filter.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
         for f in ("orc_field", "orc_node_field"):
             getattr(lib, f).argtypes = [C.c_void_p, C.c_void_p]
         lib.orc_rho.argtypes = [C.c_void_p, C.c_void_p]
@@ -259,3 +262,12 @@ class Oracle:
     def set_replay(self, ev: dict) -> None:
         self._rep = {k: np.ascontiguousarray(ev[k], dtype=dt) for k, dt in self._EV}
         self.lib.orc_set_replay(self.h, self._rep["kind"].size, *[_ptr(self._rep[k]) for k, _ in self._EV])
+
+
+def binomial_filter(x, passes: int = FILTER_PASSES, periodic: bool = False) -> np.ndarray:
+    """The oracle's current filter (Sect. 6.1) applied to a copy of x: each
+    pass x_i <- (x_{i-1} + 2 x_i + x_{i+1}) / 4, ends wrapped (periodic) or
+    repeating the end value."""
+    y = np.ascontiguousarray(x, np.float64).copy()
+    _load().orc_filter(y.ctypes.data, y.size, int(passes), int(bool(periodic)))
+    return y
