@@ -256,6 +256,36 @@ def bench_adjoint(window=2000, ckpt=100):
                        "n_co dx per step, frozen QED, loss = time-averaged <E^2>")
 
 
+def bench_filter(steps=200):
+    """The current filter (8 binomial passes per step) on the production grid:
+    the same start state of the production gap stepped with and without it,
+    wall time per step and the field update's share (HIP-event timing of
+    the field group, which then includes the filter kernel)."""
+    from paper_2608_21920_amd import Gap, workloads
+    from paper_2608_21920_amd import gap as G
+    out = {}
+    for name, extra in (("plain", 0), ("filtered", G.FILTER)):
+        cfg = dict(workloads.PRODUCTION)
+        cfg["flags"] = cfg.get("flags", 0) | extra
+        g = Gap(cfg)
+        g.step(20)
+        g.sync()
+        t0 = time.perf_counter()
+        g.step(steps)
+        g.sync()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        g.set_timing(True)
+        g.step(steps)
+        g.sync()
+        n, tms = g.timing()["field"]
+        g.set_timing(False)
+        out[name] = dict(ms_per_step=wall, field_us=tms / max(n, 1) * 1e3, leptons=g.counts()["n_lep"])
+        g.close()
+    out["filter_us_per_step"] = (out["filtered"]["field_us"] - out["plain"]["field_us"])
+    out["config"] = "production gap start state (65536 cells), %d steps each" % steps
+    return out
+
+
 def bench_diagnostics(g, calls=5):
     """The discharge diagnostics on the grown production state: wall time of
     one peak-multiplicity call (bins of 64 cells: zeroing the sums, the profile
@@ -422,6 +452,7 @@ def main():
         "diagnostics": bench_diagnostics(g),
     }
     g.close()
+    out["filter"] = bench_filter()
     if not a.no_batched:
         out["batched"] = bench_batched(value)
     if not a.no_adjoint:

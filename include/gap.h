@@ -65,6 +65,13 @@ extern "C" {
 #define GAP_INJ_FIXED    4096u  /* injection count per step from inj_rate * ppc_ref
                                    alone: inj_weight scales the injected charge only
                                    (the injected density is inj_rate * inj_weight)    */
+#define GAP_FILTER       8192u  /* the current is smoothed by the digital filter of
+                                   Sect. 6.1: 8 passes per step of the binomial 3-point
+                                   shape, ends repeating the end value (periodic: wrapped).
+                                   Applied as E = E0 + F[E_u - E0], E_u the unfiltered
+                                   Gauss field and E0 the field when the state was last
+                                   set; E_s itself is not filtered.  Not with the
+                                   differentiable window (GAP_EINVAL)                   */
 
 /* initial states (gap_params.init_kind) */
 #define GAP_INIT_GAP      0  /* vacuum below H, electrons at ppc_init per cell above H  */

@@ -215,6 +215,7 @@ struct gap_t {
   Tile* tiles = nullptr;
   int n_tiles = 0;
   long long total_nodes = 0, total_cells = 0;
+  int max_cells = 1;   // largest tube
   long long* rho = nullptr;
   long long* rho_last = nullptr;
   float* E = nullptr;
@@ -265,6 +266,9 @@ struct gap_t {
   int round_lep = 2048, round_pho = 2048, cus = 256;        // one resident round of each pass; CUs
   int rmax = 64;                                            // longest re-sort interval the tile margin allows
   bool any_periodic = false;
+  bool any_filter = false;
+  double* E0 = nullptr;   // filtered tubes: reference field; Du: E_u - E0 of the step
+  double* Du = nullptr;
   int sticky = 0;
   // graph: replay is valid from the recorded start state and leaves the end state
   WinState win;
@@ -337,6 +341,7 @@ void release(gap_t* g) {
 
 int validate(const gap_params& p) {
   if (p.n_cells < 2 || p.n_cells > (1 << 26)) return GAP_EINVAL;
+  if ((p.flags & GAP_FILTER) && p.n_cells < 2 * FLT_PASSES) return GAP_EINVAL;
   if (!(p.dx > 0) || !(p.cfl > 0 && p.cfl < 1.0)) return GAP_EINVAL;
   if (p.ppc_ref < 1 || p.ppc_init < 0) return GAP_EINVAL;
   if (!(p.b > 0) || !(p.r_curv_cm > 0) || !(p.period_s > 0)) return GAP_EINVAL;
@@ -446,6 +451,8 @@ FieldCtx make_fctx(gap_t* g, int mode) {
   f.err = g->err;
   f.pc = g->pho.ctl;
   f.fs = g->fscan;
+  f.E0 = g->E0;
+  f.Du = g->Du;
   f.mode = mode;
   return f;
 }
@@ -499,19 +506,23 @@ void rebucket_all(gap_t* g) {
 // event (no separate marker on the stream); returns whether it was.
 bool field_pass(gap_t* g, int mode, hipEvent_t done = nullptr) {
   FieldCtx f = make_fctx(g, mode);
+  const bool filt = g->any_filter && mode == 0;
+  if (filt) done = nullptr;   // the step's field is complete only after k_filter
+  bool bound = false;
   if (!g->any_periodic) {
     if (done) hipExtLaunchKernelGGL(k_field_1p, dim3(g->n_fb), dim3(FB_THREADS), 0, g->s, nullptr, done, 0, f);
     else k_field_1p<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
-    return done != nullptr;
+    bound = done != nullptr;
+  } else {
+    // a periodic tube subtracts the mean field, which needs the whole tube's
+    // sums before any output: two passes
+    k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+    k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+    k_field_periodic_ends<<<(g->n_tubes + 63) / 64, 64, 0, g->s>>>(f, g->n_tubes);
   }
-  // a periodic tube subtracts the mean field, which needs the whole tube's
-  // sums before any output: two passes
-  k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
-  k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
-  k_field_periodic_ends<<<(g->n_tubes + 63) / 64, 64, 0, g->s>>>(f, g->n_tubes);
-  return false;
+  if (filt) k_filter<<<dim3((g->max_cells + FLT_CELLS - 1) / FLT_CELLS, g->n_tubes), FLT_CELLS, 0, g->s>>>(f);
+  return bound;
 }
-
 // Node charge and field from the current particles and E_s (no drive).
 void rebuild_field(gap_t* g) {
   const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
@@ -1042,6 +1053,8 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     cap_l += q.cap_leptons;
     cap_p += q.cap_photons;
     if (q.flags & GAP_PERIODIC) g->any_periodic = true;
+    if (q.flags & GAP_FILTER) g->any_filter = true;
+    g->max_cells = std::max(g->max_cells, q.n_cells);
     const int rmax = std::max(1, (int)std::floor((MARGIN - 2) / q.cfl) - 1);
     rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : rmax);
   }
@@ -1080,6 +1093,11 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->part = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
   g->part2 = (long long*)dalloc(g, sizeof(long long) * g->n_fb);
   g->fscan = (unsigned long long*)dalloc(g, sizeof(unsigned long long) * (4 * (size_t)g->n_fb + 2));
+  if (g->any_filter) {
+    g->E0 = (double*)dalloc(g, sizeof(double) * g->total_cells);
+    g->Du = (double*)dalloc(g, sizeof(double) * g->total_cells);
+    if (!g->E0 || !g->Du) return GAP_ENOMEM;
+  }
   g->tab = (float*)dalloc(g, sizeof(float) * 2 * (NTAB + 1));
   g->err = (int*)dalloc(g, sizeof(int));
   g->live = (long long*)dalloc(g, sizeof(long long) * n_tubes);
@@ -1792,6 +1810,11 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
       }
       HIPCHK(hipMemcpy(g->E + T.cell_off, E.data(), sizeof(float) * N, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(g->ebar + T.node_off, eb.data(), sizeof(float) * (N + 1), hipMemcpyHostToDevice));
+      if (q.flags & GAP_FILTER) {
+        // the set field is the filtered update's new reference
+        std::vector<double> e0(E.begin(), E.end());
+        HIPCHK(hipMemcpy(g->E0 + T.cell_off, e0.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+      }
       if ((e = upload_tubes(g))) return e;
       return sync_and_err(g);
     }
@@ -1816,6 +1839,7 @@ int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen) {
 
 int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss) {
   if (!g || window_steps < 1 || ckpt_every < 1 || !loss) return GAP_EINVAL;
+  if (g->any_filter) return GAP_EINVAL;   // the adjoint is of the unfiltered update
   return window_forward(g, window_steps, ckpt_every, loss);
 }
 

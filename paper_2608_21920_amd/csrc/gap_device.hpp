@@ -41,7 +41,7 @@ enum : int {
 enum : uint32_t {
   F_QED_OFF = 1u, F_ETA_CO_OFF = 2u, F_FIELD_FROZEN = 4u, F_RECOIL_OFF = 8u, F_PERIODIC = 16u,
   F_MERGE_ON = 32u, F_TRACK_ALL = 64u, F_ANTI_ALIGNED = 128u, F_CONV_OFF = 1024u, F_EMIT_OFF = 2048u,
-  F_INJ_FIXED = 4096u
+  F_INJ_FIXED = 4096u, F_FILTER = 8192u
 };
 
 // sticky device error bits

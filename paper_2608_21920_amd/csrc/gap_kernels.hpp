@@ -1045,6 +1045,8 @@ struct FieldCtx {
   long long* part2;   // per block: sum rho_i (N - i)
   int* err;
   unsigned long long* fs;   // single-pass form: a four-word record per block, then the epoch and a done count
+  double* E0;         // filtered tubes: the reference field (set in mode 1)
+  double* Du;         // filtered tubes, mode 0: E_u - E0, which k_filter smooths
   Ctl* pc;            // photon store: its tail snapshot for the next step is taken here
   int mode;           // 0: step (surface update, step += 1); 1: rebuild E only
 };
@@ -1120,6 +1122,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
   const int N = T.N;
   const bool per = (T.flags & F_PERIODIC) != 0;
   const bool frozen = (T.flags & F_FIELD_FROZEN) != 0;
+  const bool filt = (T.flags & F_FILTER) != 0;
   // carry from the tube's earlier blocks
   const long long carry = wave_range_sum(f.part, b.first_blk, (int)blockIdx.x);
   double mean = 0.0;
@@ -1174,8 +1177,13 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
     const long long eint = run + bgu * (long long)kk + bgu / 2;
     const double e = per ? ((double)eint - mean) * T.scale + Es : (double)eint * T.scale + Es;
     if (!frozen) {
-      f.E[T.cell_off + kk] = (float)e;
-      if (kk > 0 || !per) f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+      if (filt && f.mode == 0) {
+        f.Du[T.cell_off + kk] = e - f.E0[T.cell_off + kk];
+      } else {
+        f.E[T.cell_off + kk] = (float)e;
+        if (kk > 0 || !per) f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+        if (filt) f.E0[T.cell_off + kk] = e;
+      }
       if (!isfinite(e)) atomicOr(f.err, E_NAN);
     }
     f.rho_last[T.node_off + kk] = r[i];
@@ -1183,7 +1191,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_b(FieldCtx f) {
     eprev = e;
     if (kk == N - 1) {
       // last node: non-periodic ghost E_{N+1/2} = E_{N-1/2}; periodic node 0 = node N
-      if (!frozen && !per) f.ebar[T.node_off + N] = (float)e;
+      if (!frozen && !per && !(filt && f.mode == 0)) f.ebar[T.node_off + N] = (float)e;
       f.rho_last[T.node_off + N] = f.rho[T.node_off + N];
       f.rho[T.node_off + N] = 0;
     }
@@ -1247,6 +1255,7 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_1p(FieldCtx f) {
   Tube& T = f.tubes[b.tube];
   const int N = T.N;
   const bool frozen = (T.flags & F_FIELD_FROZEN) != 0;
+  const bool filt = (T.flags & F_FILTER) != 0;
   unsigned long long* rec = f.fs;                       // 4 words per block
   unsigned long long* epoch = f.fs + 4 * gridDim.x;     // then the done count
   const int k = b.k0 + threadIdx.x * FB_PER;
@@ -1339,15 +1348,20 @@ __global__ __launch_bounds__(FB_THREADS) void k_field_1p(FieldCtx f) {
     run += r[i];
     const double e = (double)(run + bgu * (long long)kk + bgu / 2) * T.scale + Es;
     if (!frozen) {
-      f.E[T.cell_off + kk] = (float)e;
-      f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+      if (filt && f.mode == 0) {
+        f.Du[T.cell_off + kk] = e - f.E0[T.cell_off + kk];
+      } else {
+        f.E[T.cell_off + kk] = (float)e;
+        f.ebar[T.node_off + kk] = (float)(0.5 * (eprev + e));
+        if (filt) f.E0[T.cell_off + kk] = e;
+      }
       if (!isfinite(e)) atomicOr(f.err, E_NAN);
     }
     f.rho_last[T.node_off + kk] = r[i];
     f.rho[T.node_off + kk] = 0;
     eprev = e;
     if (kk == N - 1) {
-      if (!frozen) f.ebar[T.node_off + N] = (float)e;   // ghost E_{N+1/2} = E_{N-1/2}
+      if (!frozen && !(filt && f.mode == 0)) f.ebar[T.node_off + N] = (float)e;   // ghost E_{N+1/2} = E_{N-1/2}
       f.rho_last[T.node_off + N] = f.rho[T.node_off + N];
       f.rho[T.node_off + N] = 0;
     }
@@ -1377,6 +1391,64 @@ __global__ void k_field_periodic_ends(FieldCtx f, int n_tubes) {
   const float v = 0.5f * (f.E[T.cell_off + T.N - 1] + f.E[T.cell_off]);
   f.ebar[T.node_off] = v;
   f.ebar[T.node_off + T.N] = v;
+}
+
+// The digital filter of the current (Sect. 6.1), for tubes with F_FILTER,
+// after the field update of a step: E = E0 + F[E_u - E0] with F eight
+// passes of (x_{i-1} + 2 x_i + x_{i+1}) / 4 (E_u - E0 is in Du).  Repeating
+// the end value at every pass is the same as extending the array once by its
+// mirror image about the end face, so each block loads its cells with a halo
+// of FLT_PASSES + 1 cells on the left (the node field needs the cell before
+// the block) and FLT_PASSES on the right, mirrored (or wrapped, periodic)
+// at the ends, smooths in LDS, and writes E and the node field.
+// Grid (ceil(max N / FLT_CELLS), tubes); filtered tubes have N >= 2 FLT_PASSES.
+constexpr int FLT_PASSES = 8;
+constexpr int FLT_CELLS = 256;
+constexpr int FLT_W = FLT_CELLS + 2 * FLT_PASSES + 1;
+
+__global__ __launch_bounds__(FLT_CELLS) void k_filter(FieldCtx f) {
+  __shared__ double a[FLT_W], b[FLT_W];
+  const Tube& T = f.tubes[blockIdx.y];
+  if (!(T.flags & F_FILTER) || (T.flags & F_FIELD_FROZEN)) return;
+  const int N = T.N;
+  const int c0 = blockIdx.x * FLT_CELLS;
+  if (c0 >= N) return;
+  const bool per = (T.flags & F_PERIODIC) != 0;
+  // (window cells past N + FLT_PASSES feed no output: clamped into the tube)
+  auto src = [&](int j) {
+    if (per) return ((j % N) + N) % N;
+    const int m = j < 0 ? -1 - j : (j >= N ? 2 * N - 1 - j : j);
+    return min(max(m, 0), N - 1);
+  };
+  for (int i = threadIdx.x; i < FLT_W; i += blockDim.x) a[i] = f.Du[T.cell_off + src(c0 - FLT_PASSES - 1 + i)];
+  __syncthreads();
+  double* x = a;
+  double* y = b;
+  for (int p = 0; p < FLT_PASSES; ++p) {
+    for (int i = threadIdx.x; i < FLT_W; i += blockDim.x)
+      y[i] = (i > 0 && i < FLT_W - 1) ? (x[i - 1] + 2.0 * x[i] + x[i + 1]) / 4.0 : x[i];
+    __syncthreads();
+    double* t = x;
+    x = y;
+    y = t;
+  }
+  // x[FLT_PASSES + 1 + c - c0] is the smoothed value of cell c (exact for
+  // cells c0 - 1 .. c0 + FLT_CELLS - 1)
+  const int c = c0 + (int)threadIdx.x;
+  if (c < N) {
+    const double e = f.E0[T.cell_off + c] + x[FLT_PASSES + 1 + threadIdx.x];
+    double ep;
+    if (c > 0 || per) {
+      const int cp = c > 0 ? c - 1 : N - 1;
+      ep = f.E0[T.cell_off + cp] + x[FLT_PASSES + threadIdx.x];
+    } else {
+      ep = T.Es;   // ghost E_{-1/2} = E_s
+    }
+    f.E[T.cell_off + c] = (float)e;
+    f.ebar[T.node_off + c] = (float)(0.5 * (ep + e));
+    if (per && c == 0) f.ebar[T.node_off + N] = (float)(0.5 * (ep + e));   // node N is node 0
+    if (!per && c == N - 1) f.ebar[T.node_off + N] = (float)e;             // ghost E_{N+1/2} = E_{N-1/2}
+  }
 }
 
 // ------------------------------------------------------------------ re-sort

@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libgap.so")
 
 QED_OFF, ETA_CO_OFF, FIELD_FROZEN, RECOIL_OFF, PERIODIC, MERGE_ON, TRACK_ALL, ANTI_ALIGNED = \
     1, 2, 4, 8, 16, 32, 64, 128
-CONV_OFF, EMIT_OFF, INJ_FIXED = 1024, 2048, 4096
+CONV_OFF, EMIT_OFF, INJ_FIXED, FILTER = 1024, 2048, 4096, 8192
 FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32, TRACK_ALL=64,
-             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096)
+             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096, FILTER=8192)
 
 ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
