@@ -1521,7 +1521,7 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
         HIPCHK(hipStreamSynchronize(g->s));
         HIPCHK(hipMemcpy(host_buf, g->prof_out, sizeof(double) * 3 * PROF_G * (size_t)nb, hipMemcpyDeviceToHost));
       } else {
-        k_profile_peak<<<1, TPB, 0, g->s>>>(g->prof_acc, nb, B, g->P[tube].dx, g->D[tube].H, bppc,
+        k_profile_peak<<<1, PEAK_T, 0, g->s>>>(g->prof_acc, nb, B, g->P[tube].dx, g->D[tube].H, bppc,
                                             g->E + Th.cell_off, N, g->prof_out);
         HIPCHK(hipStreamSynchronize(g->s));
         HIPCHK(hipMemcpy(host_buf, g->prof_out, sizeof(double) * 6, hipMemcpyDeviceToHost));

@@ -170,11 +170,13 @@ __global__ void k_profile_finish(const double* acc, int nb, double bppc, double*
 // zone (h < H), with ties to the lowest bin, and the field's extremes; one
 // workgroup.  out: m_+- at the peak, the peak bin's centre height, <gamma^-3>
 // of the pairs there, the photon multiplicity (|x| > 2) there, min E, max E.
-__global__ void k_profile_peak(const double* acc, int nb, int B, double dx, double H, double bppc,
-                               const float* E, int N, double* out) {
-  __shared__ double s_v[TPB];
-  __shared__ int s_i[TPB];
-  __shared__ double s_lo[TPB], s_hi[TPB];
+constexpr int PEAK_T = 1024;   // one workgroup of 1024 threads
+
+__global__ __launch_bounds__(PEAK_T) void k_profile_peak(const double* acc, int nb, int B, double dx, double H,
+                                                         double bppc, const float* E, int N, double* out) {
+  __shared__ double s_v[PEAK_T];
+  __shared__ int s_i[PEAK_T];
+  __shared__ double s_lo[PEAK_T], s_hi[PEAK_T];
   double best = -1.0;
   int arg = -1;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -183,11 +185,18 @@ __global__ void k_profile_peak(const double* acc, int nb, int B, double dx, doub
     for (int g = 0; g < 4; ++g) m += acc[((size_t)b * PROF_G + g) * PROF_M];
     if (m > best) { best = m; arg = b; }   // (b grows within a thread: the first of equal values stays)
   }
+  // four independent loads per round
   double lo = 1e300, hi = -1e300;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) {
-    const double e = (double)E[k];
-    lo = fmin(lo, e);
-    hi = fmax(hi, e);
+  const int bd = blockDim.x;
+  for (int k = threadIdx.x; k < N; k += 4 * bd) {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = k + u * bd < N ? E[k + u * bd] : E[k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      lo = fmin(lo, (double)v[u]);
+      hi = fmax(hi, (double)v[u]);
+    }
   }
   s_v[threadIdx.x] = best;
   s_i[threadIdx.x] = arg;
