@@ -48,6 +48,17 @@ ADJOINT = dict(BASE, n_cells=16384, init_kind=1, ppc_init=122, ppc_ref=16, alpha
                r_curv_cm=1e7, r_curv_scale=1e-2, lambda_c_scale=1e3, inj_rate=0.1, seed=0,
                steps=2000, ckpt_every=100, cap_leptons=16_000_000, cap_photons=16_000_000)
 
+# The paper's own setup (Sect. 6.1), as far as this path models it: b = 0.02,
+# R_curv = 30 H_gap, j_m = 2 j_co (alpha = 2; -2 is its tested variant), two
+# particles per cell per species at n_co, the current filter on.  The gap is
+# sized so that gamma_gap = H^2/2 (E_rot = H in these units) is 3e7:
+# H = 7746 d, N = H / (0.8 dx) = 38730 cells.  With b = 0.02 and P = 1 s
+# the skin depth is 3.035 cm, so 30 H is 7.053e5 cm.  The thermal atmosphere
+# with protons is replaced by the cold surface injection of the other gaps.
+PAPER = dict(BASE, n_cells=38730, init_kind=0, ppc_init=2, ppc_ref=2, alpha=2.0, b=0.02, r_curv_cm=7.053e5,
+             inj_rate=0.1, seed=0, steps=10_000_000, cap_leptons=50_000_000, cap_photons=50_000_000,
+             merge=True, flags=8192)
+
 
 def batched_tubes(n_tubes: int = 256, seed: int = 1) -> list[dict]:
     """Independent flux tubes of uneven size (the batched ensemble).

@@ -114,3 +114,46 @@ def test_filter_refusals(torch_gpu):
     with pytest.raises(G.GapError):
         g.window_forward(10, 5)
     g.close()
+
+
+def test_graph_replays_with_filter_and_waterfall(torch_gpu):
+    # the filter kernel and the waterfall record are inside the captured
+    # steps; every replay, with eager work between, matches eager stepping
+    _say("case: graph replays of filtered steps with the waterfall on")
+    import torch
+    cfg = _filtered(dict(workloads.TINY, n_cells=512))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ga = Gap(cfg, stream=s)
+        gb = Gap(cfg, stream=s)
+        for g in (ga, gb):
+            g.set_waterfall(4, 32, 64)
+        for r in range(5):
+            ga.step_graph(16)
+            ga.sync()
+            gb.step(16)
+            assert np.array_equal(ga.field(), gb.field()), r
+            sa, a = ga.waterfall()
+            sb, b = gb.waterfall()
+            assert np.array_equal(sa, sb) and np.array_equal(a, b), r
+            assert sa.size == 4, r
+        ga.close()
+        gb.close()
+
+
+@pytest.mark.parametrize("alpha", [2.0, -2.0])
+def test_paper_preset_field_parity(torch_gpu, alpha):
+    # the paper's setup (b = 0.02, R_curv = 30 H, filter on, 38730 cells),
+    # with its fiducial alpha and the tested -2
+    _say("case: paper preset, alpha %+.0f, field parity over 100 steps" % alpha)
+    cfg = dict(workloads.PAPER, alpha=alpha, cap_leptons=1 << 20, cap_photons=1 << 20, merge=False)
+    g, o = Gap(cfg), Oracle(cfg)
+    for n in range(100):
+        g.step(1)
+        o.step(1)
+        err = rel_field_err(g.field(), o.field())
+        assert err <= 1e-5, (n, err)
+    cg, co = g.counts(), o.counts()
+    assert cg["n_lep"] == co["n_lep"] and cg["n_injected"] == co["n_injected"] and cg["err"] == 0
+    assert abs(g.es() - o.Es) <= 1e-12 * max(1.0, abs(o.Es))
+    g.close()
