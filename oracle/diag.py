@@ -16,7 +16,11 @@ These are the quantities the paper reads off its kinetic simulations
  * the peak pair multiplicity in the gap zone and <gamma^-3> at its
    location, and the extremes of E (Fig. 5);
  * one row of the space-time diagram of E^2 (Fig. 4): the mean of E^2 over
-   each bin of cells, the last bin ragged.
+   each bin of cells, the last bin ragged;
+ * the power spectrum of E along the gap (the full-scale configuration's
+   field diagnostic): the field zero-padded to M = the next power of two
+   >= N cells, P_k = |sum_j E_j exp(-2 pi i j k / M)|^2 / M for
+   k = 0 .. M/2 (Parseval: sum over all M of P_k = sum_j E_j^2).
 
 Groups, in order: electrons moving up (u > 0), down; positrons up, down;
 photons with |x| > 2 moving up (x > 0), down.  A lepton's species is the
@@ -97,3 +101,16 @@ def waterfall_row(E: np.ndarray, bin_cells: int) -> np.ndarray:
         seg = E[b * bin_cells:(b + 1) * bin_cells]
         out[b] = np.sum(seg * seg) / seg.size
     return out
+
+
+def e_power_spectrum(E: np.ndarray) -> np.ndarray:
+    """[M/2 + 1]: P_k = |X_k|^2 / M of the field zero-padded to M = 2^ceil(log2 N)
+    (numpy's FFT in FP64 as the transform)."""
+    E = np.asarray(E, np.float64)
+    M = 1
+    while M < E.size:
+        M *= 2
+    x = np.zeros(M)
+    x[:E.size] = E
+    X = np.fft.fft(x)
+    return (X.real ** 2 + X.imag ** 2)[:M // 2 + 1] / M

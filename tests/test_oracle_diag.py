@@ -143,3 +143,29 @@ def test_waterfall_row_brute_force_ragged():
         nb = (E.size + B - 1) // B
         ref = [sum(float(e) * float(e) for e in E[b * B:(b + 1) * B]) / len(E[b * B:(b + 1) * B]) for b in range(nb)]
         assert np.allclose(diag.waterfall_row(E, B), ref, rtol=1e-13, atol=0.0)
+
+
+def test_e_power_spectrum_closed_forms():
+    # a cosine of integer mode m on M = N cells puts A^2 M / 4 into bin m and
+    # nothing elsewhere; a constant puts A^2 M into bin 0; Parseval holds for
+    # any field, also zero-padded (N = 1000 -> M = 1024)
+    M, m, A = 1024, 37, 3.0
+    j = np.arange(M)
+    P = diag.e_power_spectrum(A * np.cos(2 * np.pi * m * j / M))
+    assert P.shape == (M // 2 + 1,)
+    ref = np.zeros(M // 2 + 1)
+    ref[m] = A * A * M / 4
+    assert np.allclose(P, ref, rtol=1e-12, atol=1e-9)
+    P0 = diag.e_power_spectrum(np.full(M, A))
+    assert math.isclose(P0[0], A * A * M, rel_tol=1e-14) and np.max(np.abs(P0[1:])) < 1e-12
+    rng = np.random.default_rng(4)
+    E = rng.normal(0, 2, 1000)
+    P = diag.e_power_spectrum(E)
+    full = np.r_[P, P[1:-1][::-1]]                       # the mirrored half of a real field
+    assert math.isclose(full.sum(), float((E * E).sum()), rel_tol=1e-12)
+    # brute-force DFT of the padded field at a few wavenumbers
+    x = np.r_[E, np.zeros(24)]
+    for k in (0, 1, 77, 512):
+        X = sum(x[i] * complex(math.cos(2 * math.pi * i * k / 1024), -math.sin(2 * math.pi * i * k / 1024))
+                for i in range(1024))
+        assert math.isclose(P[k], abs(X) ** 2 / 1024, rel_tol=1e-9)
