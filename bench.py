@@ -312,6 +312,14 @@ def bench_diagnostics(g, calls=5):
         g.sync()
         return (time.perf_counter() - t0) * 1e3 / k
 
+    # the power spectrum of E (65536 cells -> one FP64 FFT of 2^16 points)
+    g.e_spectrum()
+    g.sync()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        g.e_spectrum()
+    spec_ms = (time.perf_counter() - t0) * 1e3 / calls
+
     k = 2 * 136
     plain = wall(k)
     g.set_waterfall(1, 64, 64)
@@ -320,7 +328,7 @@ def bench_diagnostics(g, calls=5):
     g.set_waterfall(0)
     return dict(peak_call_ms=ms, particles=n, gbs_at_12_bytes=12.0 * n / (ms / 1e3) / 1e9,
                 m_pairs_peak=pk["m_pairs"], h_peak=pk["h"], g3_at_peak=pk["g3"], e_min=pk["e_min"],
-                e_max=pk["e_max"], waterfall=dict(ms_per_step_without=plain, ms_per_step_with=rec,
+                e_max=pk["e_max"], e_spectrum_call_ms=spec_ms, waterfall=dict(ms_per_step_without=plain, ms_per_step_with=rec,
                                                   records_read=int(ws.size), bins=int(we.shape[1]),
                                                   max_e2=float(we.max()) if we.size else None))
 

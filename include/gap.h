@@ -174,6 +174,11 @@ int gap_sync(gap_t* g);
                                 momentum, taken exactly in FP64 against edges 10^(b/4) - 1;
                                 then the total weight and the total weight x gamma (gamma in
                                 FP32); reading resets it                                    */
+#define GAP_DIAG_ESPECTRUM 13  /* double[M/2 + 1], M the next power of two >= N: the power
+                                  spectrum of E along the gap, P_k = |sum_j E_j
+                                  exp(-2 pi i j k / M)|^2 / M with E zero-padded to M cells
+                                  (FP64 FFT of the FP32 field; Parseval: the sum of P_k over
+                                  all M wavenumbers is sum_j E_j^2)                       */
 #define GAP_DIAG_WATERFALL 12  /* the space-time diagram of E^2 (Fig. 4), as recorded since the
                                   last read (GAP_STATE_WATERFALL): int64 n, int64 nb, then n
                                   step indices in ascending order, then n x nb doubles, the

@@ -260,6 +260,8 @@ struct gap_t {
   double* wf_ring = nullptr;
   long long* wf_steps = nullptr;
   std::vector<void*> wf_mem;
+  double2* fft_buf = nullptr;   // 2 M complex values of the largest tube, allocated on first use
+  double* fft_pow = nullptr;
   int* pq_count = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
@@ -1561,6 +1563,31 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
         std::memcpy(v + j * nb, ring.data() + (size_t)order[j] * g->wf_nbmax, sizeof(double) * nb);
       }
       k_fill_i64<<<1, 256, 0, g->s>>>(g->wf_steps + (size_t)tube * g->wf_cap, g->wf_cap, -1);
+      return sync_and_err(g);
+    }
+    case GAP_DIAG_ESPECTRUM: {
+      // double[M/2 + 1], M the next power of two >= N
+      int M = 1;
+      while (M < N) M *= 2;
+      if (!fits(sizeof(double) * (size_t)(M / 2 + 1))) return GAP_EINVAL;
+      if (!g->fft_buf) {
+        int Mmax = 1;
+        while (Mmax < g->max_cells) Mmax *= 2;
+        g->fft_buf = (double2*)dalloc(g, sizeof(double2) * 2 * (size_t)Mmax);
+        g->fft_pow = (double*)dalloc(g, sizeof(double) * ((size_t)Mmax / 2 + 1));
+        if (!g->fft_buf || !g->fft_pow) return GAP_ENOMEM;
+      }
+      const int grid = std::max(1, std::min(1024, (M + 255) / 256));
+      double2* x = g->fft_buf;
+      double2* y = g->fft_buf + M;
+      k_fft_load<<<grid, 256, 0, g->s>>>(g->E + Th.cell_off, N, M, x);
+      for (int Ns = 1; Ns < M; Ns *= 2) {
+        k_fft_stage<<<grid, 256, 0, g->s>>>(x, y, M, Ns);
+        std::swap(x, y);
+      }
+      k_fft_power<<<grid, 256, 0, g->s>>>(x, M, g->fft_pow);
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(host_buf, g->fft_pow, sizeof(double) * (size_t)(M / 2 + 1), hipMemcpyDeviceToHost));
       return sync_and_err(g);
     }
     case GAP_DIAG_TIMING: {

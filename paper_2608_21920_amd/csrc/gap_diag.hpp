@@ -16,6 +16,9 @@
 //    surface, binned in log10 gamma, filled by the lepton passes (gap_kernels).
 //  * Waterfall (Fig. 4): the space-time diagram of E^2, the mean of E^2 over
 //    bins of cells recorded after the field update of every k-th step.
+//  * Power spectrum of E along the gap: the field zero-padded to M, the next
+//    power of two >= N, transformed by a radix-2 Stockham FFT in FP64,
+//    P_k = |X_k|^2 / M for k = 0 .. M/2.
 #pragma once
 #include "gap_kernels.hpp"
 
@@ -272,6 +275,36 @@ __global__ __launch_bounds__(TPB) void k_waterfall(WfCtx w) {
     if (lane_id() == 0) w.ring[((size_t)t * w.cap + slot) * w.nbmax + bin] = s / (double)(c1 - c0);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) w.steps[(size_t)t * w.cap + slot] = step;
+}
+
+// Power spectrum of E: load (zero-padded), log2 M Stockham stages (each
+// output in natural order after the last), |X|^2 / M.  One thread per pair
+// of the stage; every index is below M (M a power of two).
+__global__ void k_fft_load(const float* E, int N, int M, double2* x) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x)
+    x[j] = make_double2(j < N ? (double)E[j] : 0.0, 0.0);
+}
+
+// Stage with sub-transforms of length Ns (1, 2, 4, ..., M/2): pair j takes
+// in[j] and in[j + M/2], turns the second by exp(-i pi k / Ns) with
+// k = j mod Ns, and writes the sum and difference Ns apart at 2 (j - k) + k.
+__global__ void k_fft_stage(const double2* in, double2* out, int M, int Ns) {
+  const int h = M / 2;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < h; j += gridDim.x * blockDim.x) {
+    const int k = j & (Ns - 1);
+    double s, c;
+    sincospi(-(double)k / (double)Ns, &s, &c);
+    const double2 a = in[j], b = in[j + h];
+    const double2 t = make_double2(b.x * c - b.y * s, b.x * s + b.y * c);
+    const int o = 2 * (j - k) + k;
+    out[o] = make_double2(a.x + t.x, a.y + t.y);
+    out[o + Ns] = make_double2(a.x - t.x, a.y - t.y);
+  }
+}
+
+__global__ void k_fft_power(const double2* X, int M, double* P) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= M / 2; k += gridDim.x * blockDim.x)
+    P[k] = (X[k].x * X[k].x + X[k].y * X[k].y) / (double)M;
 }
 
 }  // namespace gap

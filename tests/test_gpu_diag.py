@@ -185,3 +185,31 @@ def test_waterfall_of_each_tube_of_a_batch(torch_gpu):
         assert np.array_equal(sa, sb) and np.array_equal(a, b), t
         gp.close()
     gb.close()
+
+
+def test_e_spectrum_matches_definition(grown):
+    g, cfg = grown
+    _say("case: E power spectrum of the tiny gap at step 300")
+    P = g.e_spectrum()
+    ref = diag.e_power_spectrum(g.field())
+    assert P.shape == ref.shape == (513,)
+    assert np.max(np.abs(P - ref)) <= 1e-11 * np.max(ref)
+
+
+def test_e_spectrum_of_a_set_cosine_and_a_ragged_grid(torch_gpu):
+    _say("case: E power spectrum of a frozen cosine field (4096 cells) and of 130 cells")
+    N, m, A = 4096, 111, 2.5
+    g = Gap(dict(workloads.TINY, n_cells=N, flags=G.FIELD_FROZEN | G.QED_OFF))
+    E = (A * np.cos(2 * np.pi * m * np.arange(N) / N)).astype(np.float32)
+    g.set_field(E, 0.0)
+    P = g.e_spectrum()
+    ref = diag.e_power_spectrum(E)
+    assert np.max(np.abs(P - ref)) <= 1e-11 * np.max(ref)
+    assert math.isclose(P[m], A * A * N / 4, rel_tol=1e-6)
+    assert np.max(np.delete(P, m)) < 1e-9 * P[m]
+    g.close()
+    g = Gap(dict(workloads.TINY, n_cells=130, seed=3))
+    g.step(40)
+    P, ref = g.e_spectrum(), diag.e_power_spectrum(g.field())
+    assert P.shape == (129,) and np.max(np.abs(P - ref)) <= 1e-11 * np.max(ref)
+    g.close()
