@@ -17,6 +17,11 @@ These are the quantities the paper reads off its kinetic simulations
    location, and the extremes of E (Fig. 5);
  * one row of the space-time diagram of E^2 (Fig. 4): the mean of E^2 over
    each bin of cells, the last bin ragged;
+ * momentum spectra (Fig. 3, row 1): the weight of electrons and positrons
+   per 1/8 decade of |u| = gamma beta and of photons per 1/8 decade of |x|,
+   from 1e-2 to 1e9, with an underflow and an overflow bin; a value goes to
+   the last edge 10^(-2 + b/8) its square reaches (compared in FP64 against
+   10^(2 (-2 + b/8)));
  * the power spectrum of E along the gap (the full-scale configuration's
    field diagnostic): the field zero-padded to M = the next power of two
    >= N cells, P_k = |sum_j E_j exp(-2 pi i j k / M)|^2 / M for
@@ -114,3 +119,32 @@ def e_power_spectrum(E: np.ndarray) -> np.ndarray:
     x[:E.size] = E
     X = np.fft.fft(x)
     return (X.real ** 2 + X.imag ** 2)[:M // 2 + 1] / M
+
+
+SPEC_EDGES = 89                          # edges 10^(-2 + b/8), b = 0 .. 88
+SPEC_NB = SPEC_EDGES + 1                 # underflow, 88 bins, overflow
+
+
+def spectrum_edges_sq() -> np.ndarray:
+    """Squares of the spectrum's bin edges, 10^(2 (-2 + b/8))."""
+    return np.array([10.0 ** (2.0 * (-2.0 + b / 8.0)) for b in range(SPEC_EDGES)])
+
+
+def spectra(lep: dict, pho: dict) -> np.ndarray:
+    """[3, SPEC_NB]: weight of electrons (by |u|), positrons (by |u|) and
+    photons (by |x|) per bin; bin = number of edges whose square is <= the
+    value's square (0: below 1e-2, SPEC_NB - 1: at or above 1e9)."""
+    thr = spectrum_edges_sq()
+    out = np.zeros((3, SPEC_NB))
+    w = np.asarray(lep["w"], np.float64)
+    u = np.asarray(lep["u"], np.float64)
+    live = w != 0.0
+    b = np.searchsorted(thr, u[live] * u[live], side="right")
+    sp = np.where(w[live] < 0.0, 0, 1)
+    np.add.at(out, (sp, b), np.abs(w[live]))
+    if pho is not None and len(pho["x"]):
+        x = np.asarray(pho["x"], np.float64)
+        pw = np.asarray(pho["w"], np.float64)
+        a = x != 0.0
+        np.add.at(out, (2, np.searchsorted(thr, x[a] * x[a], side="right")), pw[a])
+    return out

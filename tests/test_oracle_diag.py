@@ -169,3 +169,30 @@ def test_e_power_spectrum_closed_forms():
         X = sum(x[i] * complex(math.cos(2 * math.pi * i * k / 1024), -math.sin(2 * math.pi * i * k / 1024))
                 for i in range(1024))
         assert math.isclose(P[k], abs(X) ** 2 / 1024, rel_tol=1e-9)
+
+
+def test_spectra_bins_beam_and_brute_force():
+    thr = diag.spectrum_edges_sq()
+    assert thr.size == 89 and math.isclose(thr[0], 1e-4) and math.isclose(thr[-1], 1e18, rel_tol=1e-15)
+    # a mono-energetic beam: all weight in the bin of its |u|, by species
+    g = 1234.5
+    u = math.sqrt(g * g - 1)
+    b = int(math.floor(8 * (math.log10(u) + 2))) + 1
+    lep = dict(u=np.r_[np.full(10, u), np.full(4, -u)], w=np.r_[-np.ones(10), 2 * np.ones(4)])
+    pho = dict(x=np.array([0.0, 5.0, -5.0]), w=np.array([7.0, 1.0, 3.0]))
+    S = diag.spectra(lep, pho)
+    assert S[0, b] == 10 and S[1, b] == 8 and S[0].sum() == 10 and S[1].sum() == 8
+    bx = int(math.floor(8 * (math.log10(5.0) + 2))) + 1
+    assert S[2, bx] == 4 and S[2].sum() == 4
+    # edges: a value whose square is an edge goes up; below 1e-2 and above 1e9
+    # go to the end bins
+    rng = np.random.default_rng(8)
+    uu = np.r_[0.0, 1e-3, 10 ** rng.uniform(-3, 10, 500), 2e9]
+    ww = rng.choice([-1.0, 1.0, 0.5], uu.size)
+    S = diag.spectra(dict(u=uu, w=ww), None)
+    ref = np.zeros((3, 90))
+    for ui, wi in zip(uu, ww):
+        k = sum(1 for t in thr if ui * ui >= t)
+        ref[0 if wi < 0 else 1, k] += abs(wi)
+    assert np.array_equal(S, ref)
+    assert S[:, 0].sum() == sum(abs(w) for x, w in zip(uu, ww) if x < 1e-2)
