@@ -174,6 +174,12 @@ int gap_sync(gap_t* g);
                                 momentum, taken exactly in FP64 against edges 10^(b/4) - 1;
                                 then the total weight and the total weight x gamma (gamma in
                                 FP32); reading resets it                                    */
+#define GAP_DIAG_SPECTRA 14    /* double[3][90]: momentum spectra (Fig. 3, row 1), the weight of
+                                  electrons and of positrons per 1/8 decade of |u| = gamma
+                                  beta, and of photons per 1/8 decade of |x|: bin 0 below
+                                  1e-2, bin b in [10^(-2+(b-1)/8), 10^(-2+b/8)) for b = 1 ..
+                                  88, bin 89 from 1e9 on; decided on the FP32 value's
+                                  square in FP64 against the squares of the edges        */
 #define GAP_DIAG_ESPECTRUM 13  /* double[M/2 + 1], M the next power of two >= N: the power
                                   spectrum of E along the gap, P_k = |sum_j E_j
                                   exp(-2 pi i j k / M)|^2 / M with E zero-padded to M cells

@@ -260,6 +260,8 @@ struct gap_t {
   double* wf_ring = nullptr;
   long long* wf_steps = nullptr;
   std::vector<void*> wf_mem;
+  double* spec_thr = nullptr;   // squares of the momentum-spectrum edges
+  double* spec_acc = nullptr;   // [3][SPEC_NB]
   double2* fft_buf = nullptr;   // 2 M complex values of the largest tube, allocated on first use
   double* fft_pow = nullptr;
   int* pq_count = nullptr;
@@ -1125,6 +1127,15 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     for (int b = 0; b < RET_NB; ++b) thr[b] = std::pow(10.0, b / 4.0) - 1.0;
     HIPCHK(hipMemcpy(g->ret_thr, thr.data(), sizeof(double) * RET_NB, hipMemcpyHostToDevice));
   }
+  g->spec_thr = (double*)dalloc(g, sizeof(double) * SPEC_EDGES);
+  g->spec_acc = (double*)dalloc(g, sizeof(double) * 3 * SPEC_NB);
+  if (!g->spec_thr || !g->spec_acc) return GAP_ENOMEM;
+  {
+    // edge b at 10^(-2 + b/8) in |u| or |x|, compared as squares
+    std::vector<double> thr(SPEC_EDGES);
+    for (int b = 0; b < SPEC_EDGES; ++b) thr[b] = std::pow(10.0, 2.0 * (-2.0 + b / 8.0));
+    HIPCHK(hipMemcpy(g->spec_thr, thr.data(), sizeof(double) * SPEC_EDGES, hipMemcpyHostToDevice));
+  }
   g->prof_acc = (double*)dalloc(g, sizeof(double) * PROF_G * PROF_M * (size_t)max_n);
   g->prof_out = (double*)dalloc(g, sizeof(double) * PROF_G * 3 * (size_t)max_n);
   if (!g->ret || !g->prof_acc || !g->prof_out) return GAP_ENOMEM;
@@ -1563,6 +1574,14 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
         std::memcpy(v + j * nb, ring.data() + (size_t)order[j] * g->wf_nbmax, sizeof(double) * nb);
       }
       k_fill_i64<<<1, 256, 0, g->s>>>(g->wf_steps + (size_t)tube * g->wf_cap, g->wf_cap, -1);
+      return sync_and_err(g);
+    }
+    case GAP_DIAG_SPECTRA: {
+      if (!fits(sizeof(double) * 3 * SPEC_NB)) return GAP_EINVAL;
+      k_fill_i64<<<1, 256, 0, g->s>>>((long long*)g->spec_acc, 3 * SPEC_NB, 0);
+      k_spectra<<<kGrid, TPB, 0, g->s>>>(make_ctx(g), tube, g->spec_thr, g->spec_acc);
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(host_buf, g->spec_acc, sizeof(double) * 3 * SPEC_NB, hipMemcpyDeviceToHost));
       return sync_and_err(g);
     }
     case GAP_DIAG_ESPECTRUM: {

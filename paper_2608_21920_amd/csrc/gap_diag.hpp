@@ -307,4 +307,60 @@ __global__ void k_fft_power(const double2* X, int M, double* P) {
     P[k] = (X[k].x * X[k].x + X[k].y * X[k].y) / (double)M;
 }
 
+// Momentum spectra (Fig. 3, row 1): the weight of electrons and positrons
+// per 1/8 decade of |u| and of photons per 1/8 decade of |x|, from 1e-2 to
+// 1e9, with an underflow and an overflow bin.  A value's bin is the number of
+// edges 10^(-2 + b/8) (b = 0 .. 88) whose square its square reaches, taken
+// in FP64 against a host-computed table of the squares (binary search).  Each
+// workgroup sums into an LDS histogram over a strided set of 256-slot pieces
+// of both stores and adds it to acc[3][SPEC_NB] once.
+constexpr int SPEC_EDGES = 89;
+constexpr int SPEC_NB = SPEC_EDGES + 1;
+
+__device__ __forceinline__ int spec_bin(const double* thr, double p2) {
+  int lo = 0, hi = SPEC_EDGES;              // count of edges <= p2, in [0, SPEC_EDGES]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (thr[mid] <= p2) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(TPB) void k_spectra(Ctx cx, int tube, const double* thr, double* acc) {
+  __shared__ double s_h[3 * SPEC_NB];
+  __shared__ double s_thr[SPEC_EDGES];
+  for (int j = threadIdx.x; j < 3 * SPEC_NB; j += blockDim.x) s_h[j] = 0.0;
+  for (int j = threadIdx.x; j < SPEC_EDGES; j += blockDim.x) s_thr[j] = thr[j];
+  __syncthreads();
+  for (int sp = 0; sp < 2; ++sp) {
+    const bool lep = sp == 0;
+    const Ctl* ctl = lep ? cx.lc : cx.pc;
+    const long long S = ctl->n_sorted_chunks * CHUNK, tail = ctl->tail;
+    const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+    const int32_t* chunk = lep ? cx.lchunk : cx.pchunk;
+    const int32_t* tt = lep ? cx.ltt : cx.ptt;
+    for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+      uint32_t slot;
+      int tile;
+      piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
+      if (tile < 0 || cx.tiles[tile].tube != tube) continue;
+      if (lep) {
+        const float w = cx.L.w[slot];
+        if (w == 0.0f) continue;
+        const double u = (double)cx.L.u[slot];
+        atomicAdd(&s_h[(w < 0.0f ? 0 : 1) * SPEC_NB + spec_bin(s_thr, u * u)], (double)fabsf(w));
+      } else {
+        const float x = cx.P.x[slot];
+        if (x == 0.0f) continue;
+        const double xd = (double)x;
+        atomicAdd(&s_h[2 * SPEC_NB + spec_bin(s_thr, xd * xd)], (double)cx.P.w[slot]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < 3 * SPEC_NB; j += blockDim.x)
+    if (s_h[j] != 0.0) atomicAdd(&acc[j], s_h[j]);
+}
+
 }  // namespace gap

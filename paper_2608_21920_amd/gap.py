@@ -25,7 +25,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
- DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM) = range(14)
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA) = range(15)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
  STATE_PROFILE_BIN, STATE_WATERFALL) = range(9)
 # discharge diagnostics: profile groups and the return spectrum's bins
@@ -306,6 +306,11 @@ class Gap:
         steps = v[16:16 + 8 * n].view(np.int64).copy()
         e2 = v[16 + 8 * n:16 + 8 * n + 8 * n * nbr].view(np.float64).reshape(n, nbr).copy()
         return steps, e2
+
+    def spectra(self, tube=0) -> np.ndarray:
+        """[3, 90]: weight of electrons, positrons (by |u|) and photons (by |x|)
+        per 1/8 decade from 1e-2 to 1e9, with underflow and overflow bins."""
+        return self._diag(DIAG_SPECTRA, tube, 8 * 3 * 90).view(np.float64).reshape(3, 90).copy()
 
     def e_spectrum(self, tube=0) -> np.ndarray:
         """Power spectrum of E along the gap, zero-padded to M = the next power

@@ -213,3 +213,39 @@ def test_e_spectrum_of_a_set_cosine_and_a_ragged_grid(torch_gpu):
     P, ref = g.e_spectrum(), diag.e_power_spectrum(g.field())
     assert P.shape == (129,) and np.max(np.abs(P - ref)) <= 1e-11 * np.max(ref)
     g.close()
+
+
+def test_momentum_spectra_match_oracle(grown):
+    g, cfg = grown
+    _say("case: momentum spectra of the tiny gap at step 300")
+    L, P = leptons_as_oracle(g.leptons()), photons_as_oracle(g.photons())
+    S, ref = g.spectra(), diag.spectra(L, P)
+    assert S.shape == (3, 90)
+    assert np.array_equal(S, ref)                       # unit weights: exact sums in FP64
+    c = g.counts()
+    assert S[0].sum() + S[1].sum() == c["n_lep"] and S[2].sum() == c["n_pho"]
+
+
+def test_momentum_spectra_of_a_set_beam_and_of_a_batch_tube(torch_gpu):
+    _say("case: momentum spectra of a loaded beam and of each tube of a batch")
+    N = 256
+    g = Gap(dict(workloads.TINY, n_cells=N, flags=G.QED_OFF))
+    L = np.zeros(9, LEPTON_DTYPE)
+    L["cell"], L["frac"] = np.arange(9) * 20, 0
+    L["u"] = np.array([1e-3, 0.01, 0.0999, 1.0, 1e3, -1e3, 3.0e7, 1e9, 4e9], np.float32)
+    L["w"] = [1.0, -1.0, 2.0, -0.5, 1.0, -1.0, 1.0, -1.0, 3.0]
+    L["id"] = np.arange(1, 10, dtype=np.uint64)
+    g.set_particles(L)
+    S, ref = g.spectra(), diag.spectra(leptons_as_oracle(L), None)
+    assert np.array_equal(S, ref)
+    assert S[1, 0] == 1.0 and S[1, 89] == 3.0 and S[0, 89] == 1.0    # 1e9 in float32 is >= 1e9
+    g.close()
+    cfgs = [dict(workloads.TINY, n_cells=384, seed=5), dict(workloads.TINY, n_cells=130, b=0.2, seed=7)]
+    gb = Gap(cfgs)
+    gb.step(150)
+    for t, c in enumerate(cfgs):
+        gp = Gap(c)
+        gp.step(150)
+        assert np.array_equal(gb.spectra(t), gp.spectra()), t
+        gp.close()
+    gb.close()
