@@ -22,6 +22,10 @@ These are the quantities the paper reads off its kinetic simulations
    from 1e-2 to 1e9, with an underflow and an overflow bin; a value goes to
    the last edge 10^(-2 + b/8) its square reaches (compared in FP64 against
    10^(2 (-2 + b/8)));
+ * phase space (Fig. 3, rows 1-4): the same weights per bin of B cells and
+   per signed momentum bin, 180 columns running from large negative to large
+   positive p (u or x): column 90 + b for p > 0, 89 - b for p <= 0, b the
+   momentum-spectrum bin of |p|;
  * the power spectrum of E along the gap (the full-scale configuration's
    field diagnostic): the field zero-padded to M = the next power of two
    >= N cells, P_k = |sum_j E_j exp(-2 pi i j k / M)|^2 / M for
@@ -147,4 +151,31 @@ def spectra(lep: dict, pho: dict) -> np.ndarray:
         pw = np.asarray(pho["w"], np.float64)
         a = x != 0.0
         np.add.at(out, (2, np.searchsorted(thr, x[a] * x[a], side="right")), pw[a])
+    return out
+
+
+PHASE_NP = 2 * SPEC_NB                   # signed momentum columns
+
+
+def phase_space(lep: dict, pho: dict, n_cells: int, bin_cells: int) -> np.ndarray:
+    """[3, nb, 180]: weight of electrons, positrons (by u) and photons (by x)
+    per bin of `bin_cells` cells and signed momentum column."""
+    thr = spectrum_edges_sq()
+    nb = (n_cells + bin_cells - 1) // bin_cells
+    out = np.zeros((3, nb, PHASE_NP))
+
+    def col(p):
+        b = np.searchsorted(thr, p * p, side="right")
+        return np.where(p > 0.0, SPEC_NB + b, SPEC_NB - 1 - b)
+
+    w = np.asarray(lep["w"], np.float64)
+    u = np.asarray(lep["u"], np.float64)
+    live = w != 0.0
+    cell = np.clip(np.asarray(lep["cell"], np.int64), 0, n_cells - 1)[live]
+    np.add.at(out, (np.where(w[live] < 0.0, 0, 1), cell // bin_cells, col(u[live])), np.abs(w[live]))
+    if pho is not None and len(pho["x"]):
+        x = np.asarray(pho["x"], np.float64)
+        a = x != 0.0
+        pc = np.clip(np.asarray(pho["cell"], np.int64), 0, n_cells - 1)[a]
+        np.add.at(out, (2, pc // bin_cells, col(x[a])), np.asarray(pho["w"], np.float64)[a])
     return out

@@ -196,3 +196,32 @@ def test_spectra_bins_beam_and_brute_force():
         ref[0 if wi < 0 else 1, k] += abs(wi)
     assert np.array_equal(S, ref)
     assert S[:, 0].sum() == sum(abs(w) for x, w in zip(uu, ww) if x < 1e-2)
+
+
+def test_phase_space_brute_force_and_marginals():
+    rng = np.random.default_rng(9)
+    N, B = 300, 32
+    lep, pho = _state(rng, 1500, 600, N)
+    ph = diag.phase_space(lep, pho, N, B)
+    assert ph.shape == (3, 10, 180)
+    thr = diag.spectrum_edges_sq()
+    ref = np.zeros_like(ph)
+    for c, u, w in zip(lep["cell"], lep["u"], lep["w"]):
+        if w == 0.0:
+            continue
+        b = sum(1 for t in thr if u * u >= t)
+        ref[0 if w < 0 else 1, min(max(int(c), 0), N - 1) // B, 90 + b if u > 0 else 89 - b] += abs(w)
+    for c, x, w in zip(pho["cell"], pho["x"], pho["w"]):
+        if x == 0.0:
+            continue
+        b = sum(1 for t in thr if x * x >= t)
+        ref[2, min(max(int(c), 0), N - 1) // B, 90 + b if x > 0 else 89 - b] += w
+    assert np.allclose(ph, ref, rtol=1e-14, atol=0.0)
+    # marginals: over momentum it is the profile's weight per bin and species
+    # (photons: all, not only |x| > 2); over space, the |p| spectrum folded
+    S = diag.spectra(lep, pho)
+    folded = ph.sum(axis=1)[:, 90:] + ph.sum(axis=1)[:, 89::-1]
+    assert np.allclose(folded, S, rtol=1e-13, atol=0.0)
+    prof = diag.profile_sums(lep, None, N, B)
+    assert np.allclose(ph[0].sum(axis=1), prof[:, 0, 0] + prof[:, 1, 0], rtol=1e-13)
+    assert np.allclose(ph[1].sum(axis=1), prof[:, 2, 0] + prof[:, 3, 0], rtol=1e-13)
