@@ -326,6 +326,13 @@ def bench_diagnostics(g, calls=5):
     for _ in range(calls):
         g.spectra()
     mspec_ms = (time.perf_counter() - t0) * 1e3 / calls
+    # phase space (bins of 64 cells x 180 signed momentum columns)
+    g.phase_space()
+    g.sync()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        g.phase_space()
+    phase_ms = (time.perf_counter() - t0) * 1e3 / calls
 
     k = 2 * 136
     plain = wall(k)
@@ -335,7 +342,7 @@ def bench_diagnostics(g, calls=5):
     g.set_waterfall(0)
     return dict(peak_call_ms=ms, particles=n, gbs_at_12_bytes=12.0 * n / (ms / 1e3) / 1e9,
                 m_pairs_peak=pk["m_pairs"], h_peak=pk["h"], g3_at_peak=pk["g3"], e_min=pk["e_min"],
-                e_max=pk["e_max"], e_spectrum_call_ms=spec_ms, momentum_spectra_call_ms=mspec_ms, waterfall=dict(ms_per_step_without=plain, ms_per_step_with=rec,
+                e_max=pk["e_max"], e_spectrum_call_ms=spec_ms, momentum_spectra_call_ms=mspec_ms, phase_space_call_ms=phase_ms, waterfall=dict(ms_per_step_without=plain, ms_per_step_with=rec,
                                                   records_read=int(ws.size), bins=int(we.shape[1]),
                                                   max_e2=float(we.max()) if we.size else None))
 

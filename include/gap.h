@@ -180,6 +180,11 @@ int gap_sync(gap_t* g);
                                   1e-2, bin b in [10^(-2+(b-1)/8), 10^(-2+b/8)) for b = 1 ..
                                   88, bin 89 from 1e9 on; decided on the FP32 value's
                                   square in FP64 against the squares of the edges        */
+#define GAP_DIAG_PHASE   15    /* double[3][nb][180]: phase space (Fig. 3, rows 1-4), the weights
+                                  of GAP_DIAG_SPECTRA per bin of GAP_STATE_PROFILE_BIN cells
+                                  and signed momentum column: 90 + b for p > 0 and 89 - b
+                                  for p <= 0 (p = u, photons x), b the spectrum bin of |p|;
+                                  the first call for a bin width allocates device memory  */
 #define GAP_DIAG_ESPECTRUM 13  /* double[M/2 + 1], M the next power of two >= N: the power
                                   spectrum of E along the gap, P_k = |sum_j E_j
                                   exp(-2 pi i j k / M)|^2 / M with E zero-padded to M cells

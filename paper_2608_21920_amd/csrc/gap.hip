@@ -262,6 +262,8 @@ struct gap_t {
   std::vector<void*> wf_mem;
   double* spec_thr = nullptr;   // squares of the momentum-spectrum edges
   double* spec_acc = nullptr;   // [3][SPEC_NB]
+  double* phase_acc = nullptr;  // [3][nb][PHASE_NP], allocated on first use
+  size_t phase_cap = 0;
   double2* fft_buf = nullptr;   // 2 M complex values of the largest tube, allocated on first use
   double* fft_pow = nullptr;
   int* pq_count = nullptr;
@@ -1574,6 +1576,24 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
         std::memcpy(v + j * nb, ring.data() + (size_t)order[j] * g->wf_nbmax, sizeof(double) * nb);
       }
       k_fill_i64<<<1, 256, 0, g->s>>>(g->wf_steps + (size_t)tube * g->wf_cap, g->wf_cap, -1);
+      return sync_and_err(g);
+    }
+    case GAP_DIAG_PHASE: {
+      // double[3][nb][180], nb bins of the profile's bin width
+      const int B = g->prof_bin;
+      const int nb = (N + B - 1) / B;
+      const size_t n = (size_t)3 * nb * PHASE_NP;
+      if (!fits(sizeof(double) * n)) return GAP_EINVAL;
+      if (g->phase_cap < n) {
+        g->phase_acc = (double*)dalloc(g, sizeof(double) * n);   // kept until the handle ends
+        if (!g->phase_acc) return GAP_ENOMEM;
+        g->phase_cap = n;
+      }
+      k_fill_i64<<<std::max(1, (int)std::min<size_t>(1024, (n + 255) / 256)), 256, 0, g->s>>>(
+          (long long*)g->phase_acc, (long long)n, 0);
+      k_phase<<<kGrid, TPB, 0, g->s>>>(make_ctx(g), tube, B, nb, g->spec_thr, g->phase_acc);
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(host_buf, g->phase_acc, sizeof(double) * n, hipMemcpyDeviceToHost));
       return sync_and_err(g);
     }
     case GAP_DIAG_SPECTRA: {

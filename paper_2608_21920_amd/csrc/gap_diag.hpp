@@ -363,4 +363,63 @@ __global__ __launch_bounds__(TPB) void k_spectra(Ctx cx, int tube, const double*
     if (s_h[j] != 0.0) atomicAdd(&acc[j], s_h[j]);
 }
 
+// Phase space (Fig. 3, rows 1-4): the weights of the momentum spectra, per
+// bin of B cells and signed momentum column (column SPEC_NB + b for p > 0,
+// SPEC_NB - 1 - b for p <= 0, b the spectrum bin of |p|), added to
+// acc[3][nb][2 SPEC_NB] with one atomic per distinct key of a wave.
+constexpr int PHASE_NP = 2 * SPEC_NB;
+
+__device__ __forceinline__ void phase_wave_add(long long key, double v, double* acc) {
+  while (true) {
+    const uint64_t m = __ballot(key >= 0);
+    if (!m) break;
+    const int lead = __ffsll((long long)m) - 1;
+    const long long kk = __shfl(key, lead);
+    double a = key == kk ? v : 0.0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d);
+    if (lane_id() == lead) atomicAdd(&acc[kk], a);
+    if (key == kk) key = -1;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_phase(Ctx cx, int tube, int B, int nb, const double* thr, double* acc) {
+  __shared__ double s_thr[SPEC_EDGES];
+  for (int j = threadIdx.x; j < SPEC_EDGES; j += blockDim.x) s_thr[j] = thr[j];
+  __syncthreads();
+  const Tube& T = cx.tubes[tube];
+  for (int sp = 0; sp < 2; ++sp) {
+    const bool lep = sp == 0;
+    const Ctl* ctl = lep ? cx.lc : cx.pc;
+    const long long S = ctl->n_sorted_chunks * CHUNK, tail = ctl->tail;
+    const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
+    const int32_t* chunk = lep ? cx.lchunk : cx.pchunk;
+    const int32_t* tt = lep ? cx.ltt : cx.ptt;
+    for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
+      uint32_t slot;
+      int tile;
+      piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
+      long long key = -1;
+      double v = 0.0;
+      if (tile >= 0 && cx.tiles[tile].tube == tube) {
+        const float a = lep ? cx.L.w[slot] : cx.P.x[slot];
+        if (a != 0.0f) {
+          const Tile tl = cx.tiles[tile];
+          const uint32_t pos = lep ? cx.L.pos[slot] : cx.P.pos[slot];
+          int cell = tl.base + (int)(pos >> FRAC);
+          if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
+          cell = min(max(cell, 0), T.N - 1);
+          const double p = lep ? (double)cx.L.u[slot] : (double)a;
+          const int b = spec_bin(s_thr, p * p);
+          const int col = p > 0.0 ? SPEC_NB + b : SPEC_NB - 1 - b;
+          const int s3 = lep ? (a < 0.0f ? 0 : 1) : 2;
+          key = ((long long)s3 * nb + cell / B) * PHASE_NP + col;
+          v = lep ? (double)fabsf(a) : (double)cx.P.w[slot];
+        }
+      }
+      phase_wave_add(key, v, acc);
+    }
+  }
+}
+
 }  // namespace gap

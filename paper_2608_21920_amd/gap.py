@@ -25,7 +25,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
- DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA) = range(15)
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE) = range(16)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
  STATE_PROFILE_BIN, STATE_WATERFALL) = range(9)
 # discharge diagnostics: profile groups and the return spectrum's bins
@@ -311,6 +311,14 @@ class Gap:
         """[3, 90]: weight of electrons, positrons (by |u|) and photons (by |x|)
         per 1/8 decade from 1e-2 to 1e9, with underflow and overflow bins."""
         return self._diag(DIAG_SPECTRA, tube, 8 * 3 * 90).view(np.float64).reshape(3, 90).copy()
+
+    def phase_space(self, tube=0) -> np.ndarray:
+        """[3, nb, 180]: weight of electrons, positrons (by u) and photons (by x)
+        per profile bin and signed momentum column (90 + b for p > 0, 89 - b
+        for p <= 0, b the momentum-spectrum bin of |p|)."""
+        b = getattr(self, "_prof_bin", 64)
+        nb = (self.n_cells(tube) + b - 1) // b
+        return self._diag(DIAG_PHASE, tube, 8 * 3 * nb * 180).view(np.float64).reshape(3, nb, 180).copy()
 
     def e_spectrum(self, tube=0) -> np.ndarray:
         """Power spectrum of E along the gap, zero-padded to M = the next power

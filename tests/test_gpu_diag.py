@@ -249,3 +249,31 @@ def test_momentum_spectra_of_a_set_beam_and_of_a_batch_tube(torch_gpu):
         assert np.array_equal(gb.spectra(t), gp.spectra()), t
         gp.close()
     gb.close()
+
+
+@pytest.mark.parametrize("bin_cells", [64, 37])
+def test_phase_space_matches_oracle(grown, bin_cells):
+    g, cfg = grown
+    _say("case: phase space of the tiny gap at step 300, bins of %d cells" % bin_cells)
+    g.set_profile_bin(bin_cells)
+    L, P = leptons_as_oracle(g.leptons()), photons_as_oracle(g.photons())
+    ph, ref = g.phase_space(), diag.phase_space(L, P, cfg["n_cells"], bin_cells)
+    assert ph.shape == ref.shape == (3, (cfg["n_cells"] + bin_cells - 1) // bin_cells, 180)
+    assert np.array_equal(ph, ref)                      # unit weights: exact sums in FP64
+    S = g.spectra()
+    assert np.array_equal(ph.sum(axis=1)[:, 90:] + ph.sum(axis=1)[:, 89::-1], S)
+
+
+def test_phase_space_of_one_tube_of_a_batch(torch_gpu):
+    _say("case: phase space of each tube of a 2-tube handle vs plain handles")
+    cfgs = [dict(workloads.TINY, n_cells=384, seed=5), dict(workloads.TINY, n_cells=130, b=0.2, seed=7)]
+    gb = Gap(cfgs)
+    gb.step(150)
+    gb.set_profile_bin(16)
+    for t, c in enumerate(cfgs):
+        gp = Gap(c)
+        gp.step(150)
+        gp.set_profile_bin(16)
+        assert np.array_equal(gb.phase_space(t), gp.phase_space()), t
+        gp.close()
+    gb.close()
