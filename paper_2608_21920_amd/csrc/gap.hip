@@ -1078,13 +1078,14 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
     // defaults measured on the production gap (2e7 particles): one resident
     // round for the lepton pass, four for the photon pass (short ranges keep
-    // its conversion queue segments small), eight workgroups per CU for the
-    // tail passes; gap_autotune or GAP_STATE_LAUNCH can change them
+    // its conversion queue segments small), two workgroups per CU for each
+    // role of the fused tail launch; gap_autotune or GAP_STATE_LAUNCH can
+    // change them
     g->round_lep = std::max(8, (cus * std::max(nl, 1)) / 8 * 8);
     g->round_pho = std::max(8, (cus * std::max(np, 1)) / 8 * 8);
     g->grid_lep = g->round_lep;
     g->grid_pho = 4 * g->round_pho;
-    g->grid_tail = std::max(8, cus * 8);
+    g->grid_tail = std::max(8, cus * 2);
     g->cus = cus;
   }
   if (g->total_nodes > (1LL << 30)) return GAP_EINVAL;
