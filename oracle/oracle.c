@@ -445,7 +445,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
 void orc_free(orc_sim* s) {
   if (!s) return;
   free(s->lep); free(s->pho); free(s->E); free(s->E0); free(s->Eb); free(s->rho); free(s->ev);
-  free(s->q_cosh); free(s->q_g);
+  free(s->q_cosh); free(s->q_g); free((void*)s->rep);
   free(s);
 }
 
@@ -893,6 +893,13 @@ void orc_set_field(orc_sim* s, const double* E, double Es) {
 
 void orc_set_injection(orc_sim* s, double acc, uint64_t count) { s->inj_acc = acc; s->inj_count = count; }
 
+/* Test hook: the merge of both species on the current state, as a step whose
+ * merge check is due runs it first (draws keyed by the current step). */
+void orc_merge_now(orc_sim* s) {
+  merge_leptons(s);
+  merge_photons(s);
+}
+
 /* Install a recorded event log for replay (sorted here by step/kind/id/sub). */
 static int ev_sort_cmp(const void* a, const void* b) {
   const oevent* x = (const oevent*)a; const oevent* y = (const oevent*)b;
@@ -906,6 +913,7 @@ void orc_set_replay(orc_sim* s, int64_t n, const int32_t* kind, const int32_t* s
     e[i].cell = cell[i]; e[i].xi = xi[i]; e[i].w = w[i];
   }
   qsort(e, n, sizeof(oevent), ev_sort_cmp);
+  free((void*)s->rep);   /* a log installed before is replaced */
   s->rep = e; s->nrep = n;
 }
 

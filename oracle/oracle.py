@@ -96,6 +96,7 @@ def _load():
             [C.c_void_p] * 6 + [C.c_double, C.c_int64]
         lib.orc_set_field.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         lib.orc_set_injection.argtypes = [C.c_void_p, C.c_double, C.c_uint64]
+        lib.orc_merge_now.argtypes = [C.c_void_p]
         lib.orc_set_replay.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 8
         lib.orc_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         lib.orc_tsyn.restype = C.c_double
@@ -258,6 +259,11 @@ class Oracle:
 
     def set_injection(self, acc: float, count: int) -> None:
         self.lib.orc_set_injection(self.h, float(acc), int(count))
+
+    def merge_now(self) -> None:
+        """Run the weight-doubling merge of both species on the current
+        state (the first part of a step whose merge check is due)."""
+        self.lib.orc_merge_now(self.h)
 
     def set_replay(self, ev: dict) -> None:
         self._rep = {k: np.ascontiguousarray(ev[k], dtype=dt) for k, dt in self._EV}

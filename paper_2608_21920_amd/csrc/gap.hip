@@ -433,7 +433,9 @@ enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, 
 struct Timer {
   gap_t* g; int id; hipStream_t st; hipEvent_t a = nullptr, b = nullptr;
   Timer(gap_t* gg, int i, hipStream_t stream) : g(gg), id(i), st(stream) {
-    if (g->timing && g->ev_pool.size() < 200000) {
+    // eager steps only: an event recorded into a captured graph is not a
+    // timestamp the host can read
+    if (g->timing && !g->capturing && g->ev_pool.size() < 200000) {
       a = next_event(g); b = next_event(g);
       if (a) (void)hipEventRecord(a, st);
     }
