@@ -28,7 +28,9 @@
  *    of default priority and joins it back before the step ends, so the
  *    order seen on the caller's stream is unchanged); errors raised on the
  *    device are sticky and reported by the next call that synchronises
- *    (gap_sync, gap_diag, gap_set_state);
+ *    (gap_sync, gap_diag, gap_set_state); once reported, an error stops
+ *    the run: gap_step, gap_step_graph and the window calls return it
+ *    without enqueuing work;
  *  - one handle must not be used from two host threads at once.
  */
 #ifndef GAP_H
@@ -247,6 +249,12 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
                                   stops recording and frees the record.  Allocates device
                                   memory (GAP_ENOMEM if it cannot), drops a captured graph,
                                   waits for queued work and empties the record              */
+#define GAP_STATE_RAISE     9  /* int32 bits: OR them into the device error word, as a kernel
+                                  that meets the condition does (1 store overflow -> GAP_ECAP,
+                                  2 particle outside its tile window -> GAP_ETILE, 4 non-finite
+                                  field -> GAP_ENAN, 8 field scan wait bound -> GAP_EDEVICE;
+                                  any other bit GAP_EINVAL).  For tests of the error path:
+                                  the next synchronising call reports the code              */
 #define GAP_STATE_LAUNCH    6  /* int32[4]: workgroups of the sorted lepton pass, of the sorted
                                   photon pass and of the tail passes, and the re-sort interval
                                   (the values gap_autotune returns); grids must be multiples
@@ -288,7 +296,7 @@ int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen);
  * i.e. ckpt_every <= (64 - 2) / cfl - 1 (136 steps at cfl = 0.45); GAP_EINVAL
  * otherwise.  Blocks until the window has run.
  *
- * gap_backward then returns, per tube, dL/dalpha and dL/dn_inj of that window
+ * gap_window_backward then returns, per tube, dL/dalpha and dL/dn_inj of that window
  * (host arrays of n_tubes doubles), where n_inj = inj_rate * inj_weight is the
  * injected charge per step in units of n_co dx (use GAP_INJ_FIXED so that the
  * number of injected macro-electrons does not depend on inj_weight).  The map
@@ -304,7 +312,17 @@ int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen);
  * state.  GAP_ESTATE if no window was run, or if steps or state changes came
  * after it.  Blocks until done. */
 int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss);
-int gap_backward(gap_t* g, double* dL_dalpha, double* dL_dninj);
+int gap_window_backward(gap_t* g, double* dL_dalpha, double* dL_dninj);
+
+/* Both halves in one call: gap_window_forward(g, window_steps, ckpt_every,
+ * loss) then gap_window_backward(g, dL_dalpha, dL_dninj); loss, dL_dalpha
+ * and dL_dninj are host arrays of n_tubes doubles.  Returns the first error
+ * of the two.  The window's QED realisation is recorded implicitly: every
+ * random decision is Philox keyed by (seed, particle id, step), so the
+ * recomputation inside the reverse pass draws the same events and no event
+ * log is kept. */
+int gap_backward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss, double* dL_dalpha,
+                 double* dL_dninj);
 
 /* Release the handle and every buffer it owns (waits for queued work). */
 void gap_free(gap_t* g);

@@ -466,6 +466,7 @@ FieldCtx make_fctx(gap_t* g, int mode) {
 }
 
 __global__ void k_cold_off(Ctl* c) { c->cold_steps = -1; }
+__global__ void k_raise(int* err, int bits) { atomicOr(err, bits); }
 
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
@@ -1427,6 +1428,7 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
 
 int gap_step(gap_t* g, int64_t n_steps) {
   if (!g || n_steps < 0) return GAP_EINVAL;
+  if (g->sticky) return g->sticky;   // a reported error stops the run
   for (int64_t i = 0; i < n_steps; ++i) enqueue_step(g, i + 1 < n_steps);
   join_photon_side(g);   // the caller's stream holds all the work again
   if (hipGetLastError() != hipSuccess) return GAP_EDEVICE;
@@ -1435,7 +1437,7 @@ int gap_step(gap_t* g, int64_t n_steps) {
 
 int gap_step_graph(gap_t* g, int64_t n_steps) {
   if (!g || n_steps < 0) return GAP_EINVAL;
-  if (n_steps == 0) return g->sticky;
+  if (n_steps == 0 || g->sticky) return g->sticky;
   if (g->s == nullptr) return GAP_ESTATE;   // stream capture needs a non-default stream
   join_photon_side(g);
   const bool valid = g->gexec && g->gsteps == n_steps && g->lep.cur == g->gs_l && g->pho.cur == g->gs_p &&
@@ -1741,6 +1743,15 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
     g->wf_nbmax = nbmax;
     return sync_and_err(g);
   }
+  if (kind == GAP_STATE_RAISE) {
+    // the device error word as a kernel sets it (tests of the error path)
+    if (bytes < 4) return GAP_EINVAL;
+    int32_t bits;
+    std::memcpy(&bits, host_buf, 4);
+    if (bits & ~(E_CAP | E_TILE | E_NAN | E_SCAN)) return GAP_EINVAL;
+    k_raise<<<1, 1, 0, g->s>>>(g->err, bits);
+    return GAP_OK;
+  }
   if (kind == GAP_STATE_LAUNCH) {
     if (bytes < 16) return GAP_EINVAL;
     int32_t v[4];
@@ -1909,12 +1920,22 @@ int gap_autotune(gap_t* g, int32_t trial_steps, int32_t* chosen) {
 int gap_window_forward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss) {
   if (!g || window_steps < 1 || ckpt_every < 1 || !loss) return GAP_EINVAL;
   if (g->any_filter) return GAP_EINVAL;   // the adjoint is of the unfiltered update
+  if (g->sticky) return g->sticky;
   return window_forward(g, window_steps, ckpt_every, loss);
 }
 
-int gap_backward(gap_t* g, double* dL_dalpha, double* dL_dninj) {
+int gap_window_backward(gap_t* g, double* dL_dalpha, double* dL_dninj) {
   if (!g || !dL_dalpha || !dL_dninj) return GAP_EINVAL;
+  if (g->sticky) return g->sticky;
   return backward(g, dL_dalpha, dL_dninj);
+}
+
+int gap_backward(gap_t* g, int64_t window_steps, int32_t ckpt_every, double* loss, double* dL_dalpha,
+                 double* dL_dninj) {
+  if (!g || !loss || !dL_dalpha || !dL_dninj) return GAP_EINVAL;
+  int e = gap_window_forward(g, window_steps, ckpt_every, loss);
+  if (e) return e;
+  return gap_window_backward(g, dL_dalpha, dL_dninj);
 }
 
 void gap_free(gap_t* g) {

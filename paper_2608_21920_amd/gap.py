@@ -27,7 +27,7 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
  DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE) = range(16)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
- STATE_PROFILE_BIN, STATE_WATERFALL) = range(9)
+ STATE_PROFILE_BIN, STATE_WATERFALL, STATE_RAISE) = range(10)
 # discharge diagnostics: profile groups and the return spectrum's bins
 PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
 RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
@@ -112,8 +112,10 @@ def load_library():
     lib.gap_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     lib.gap_window_forward.restype = C.c_int
     lib.gap_window_forward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.gap_window_backward.restype = C.c_int
+    lib.gap_window_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gap_backward.restype = C.c_int
-    lib.gap_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gap_backward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gap_sync_inverse_host.restype = C.c_int
     lib.gap_sync_inverse_host.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     _lib = lib
@@ -350,8 +352,22 @@ class Gap:
     def backward(self):
         da = np.zeros(self.n_tubes, np.float64)
         dn = np.zeros(self.n_tubes, np.float64)
-        _check(self.lib.gap_backward(self.h, da.ctypes.data, dn.ctypes.data), "gap_backward")
+        _check(self.lib.gap_window_backward(self.h, da.ctypes.data, dn.ctypes.data), "gap_window_backward")
         return da, dn
+
+    def window_grad(self, steps: int, ckpt_every: int = 100):
+        """Forward and reverse pass in one call: (loss, dL/dalpha, dL/dn_inj)."""
+        loss = np.zeros(self.n_tubes, np.float64)
+        da = np.zeros(self.n_tubes, np.float64)
+        dn = np.zeros(self.n_tubes, np.float64)
+        _check(self.lib.gap_backward(self.h, int(steps), int(ckpt_every), loss.ctypes.data, da.ctypes.data,
+                                     dn.ctypes.data), "gap_backward")
+        return loss, da, dn
+
+    def raise_device_error(self, bits: int):
+        """Set device error bits as a kernel would (tests of the error path)."""
+        buf = np.array([bits], np.int32)
+        _check(self.lib.gap_set_state(self.h, STATE_RAISE, 0, buf.ctypes.data, buf.nbytes), "raise")
 
     def set_injection(self, acc: float, count: int):
         buf = np.concatenate([np.array([acc], np.float64).view(np.uint8), np.array([count], np.uint64).view(np.uint8)])

@@ -220,7 +220,17 @@ void single_tube() {
   // the window needs the device to re-sort (kernels do not run here): either
   // result is a clean return
   int e = gap_window_forward(g, 12, 5, loss);
-  if (e == 0) expect(gap_backward(g, da, dn), "backward");
+  if (e == 0) expect(gap_window_backward(g, da, dn), "backward");
+  e = gap_backward(g, 12, 5, loss, da, dn);
+  if (e != 0 && e != GAP_ESTATE) expect(e, "backward in one call");
+  // the error hook (no kernel runs here, so the word itself stays clear)
+  int32_t bits = 2;
+  expect(gap_set_state(g, GAP_STATE_RAISE, 0, &bits, 4), "raise");
+  bits = 64;
+  if (gap_set_state(g, GAP_STATE_RAISE, 0, &bits, 4) != GAP_EINVAL) {
+    fprintf(stderr, "REPLAY: unknown error bit accepted\n");
+    g_fail = 1;
+  }
   gap_free(g);
   hipStreamDestroy(st);
 }

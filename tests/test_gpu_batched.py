@@ -106,3 +106,39 @@ def test_autotune_keeps_the_drift_bound(torch_gpu):
     g.sync()
     assert g.counts()["err"] == 0
     g.close()
+
+
+def test_launch_shape_sweep_recaptures_equal_single_tubes(torch_gpu):
+    """The batched launch-shape sweep as a regression test of the graph
+    lifecycle: eight cycles of a new launch shape (which drops the captured
+    graph), then two replays whose length holds one re-sort, so the store
+    parity flips and each replay captures a new graph while the previous
+    replay may still run, then eager steps and reads.  Every tube must equal
+    a single-tube run of the same number of eager steps, bitwise."""
+    import torch
+    _say("case: 6-tube ensemble, 8 launch-shape cycles with re-capture")
+    cfgs = [dict(c, n_cells=c["n_cells"] // 8, cap_leptons=c["cap_leptons"] // 8, cap_photons=c["cap_photons"] // 8)
+            for c in workloads.batched_tubes(6, seed=1)]
+    shapes = [(256, 512, 512, 68), (512, 256, 1024, 34), (1024, 1024, 256, 136), (256, 256, 256, 17),
+              (512, 1024, 512, 68), (1024, 512, 1024, 34), (256, 1024, 256, 136), (512, 512, 512, 40)]
+    s = torch.cuda.Stream()
+    total = 0
+    with torch.cuda.stream(s):
+        gb = Gap(cfgs, stream=s)
+        for cyc, shp in enumerate(shapes):
+            _say("  cycle %d shape %s" % (cyc, shp))
+            gb.set_launch(*shp)
+            n = shp[3] + (cyc & 1)
+            gb.step_graph(n)
+            gb.step_graph(n)
+            gb.step(3)
+            total += 2 * n + 3
+            c = gb.counts(cyc % len(cfgs))
+            assert c["err"] == 0 and c["step"] == total
+        gb.sync()
+        for t in (0, 3, 5):
+            g1 = Gap(cfgs[t], stream=s)
+            g1.step(total)
+            _same(gb, t, g1, 0)
+            g1.close()
+        gb.close()
