@@ -330,6 +330,19 @@ void gap_free(gap_t* g);
 /* Static description of an error code. */
 const char* gap_strerror(int code);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the power
+ * spectrum of GAP_DIAG_ESPECTRUM for tube `tube`, written to `power`, a
+ * device buffer of power_len >= M/2 + 1 doubles (M the next power of two
+ * >= N), owned by the caller.  Enqueued on the handle's stream, it neither
+ * allocates nor waits: the FFT's two ping-pong buffers live in a static
+ * workspace of the library on each device (2 x 2^18 complex doubles, 8 MiB,
+ * held until the process ends), so M is at most 2^18 (N <= 262144 cells);
+ * larger tubes, or a shorter buffer, give GAP_EINVAL.  Every call on one
+ * device shares that workspace: calls that may overlap on one device (two
+ * streams, two handles) race and must be ordered by the caller. */
+int gap_e_spectrum_noalloc(gap_t* g, int32_t tube, double* power, int64_t power_len);
+
 /* Host utility: invert the cumulative classical synchrotron photon-number
  * spectrum with the library's own table (the sampler the device uses):
  * xi[i] = C^-1(r[i]) for r in (0,1).  Host pointers; no device work. */

@@ -132,6 +132,31 @@ float sync_sample_host(float r, const float* tab) {
   return h[i] + f * (h[i + 1] - h[i]);
 }
 
+// ---------------------------------------------------------------- static workspace
+// Workspace of the allocation-free spectrum entry point: the two ping-pong
+// buffers of the largest FFT it accepts (2^18 points, 8 MiB per device, held
+// until the process ends).  In host code the name below is not a device
+// address: the address on each device comes from hipGetSymbolAddress, taken
+// once per device (scratch_on_device) and kept.
+constexpr int kScratchMaxM = 1 << 18;
+static __device__ __align__(256) double2 scratch[2 * kScratchMaxM];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2* g_scratch_dev[kMaxDevices] = {};
+
+// Address of `scratch` on the current device `dev` (nullptr if it cannot be had).
+double2* scratch_on_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_dev[dev] = (double2*)p;
+  }
+  return g_scratch_dev[dev];
+}
+
 // ---------------------------------------------------------------- state
 struct Store {
   Ctl* ctl = nullptr;
@@ -276,6 +301,7 @@ struct gap_t {
   double* E0 = nullptr;   // filtered tubes: reference field; Du: E_u - E0 of the step
   double* Du = nullptr;
   int sticky = 0;
+  double2* scratch = nullptr;   // this device's address of the allocation-free spectrum's workspace
   // graph: replay is valid from the recorded start state and leaves the end state
   WinState win;
   hipGraphExec_t gexec = nullptr;
@@ -1404,6 +1430,14 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return GAP_EDEVICE;
   gap_t* g = new gap_t();
   g->s = (hipStream_t)stream;
+  {
+    // this device's address of the static workspace, taken once per device
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || !(g->scratch = scratch_on_device(dev))) {
+      delete g;
+      return GAP_EDEVICE;
+    }
+  }
   // default priority, like every stream of the library; the events order the two
   // streams on this device only, so they need no system-scope fence
   constexpr unsigned kSyncEvent = hipEventDisableTiming | hipEventDisableSystemFence;
@@ -1956,6 +1990,28 @@ const char* gap_strerror(int code) {
     case GAP_ESTATE: return "call not valid in the current state";
     default: return "unknown error";
   }
+}
+
+int gap_e_spectrum_noalloc(gap_t* g, int32_t tube, double* power, int64_t power_len) {
+  if (!g || tube < 0 || tube >= g->n_tubes || !power) return GAP_EINVAL;
+  const int N = g->P[tube].n_cells;
+  int M = 1;
+  while (M < N) M *= 2;
+  if (M > kScratchMaxM) return GAP_EINVAL;                  // beyond the static workspace
+  if (power_len < (int64_t)M / 2 + 1) return GAP_EINVAL;
+  // the transform of GAP_DIAG_ESPECTRUM, with its ping-pong buffers in the
+  // static workspace (every entry is written before it is read) and the
+  // result in the caller's buffer; nothing is allocated, nothing waits
+  const int grid = std::max(1, std::min(1024, (M + 255) / 256));
+  double2* x = g->scratch;
+  double2* y = g->scratch + M;
+  k_fft_load<<<grid, 256, 0, g->s>>>(g->E + g->th[tube].cell_off, N, M, x);
+  for (int Ns = 1; Ns < M; Ns *= 2) {
+    k_fft_stage<<<grid, 256, 0, g->s>>>(x, y, M, Ns);
+    std::swap(x, y);
+  }
+  k_fft_power<<<grid, 256, 0, g->s>>>(x, M, power);
+  return hipGetLastError() == hipSuccess ? GAP_OK : GAP_EDEVICE;
 }
 
 int gap_sync_inverse_host(const float* r, float* xi, int64_t n) {

@@ -116,6 +116,8 @@ def load_library():
     lib.gap_window_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gap_backward.restype = C.c_int
     lib.gap_backward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.gap_e_spectrum_noalloc.restype = C.c_int
+    lib.gap_e_spectrum_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]
     lib.gap_sync_inverse_host.restype = C.c_int
     lib.gap_sync_inverse_host.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     _lib = lib
@@ -329,6 +331,13 @@ class Gap:
         while M < self.n_cells(tube):
             M *= 2
         return self._diag(DIAG_ESPECTRUM, tube, 8 * (M // 2 + 1)).view(np.float64).copy()
+
+    def e_spectrum_into(self, power, tube=0):
+        """The power spectrum of E into a caller's device tensor (float64,
+        at least M/2 + 1 entries), on the handle's stream, allocating
+        nothing (gap_e_spectrum_noalloc)."""
+        _check(self.lib.gap_e_spectrum_noalloc(self.h, int(tube), C.c_void_p(power.data_ptr()), int(power.numel())),
+               "gap_e_spectrum_noalloc")
 
     def set_launch(self, grid_leptons: int, grid_photons: int, grid_tails: int, resort_every: int):
         """Launch shapes and re-sort interval (the keys autotune() returns)."""

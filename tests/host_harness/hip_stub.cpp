@@ -143,6 +143,28 @@ void __hipRegisterFunction(void**, const void*, char*, const char*, unsigned int
                            int*) {}
 void __hipUnregisterFatBinary(void**) {}
 
+// device variables: each registered host shadow gets a stand-in allocation of
+// its size, which hipGetSymbolAddress returns
+// (constructed on first use: the library's module constructor registers its
+// variables before this file's globals are initialised)
+std::map<const void*, std::pair<void*, size_t>>& vars() {
+  static std::map<const void*, std::pair<void*, size_t>> m;
+  return m;
+}
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) {
+  void* q = aligned_alloc(256, (size + 255) / 256 * 256);
+  memset(q, 0, size);
+  vars()[var] = {q, size};
+}
+hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+  trail("hipGetSymbolAddress(%p)", sym);
+  auto it = vars().find(sym);
+  if (it == vars().end()) fail("hipGetSymbolAddress of an unregistered symbol %p", sym);
+  g_mem[(uintptr_t)it->second.first] = it->second.second;   // device memory from now on, never freed
+  *p = it->second.first;
+  return hipSuccess;
+}
+
 hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t sh, hipStream_t s) {
   if (g_cfg_n == 8) fail("launch configuration stack overflow");
   g_cfg[g_cfg_n++] = LaunchCfg{g, b, sh, s};
@@ -398,7 +420,9 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
 
 // summary for the driver
 void hipstub_report(long long* out) {
-  out[0] = (long long)g_mem.size();
+  long long statics = 0;
+  for (auto& v : vars()) statics += g_mem.count((uintptr_t)v.second.first);
+  out[0] = (long long)g_mem.size() - statics;
   out[1] = (long long)g_streams.size();
   out[2] = (long long)g_events.size();
   out[3] = (long long)g_graphs.size();

@@ -223,6 +223,20 @@ void single_tube() {
   if (e == 0) expect(gap_window_backward(g, da, dn), "backward");
   e = gap_backward(g, 12, 5, loss, da, dn);
   if (e != 0 && e != GAP_ESTATE) expect(e, "backward in one call");
+  // the allocation-free spectrum: into a caller's buffer, twice (then a
+  // smaller request), and its refusals
+  {
+    void* pw = nullptr;
+    hipMalloc(&pw, sizeof(double) * 257);
+    expect(gap_e_spectrum_noalloc(g, 0, (double*)pw, 257), "noalloc spectrum");
+    expect(gap_e_spectrum_noalloc(g, 0, (double*)pw, 200), "noalloc spectrum (short)", GAP_EINVAL);
+    if (gap_e_spectrum_noalloc(g, 0, (double*)pw, 256) != GAP_EINVAL || gap_e_spectrum_noalloc(g, 0, nullptr, 257) != GAP_EINVAL) {
+      fprintf(stderr, "REPLAY: bad spectrum buffer accepted\n");
+      g_fail = 1;
+    }
+    gap_sync(g);
+    hipFree(pw);
+  }
   // the error hook (no kernel runs here, so the word itself stays clear)
   int32_t bits = 2;
   expect(gap_set_state(g, GAP_STATE_RAISE, 0, &bits, 4), "raise");
