@@ -152,7 +152,7 @@ int gap_sync(gap_t* g);
 #define GAP_DIAG_DERIVED  7  /* double[8]: d_cm, lambda~, R~, dt, H, w0, s_co, N            */
 #define GAP_DIAG_TIMING   8  /* double[16]: (launches, summed ms) of the lepton pass, photon
                                 pass, field, re-sort, prologue, tail passes of both
-                                species (one launch), an unused pair (always 0) and
+                                species (one launch), the merge check (and merge, when due) and
                                 conversion draws since timing was enabled or last read
                                 (tube ignored; resets the record)                           */
 /* Discharge diagnostics (Sect. 5: Fig. 3 rows 5-7, Fig. 5, Fig. 7).  Bins are
@@ -187,6 +187,9 @@ int gap_sync(gap_t* g);
                                   and signed momentum column: 90 + b for p > 0 and 89 - b
                                   for p <= 0 (p = u, photons x), b the spectrum bin of |p|;
                                   the first call for a bin width allocates device memory  */
+#define GAP_DIAG_LAUNCH  16    /* int32[4]: the handle's launch shape, as GAP_STATE_LAUNCH sets it
+                                  (workgroups of the sorted lepton pass, of the sorted photon
+                                  pass and of the tail passes, re-sort interval; tube ignored) */
 #define GAP_DIAG_ESPECTRUM 13  /* double[M/2 + 1], M the next power of two >= N: the power
                                   spectrum of E along the gap, P_k = |sum_j E_j
                                   exp(-2 pi i j k / M)|^2 / M with E zero-padded to M cells

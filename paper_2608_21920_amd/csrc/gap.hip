@@ -453,7 +453,7 @@ hipEvent_t next_event(gap_t* g) {
 }
 
 // kernel ids of the timing diagnostic
-enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_TAILS = 5, KT_UNUSED = 6,
+enum { KT_LEPTONS = 0, KT_PHOTONS = 1, KT_FIELD = 2, KT_RESORT = 3, KT_PRE = 4, KT_TAILS = 5, KT_MERGE = 6,
        KT_CONV = 7, KT_N = 8 };
 
 struct Timer {
@@ -532,9 +532,15 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst) {
   st.cur ^= 1;
 }
 
+__global__ void k_count_resort(Tube* tubes, int n_tubes) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tubes) tubes[t].cnt[C_REBUCKETS] += 1;
+}
+
 void rebucket_all(gap_t* g) {
   rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1));
   rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1));
+  k_count_resort<<<(g->n_tubes + 255) / 256, 256, 0, g->s>>>(g->tubes, g->n_tubes);
 }
 
 // With `done`, the single-pass kernel's own completion is recorded into that
@@ -913,6 +919,7 @@ void enqueue_step(gap_t* g, bool more) {
   const bool merge = g->merge_on && g->host_step % g->merge_every == 0;
   if (merge) {
     if (two) join_photon_side(g);
+    Timer t(g, KT_MERGE);
     merge_all(g);
   }
   Ctx cx = make_ctx(g);
@@ -1681,6 +1688,12 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       }
       g->ev_marks.clear();
       g->ev_used = 0;
+      return GAP_OK;
+    }
+    case GAP_DIAG_LAUNCH: {
+      if (!fits(sizeof(int32_t) * 4)) return GAP_EINVAL;
+      const int32_t v[4] = {g->grid_lep, g->grid_pho, g->grid_tail, g->R};
+      std::memcpy(host_buf, v, sizeof(v));
       return GAP_OK;
     }
     case GAP_DIAG_DERIVED: {

@@ -25,13 +25,13 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
- DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE) = range(16)
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE, DIAG_LAUNCH) = range(17)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
  STATE_PROFILE_BIN, STATE_WATERFALL, STATE_RAISE) = range(10)
 # discharge diagnostics: profile groups and the return spectrum's bins
 PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
 RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
-TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "tails", "unused", "conversions"]
+TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "tails", "merge", "conversions"]
 
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
               "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
@@ -343,6 +343,11 @@ class Gap:
         """Launch shapes and re-sort interval (the keys autotune() returns)."""
         buf = np.array([grid_leptons, grid_photons, grid_tails, resort_every], np.int32)
         _check(self.lib.gap_set_state(self.h, STATE_LAUNCH, 0, buf.ctypes.data, buf.nbytes), "set_launch")
+
+    def launch(self) -> dict:
+        """The launch shape and re-sort interval in use."""
+        v = self._diag(DIAG_LAUNCH, 0, 16).view(np.int32)
+        return dict(grid_leptons=int(v[0]), grid_photons=int(v[1]), grid_tails=int(v[2]), resort_every=int(v[3]))
 
     def autotune(self, trial_steps: int = 32) -> dict:
         """Tune the launch shapes and the re-sort interval on real steps

@@ -78,3 +78,12 @@ def batched_tubes(n_tubes: int = 256, seed: int = 1) -> list[dict]:
                         seed=int(seed) * 100003 + t, steps=20000,
                         cap_leptons=max(4 * 2 * ppc * n, 1 << 16), cap_photons=max(2 * ppc * n, 1 << 16)))
     return out
+
+
+def batched_qed_active(tubes: list[dict]) -> list[dict]:
+    """The batched tubes with the QED rescaled so that each tube's emission,
+    photon transport and pair creation run within a few hundred steps
+    (lambda~ x 3e4, R~ x 3e-4: lambda~/R~ = 1e8 times the physical value),
+    with the photon store as large as the lepton store and merging on to keep
+    both under their caps."""
+    return [dict(c, lambda_c_scale=3e4, r_curv_scale=3e-4, cap_photons=c["cap_leptons"], merge=True) for c in tubes]

@@ -161,3 +161,58 @@ def test_window_argument_checks(torch_gpu):
     with pytest.raises(G.GapError):
         p.window_forward(10, 5)
     p.close()
+
+
+def test_adjoint_workload_matches_oracle_adjoint(torch_gpu):
+    """The adjoint at the differentiable window's own size (16384 cells,
+    4.0e6 leptons, its QED preset, injection on) over a short window from the
+    seeded initial state: GPU loss and gradients against the FP64 oracle
+    adjoint of the same realisation (W = 20, K = 10)."""
+    cfg = dict(workloads.ADJOINT)
+    W, K = 20, 10
+    _say("case: adjoint workload vs oracle adjoint, W=%d K=%d" % (W, K))
+    g = _gpu(cfg)
+    loss = g.window_forward(W, K)[0]
+    da, dn = g.backward()
+    c = g.counts()
+    g.close()
+    win = A.Window(cfg, W, None)
+    ad = A.adjoint(win)
+    ev = win.events
+    _say("  leptons %d; oracle events: emit %d conv %d births %d; loss gpu %.9e orc %.9e; dalpha %.6e / %.6e; "
+         "dninj %.6e / %.6e" % (c["n_lep"], (ev["kind"] == 0).sum(), (ev["kind"] == 1).sum(), (ev["kind"] == 2).sum(),
+                                loss, ad["loss"], da[0], ad["dL_dalpha"], dn[0], ad["dL_dninj"]))
+    assert (ev["kind"] == 0).sum() > 500
+    assert _rel(loss, ad["loss"]) < 1e-6
+    assert _rel(da[0], ad["dL_dalpha"]) < 1e-3
+    assert _rel(dn[0], ad["dL_dninj"]) < 1e-3
+
+
+def test_adjoint_workload_full_window_matches_gpu_finite_differences(torch_gpu):
+    """The full window of the differentiable workload (16384 cells, 4.0e6
+    leptons, W = 2000, K = 100), QED off so that the map is smooth: the
+    GPU adjoint against GPU central differences (h = 1e-4 in alpha; in n_inj
+    the injected weight steps on the 2^-24 grid of the fixed-point charge)."""
+    cfg = dict(workloads.ADJOINT, flags=G.QED_OFF)
+    W, K = 2000, 100
+    _say("case: adjoint workload, full window vs GPU finite differences, QED off")
+    g = _gpu(cfg)
+    g.window_forward(W, K)
+    da, dn = g.backward()
+    g.close()
+
+    def loss(alpha, w):
+        h = _gpu(cfg)
+        h.set_drive(alpha, w)
+        v = h.window_forward(W, K)[0]
+        h.close()
+        return v
+
+    a0, w0, rate = cfg["alpha"], cfg.get("inj_weight", 1.0), cfg["inj_rate"]
+    h = 1e-4
+    fa = (loss(a0 + h, w0) - loss(a0 - h, w0)) / (2 * h)
+    dw = max(1.0, round(h / rate * 16777216.0)) / 16777216.0
+    fn = (loss(a0, w0 + dw) - loss(a0, w0 - dw)) / (2 * dw * rate)
+    _say("  dL/dalpha adjoint %.6e fd %.6e; dL/dninj adjoint %.6e fd %.6e" % (da[0], fa, dn[0], fn))
+    assert _rel(da[0], fa) < 1e-3
+    assert _rel(dn[0], fn) < 1e-3

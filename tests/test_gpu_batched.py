@@ -142,3 +142,51 @@ def test_launch_shape_sweep_recaptures_equal_single_tubes(torch_gpu):
             _same(gb, t, g1, 0)
             g1.close()
         gb.close()
+
+
+def _qed_active(cfg):
+    """A tube of the batched recipe at its own size, with the tiny gap's QED
+    rescale so that emission, transport and conversion all run within 100
+    steps."""
+    return dict(cfg, lambda_c_scale=workloads.TINY["lambda_c_scale"], r_curv_scale=workloads.TINY["r_curv_scale"])
+
+
+def test_batched_tubes_match_the_oracle(torch_gpu):
+    """Tubes of the 256-tube recipe, at full size, stepped together in one
+    handle (concatenated launches), against the FP64 oracle run of each tube
+    alone: the field within 1e-5 of max|E| at every one of 100 steps, the
+    Monte Carlo counts equal up to FP32/FP64 near-ties, and the photons by
+    id.  QED-active: 1e4-1e5 emissions and 1e3 conversions per tube."""
+    from oracle.oracle import Oracle
+    from gpu_util import gpu_photons_as_oracle, rel_field_err
+    recipe = workloads.batched_tubes(256, seed=1)
+    pick = (76, 3, 109)                 # the three smallest of the recipe
+    cfgs = [_qed_active(recipe[i]) for i in pick]
+    _say("case: batched tubes %s vs the oracle, 100 steps" % (pick,))
+    g = Gap(cfgs)
+    orcs = [Oracle(c) for c in cfgs]
+    worst = [0.0] * len(cfgs)
+    for n in range(100):
+        g.step(1)
+        for t, o in enumerate(orcs):
+            o.step(1)
+            err = rel_field_err(g.field(t), o.field())
+            worst[t] = max(worst[t], err)
+            assert err <= 1e-5, (pick[t], n, err)
+    for t, o in enumerate(orcs):
+        cg, co = g.counts(t), o.counts()
+        _say("  tube %d: worst field err %.2e; emit %d/%d born %d/%d conv %d/%d leptons %d/%d" % (
+            pick[t], worst[t], cg["n_emit"], co["n_emit"], cg["n_pho_born"], co["n_pho_born"], cg["n_conv"],
+            co["n_conv"], cg["n_lep"], co["n_lep"]))
+        assert cg["err"] == 0
+        assert co["n_emit"] > 10000 and co["n_conv"] > 500
+        for k in ("n_emit", "n_pho_born", "n_conv"):
+            assert abs(cg[k] - co[k]) <= max(2, 1e-3 * co[k]), (pick[t], k)
+        assert abs(cg["n_lep"] - co["n_lep"]) <= max(4, 2e-3 * co["n_lep"])
+        assert abs(g.es(t) - o.Es) <= 1e-9 * max(1.0, abs(o.Es))
+        P, Q = by_id(gpu_photons_as_oracle(g.photons(t))), by_id(o.photons())
+        common, ia, ib = np.intersect1d(P["id"], Q["id"], return_indices=True)
+        assert common.size >= 0.998 * max(P["id"].size, Q["id"].size)
+        assert np.all(P["n0"][ia] == Q["n0"][ib])
+        assert np.allclose(P["x"][ia], Q["x"][ib], rtol=2e-4, atol=0)
+    g.close()
