@@ -25,6 +25,12 @@ struct AdjTube {            // per tube (device)
   double lamEs;             // adjoint of the surface field
   double dalpha;            // dL/dalpha
   double dinjw;             // dL/d(weight of one injected electron)
+  // w0 sum_k lamE_k summed over the reverse steps taken so far: the part of
+  // every live lepton's weight adjoint that does not depend on its cell.
+  // The slots hold their weight adjoints less this sum (FP32 then keeps the
+  // small cell-dependent rest, and an injected electron's -lam_w + lamEs w0,
+  // a near cancellation of two large sums, is formed in FP64).
+  double cw;
   double w0, s_co, dt, cfl, lossw;   // lossw = 2 / (window steps * N)
   int32_t N, cell_off, node_off, pad;
 };
@@ -165,6 +171,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_field(const double* lamE, d
   if (threadIdx.x == 0) {
     suf[a.node_off + N] = 0.0;
     a.lamEs += total;
+    a.cw += a.w0 * total;
     a.dalpha += a.lamEs * a.s_co * a.dt;
   }
 }
@@ -192,7 +199,8 @@ __device__ __forceinline__ void adj_one(const AdjCtx& c, long long slot, int til
     const double xi1 = (double)(p1 & 0xFFFFFFu) * 5.9604644775390625e-8;
     const double e = c.lamE[a.cell_off + cell1];
     lxi += (float)(-w0 * (double)w * e);
-    lw += (float)(w0 * ((1.0 - xi1) * e + c.suf[a.node_off + cell1 + 1]));
+    // w0 ((1 - xi) lamE_k + sum_{m>k} lamE_m), less the common w0 sum_m lamE_m
+    lw += (float)(w0 * ((1.0 - xi1) * e + (c.suf[a.node_off + cell1 + 1] - c.suf[a.node_off])));
     const float u1 = c.u1[slot];
     const float g = sqrtf(1.0f + u1 * u1);
     lu += lxi * cfl / (g * g * g);
@@ -201,7 +209,7 @@ __device__ __forceinline__ void adj_one(const AdjCtx& c, long long slot, int til
     // or out of the top of the box
     lxi = 0.0f;
     lu = 0.0f;
-    if (cell0 < a.N / 2) lw += (float)(a.lamEs * w0);
+    lw = (float)((cell0 < a.N / 2 ? a.lamEs * w0 : 0.0) - a.cw);
   }
   const float e0 = c.eb0[a.node_off + cell0], e1 = c.eb0[a.node_off + cell0 + 1];
   const float lEp = sg * dt * lu;
@@ -217,7 +225,7 @@ __device__ __forceinline__ void adj_one(const AdjCtx& c, long long slot, int til
   if (slot >= inj0 && slot < inj1) {
     // injected at the start of step j with weight -inj_w; its injection also
     // raised E_s by inj_w w0
-    atomicAdd(&a.dinjw, -(double)lw + a.lamEs * w0);
+    atomicAdd(&a.dinjw, -(double)lw + (a.lamEs * w0 - a.cw));
     lxi = 0.0f;
     lu = 0.0f;
     lw = 0.0f;

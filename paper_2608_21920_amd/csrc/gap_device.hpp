@@ -111,8 +111,7 @@ struct PhoBuf { uint32_t* pos; float* x; float* w; int32_t* n0; uint64_t* id; };
 struct u4 { uint32_t a, b, c, d; };
 
 // Two equivalent forms of the same rounds: WIDE takes each product with one
-// 32x32 -> 64 multiply, otherwise with separate low and high multiplies (the
-// lepton pass keeps the latter: it needs fewer registers there).
+// 32x32 -> 64 multiply, otherwise with separate low and high multiplies.
 template <bool WIDE = false>
 __device__ __forceinline__ u4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -148,6 +147,10 @@ enum : uint32_t { T_INIT = 1, T_EMIT = 2, T_CONV = 3, T_INJ = 4, T_MERGE = 5, T_
 __device__ __forceinline__ bool bern(uint32_t r, float p) {
   return (double)(2u * (r >> 8) + 1u) < (double)p * 33554432.0;
 }
+// The same decision in integers: 2k + 1 < P (P = p 2^25, exact in FP32) holds
+// iff 2k + 1 < ceil(P), and 2k + 1 = (r >> 7) | 1.
+__device__ __forceinline__ uint32_t bern_thr(float p) { return (uint32_t)ceilf(p * 33554432.0f); }
+__device__ __forceinline__ bool bern_t(uint32_t r, uint32_t thr) { return ((r >> 7) | 1u) < thr; }
 __device__ __forceinline__ float unif(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 5.9604645e-8f; }
 
 __device__ __forceinline__ uint64_t child_id(uint64_t seed, uint64_t parent, int64_t step, uint32_t j) {
@@ -160,8 +163,8 @@ __device__ __forceinline__ uint64_t child_id(uint64_t seed, uint64_t parent, int
 // 5/(2 sqrt 3) (1 + 16 sqrt3/5 chi + 1.1 chi^2)^(-1/6), via the hardware
 // base-2 logarithm and exponential
 __device__ __forceinline__ float t_syn(float chi) {
-  const float v = 1.0f + 5.5425625842204074f * chi + 1.1f * chi * chi;
-  return 1.4433756729740644f * __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * (-1.0f / 6.0f));
+  const float v = __fmaf_rn(__fmul_rn(1.1f, chi), chi, __fmaf_rn(5.5425625842204074f, chi, 1.0f));
+  return __fmul_rn(1.4433756729740644f, __builtin_amdgcn_exp2f(__fmul_rn(__builtin_amdgcn_logf(v), -1.0f / 6.0f)));
 }
 // pair-creation function of Sect. 3.2 (fit quoted with eq. tau_bw):
 // 0.23 exp(-8/(3 chi)) (1 + 0.22 chi)^(-1/3)
