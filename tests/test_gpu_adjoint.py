@@ -82,11 +82,24 @@ def test_adjoint_matches_gpu_finite_differences(torch_gpu):
         return v
     ha = 1e-3
     fa = (loss(1.5 + ha, 1.0) - loss(1.5 - ha, 1.0)) / (2 * ha)
-    hw = 2.0 ** -10                      # on the 2^-24 grid of the fixed-point charge
+    # the injected weight on the 2^-24 grid of the fixed-point charge.  The
+    # map is only piecewise smooth in it (whether an injected electron is
+    # absorbed again, or crosses a cell, changes discretely), so central
+    # differences wander with the step: the FP64 oracle's own differences
+    # give 0.011849, 0.011825 and 0.01154 at steps 2e-4, 2^-10 and 2^-7
+    # against its adjoint's 0.011844.  The bar for them is 5e-3; the exact
+    # reference is the oracle adjoint below.
+    hw = 2.0 ** -10
     fn = (loss(1.5, 1.0 + hw) - loss(1.5, 1.0 - hw)) / (2 * hw * 0.5)
-    _say("  dalpha adj %.6e fd %.6e; dninj adj %.6e fd %.6e" % (da[0], fa, dn[0], fn))
+    # QED off: the map has no random events, so the FP64 oracle adjoint of
+    # the same window is the exact reference for both
+    ad = A.adjoint(A.Window(dict(cfg, flags=OF["QED_OFF"]), W, None))
+    _say("  dalpha adj %.6e fd %.6e orc %.6e; dninj adj %.6e fd %.6e orc %.6e" % (
+        da[0], fa, ad["dL_dalpha"], dn[0], fn, ad["dL_dninj"]))
     assert _rel(da[0], fa) < 1e-3
-    assert _rel(dn[0], fn) < 1e-3
+    assert _rel(dn[0], fn) < 5e-3
+    assert _rel(da[0], ad["dL_dalpha"]) < 1e-5
+    assert _rel(dn[0], ad["dL_dninj"]) < 1e-5
 
 
 def test_checkpoint_interval_and_restored_state(torch_gpu):
@@ -215,4 +228,5 @@ def test_adjoint_workload_full_window_matches_gpu_finite_differences(torch_gpu):
     fn = (loss(a0, w0 + dw) - loss(a0, w0 - dw)) / (2 * dw * rate)
     _say("  dL/dalpha adjoint %.6e fd %.6e; dL/dninj adjoint %.6e fd %.6e" % (da[0], fa, dn[0], fn))
     assert _rel(da[0], fa) < 1e-3
-    assert _rel(dn[0], fn) < 1e-3
+    # piecewise smooth in the injected weight (see the small window's test)
+    assert _rel(dn[0], fn) < 5e-3
