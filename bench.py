@@ -610,7 +610,8 @@ def main():
     import torch
     from paper_2608_21920_amd import Gap, workloads
     cfg = dict(workloads.PRODUCTION)
-    g = Gap(cfg)
+    # graph capture needs a stream other than the legacy default one
+    g = Gap(cfg, stream=torch.cuda.Stream() if a.graph else None)
     region = ProfilerRegion()
     res = measure_gap(g, torch, cfg, a.steps, a.warmup, a.grow_to, a.max_grow_steps, graph=a.graph, region=region,
                       kernels=not a.graph)
@@ -668,7 +669,8 @@ def main():
             torch, res["value"], workloads.batched_qed_active(recipe), ignite_steps=400, launch=phys["autotune"],
             label="256 tubes: cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q log-uniform in "
                   "[0.01, 0.3], ppc uniform in [4, 64] per species, seed 1; uniform e+- start, QED rescaled "
-                  "(lambda~ x 3e4, R~ x 3e-4) so that emission, photon transport and conversion run, merging on; "
+                  "(lambda~ x 3e4, R~ x 3e-4) so that emission, photon transport and conversion run, merging every 16 "
+                  "steps above half the cap; "
                   "timed after 400 steps, past ignition, with the physical run's tuned launch shape")
         out["batched_physical_qed"] = phys
         torch.cuda.empty_cache()

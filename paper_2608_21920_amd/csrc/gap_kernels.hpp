@@ -191,14 +191,6 @@ __device__ __forceinline__ long long reserve_tail(Ctl* c, const Room& rm, int n,
   return first;
 }
 
-// First chunk of the range of workgroup `bx` of a grid of G over nsc chunks
-// (XCD-aware: consecutive ranges go to workgroups of the same XCD).
-__device__ __forceinline__ void chunk_range(long long nsc, int G, int bx, long long* c0, long long* c1) {
-  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
-  *c0 = nsc * r / G;
-  *c1 = nsc * (r + 1) / G;
-}
-
 // ------------------------------------------------------------------ prologue
 // Surface injection (cold electrons in cell 0 at a deterministic rate) and
 // the snapshots of the tails that this step's passes will process.
@@ -367,329 +359,179 @@ __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), 
   return r;
 }
 
-// ---- The arithmetic of one lepton step, shared by the sorted and the tail
-// passes.  The FP32 operations carry explicit roundings, so that a lepton's
-// step is bitwise the same in either pass whatever the compiler contracts.
-
-// Kick with the node field at the particle (first-order shape):
-// u + q E_p dt, E_p = (1 - xi) Ebar_k + xi Ebar_{k+1}, xi = frac 2^-24.
-__device__ __forceinline__ float lep_kick(float u, float sg, uint32_t frac, float e0, float e1, float dt) {
-  const float xi = (float)frac * 5.9604645e-8f;        // exact
-  const float ep = __fmaf_rn(xi, e1, __fmul_rn(1.0f - xi, e0));
-  return __fmaf_rn(dt, __fmul_rn(sg, ep), u);
-}
-
-// gamma, chi = gamma^2 lambda~/R~ and the curvature photon energy scale
-// x_c = 1.5 gamma chi (Sect. 3.1, eq. x_curv)
-struct LepQ { float g, chi, xc; };
-__device__ __forceinline__ LepQ lep_q(float u, float lr) {
-  LepQ q;
-  q.g = __builtin_amdgcn_sqrtf(__fmaf_rn(u, u, 1.0f));
-  q.chi = __fmul_rn(__fmul_rn(q.g, q.g), lr);
-  q.xc = __fmul_rn(__fmul_rn(1.5f, q.g), q.chi);
-  return q;
-}
-
-// Sub-steps and the draw threshold of one emission evaluation: the optical
-// depth of the step is alpha_em gamma/R~ T_syn(chi) dt (Sect. 3.1, eq.
-// tau_syn), split into n_sub = ceil(10 dtau) <= nsub_max draws of
-// probability 1 - exp(-dtau / n_sub) each.
-__device__ __forceinline__ void lep_emit_setup(const LepQ& q, float emit_k, int nsub_max, int* nsub, uint32_t* thr) {
-  const float dtau = __fmul_rn(__fmul_rn(emit_k, q.g), t_syn(q.chi));
-  int n = (int)ceilf(__fmul_rn(dtau, 10.0f));
-  n = max(1, min(n, nsub_max));
-  float x = dtau;
-  if (__ballot(n > 1)) {
-    if (n > 1) x = __fdiv_rn(dtau, (float)n);
-  }
-  *nsub = n;
-  *thr = bern_thr(one_minus_exp_neg(x));
-}
-
-// Drift dh/dt = u/gamma in fixed point: the displacement in 2^-24 cells.
-__device__ __forceinline__ int lep_dfix(float u, float cfl24) {
-  return __float2int_rn(__fmul_rn(__fmul_rn(u, __builtin_amdgcn_rsqf(__fmaf_rn(u, u, 1.0f))), cfl24));
-}
-
-// Fixed-point charge T = round(|w| 2^24) (half even) and its CIC split at the
-// fraction nfrac: A = round(T nfrac 2^-24) (half up) on the upper node,
-// T - A on the lower one (exact integers).
-__device__ __forceinline__ int64_t lep_T(float w) { return __float2ll_rn(fabsf(w) * 16777216.0f); }
-__device__ __forceinline__ int64_t lep_A(int64_t T, uint32_t nfrac) {
-  return (int64_t)(((unsigned long long)T * nfrac + (1ull << 23)) >> FRAC);
-}
-
-// ---- Photon births of one lepton (rare): the emitted photons of this step
-// that are tracked (x >= x_thr) are stored at the emitter's post-drift
-// position, with birth step n0 = n + 1; their energies are drawn again from
-// the same Philox words as in the evaluation.
-__device__ __forceinline__ void lep_births(const Ctx& cx, const KC& k, int nst, uint64_t id, uint64_t evmask,
-                                           float upk, float xc, float w, uint32_t np, LocalCounts& lcn) {
-  const Room proom = load_room(cx.pc);
-  const int tile = k.tile;
-  int dropped = 0;
-  const long long first = reserve_tail(cx.pc, proom, nst, &dropped);
-  const long long lim = proom.L;
-  if (nst > 0) {
-    float au = fabsf(upk);
-    const float dir = upk >= 0.0f ? 1.0f : -1.0f;
-    const float aw = fabsf(w);
-    long long q = first;
-    uint64_t m = evmask;
-    while (m) {
-      const int j = __ffsll((long long)m) - 1;
-      m &= m - 1;
-      u4 r = draw<true>(k.seed, id, k.step, T_EMIT, (uint32_t)j);
-      float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
-      au -= x;
-      if (x >= k.x_thr || (k.flags & F_TRACK_ALL)) {
-        if (q < lim) {
-          const uint32_t kk = (uint32_t)q;
-          cx.P.pos[kk] = np;
-          cx.P.x[kk] = dir * x;
-          cx.P.w[kk] = aw;
-          cx.P.n0[kk] = (int32_t)(k.step + 1);
-          cx.P.id[kk] = child_id(k.seed, id, k.step, 2u + (uint32_t)j);
-          cx.ptt[kk] = tile;
-        }
-        ++q;
-      }
-    }
-  }
-  if (dropped) atomicOr(cx.err, E_CAP);
-  lcn.v[3] += nst - dropped;
-  lcn.v[4] += dropped;
-}
-
-// ---- Emission evaluation of one lepton (Monte Carlo with recoil): n_sub
-// Bernoulli draws keyed by (id, step, sub-step); each event takes x = xi_s
-// x_c (xi_s from the classical spectrum), clamped to |u|, off |u|.  Returns
-// the momentum after recoil; evmask marks the sub-steps that fired.
-__device__ __forceinline__ float lep_emit(const Ctx& cx, const KC& k, const LepQ& q, uint64_t id, float u,
-                                          uint64_t* evmask, int* ncand, int* nev) {
-  int nsub;
-  uint32_t thr;
-  lep_emit_setup(q, k.emit_k, k.nsub_max, &nsub, &thr);
-  float au = fabsf(u);
-  uint64_t em = 0;
-  int nc = 0, ne = 0;
-  for (int j = 0; j < nsub; ++j) {
-    const u4 r = draw<true>(k.seed, id, k.step, T_EMIT, (uint32_t)j);
-    if (bern_t(r.a, thr)) {
-      const float x = fminf(sync_sample(unif(r.b), cx.tab) * q.xc, au);
-      au -= x;
-      em |= 1ull << j;
-      ++ne;
-      if (x >= k.x_thr || (k.flags & F_TRACK_ALL)) ++nc;
-    }
-  }
-  *evmask = em;
-  *ncand = nc;
-  *nev = ne;
-  return (k.flags & F_RECOIL_OFF) ? u : copysignf(au, u);
-}
-
-// Tile constants of the sorted lepton pass (held in scalar registers): a
-// non-periodic tube's tile-local position p (8 bits of cell offset from the
-// window base, 24 of fraction) lies in the QED zone h < H when zall or
-// p < zl; a cell offset below off_lo is below the surface (absorbed), one at
-// or above off_hi is above the top of the box (outflow).
-struct LT { uint32_t zl; int off_lo, off_hi; bool zall, per, qed; };
-
-
-__device__ __forceinline__ LT lepton_tile(const KC& k) {
-  LT t;
-  const int64_t zlim = k.hfix - ((int64_t)k.base << FRAC);
-  t.zall = zlim > (int64_t)0xFFFFFFFFll;
-  t.zl = zlim <= 0 ? 0u : (t.zall ? 0xFFFFFFFFu : (uint32_t)zlim);
-  t.off_lo = -k.base;
-  t.off_hi = k.N - k.base;
-  t.per = (k.flags & F_PERIODIC) != 0;
-  t.qed = !(k.flags & (F_QED_OFF | F_EMIT_OFF));
-  return t;
-}
-
-// Wave-level event counts of the sorted pass (scalar registers).
-struct WaveCounts { int alive, eval, absorbed, outflow; };
-
-// One lepton of a sorted chunk: gather (LDS window), kick, emission, drift,
-// boundaries, deposit (LDS window), photon births.  Rare branches are taken
-// only by waves with a lane that needs them; periodic tubes (a uniform flag)
-// wrap the cell of the zone tests and count the current for their mean field.
-__device__ __forceinline__ void lepton_sorted(const Ctx& cx, uint32_t slot, const KC& k, const LT& t, long long* s_rho,
-                                              const float* s_eb, LocalCounts& lcn, WaveCounts& wc, float w, uint32_t pos,
-                                              float u) {
-  const bool alive = w != 0.0f;
-  const bool neg = w < 0.0f;
-  const float sg = neg ? -1.0f : 1.0f;
-  const int off = alive ? (int)(pos >> FRAC) : 0;
-  const uint32_t frac = pos & 0xFFFFFFu;
-  const float e0 = s_eb[off], e1 = s_eb[off + 1];     // (an empty slot reads the window's first pair)
-  u = lep_kick(u, sg, frac, alive ? e0 : 0.0f, alive ? e1 : 0.0f, k.dt);
-
-  // emission, in the QED zone above the x_c floor
-  bool in_zone;
-  if (t.per) {
-    const int cg = wrap_cell(k.base + off, k.N);
-    in_zone = ((int64_t)cg << FRAC) + frac < k.hfix;
+// One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
+// boundaries, deposit, photon births.  UNI: the lane's tile is the
+// wave-uniform tile of a sorted chunk (tube constants come through scalar
+// loads, gather and deposit go through the LDS window); otherwise the lane's
+// own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
+template <bool UNI>
+__device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
+                           LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out,
+                           const Room& proom) {
+  bool alive;
+  KC k;
+  if (UNI) {
+    k = ku;
+    alive = w != 0.0f;
   } else {
-    in_zone = t.zall || pos < t.zl;
+    alive = tile >= 0 && w != 0.0f;
+    k = lane_kc(cx, alive ? tile : 0, false);   // tile 0 always exists; no branch on the struct
   }
-  const LepQ q = lep_q(u, k.lr);
-  const bool eval = alive && t.qed && in_zone && q.xc >= k.xc_floor;
-  uint64_t evmask = 0, id = 0;
-  int ncand = 0;
-  const float upk = u;
-  if (__ballot(eval)) {
-    if (eval) {
-      int nev;
-      id = cx.L.id[slot];
-      u = lep_emit(cx, k, q, id, u, &evmask, &ncand, &nev);
-      lcn.v[2] += nev;
-    }
-  }
-
-  // drift; a crossing of the 256-cell window is the 32-bit add wrapping
-  const int dfix = lep_dfix(u, k.cfl24);
-  const uint32_t np = pos + (uint32_t)dfix;
-  const bool oob = alive && (dfix >= 0 ? np < pos : np > pos);
-  const int noff = (int)(np >> FRAC);
-  const bool absorbed = alive && !oob && !t.per && noff < t.off_lo;
-  const bool outflow = alive && !oob && !t.per && noff >= t.off_hi;
-  const bool dead = oob || absorbed || outflow;
-  const bool live = alive && !dead;
-  const float ts = fabsf(w) * 16777216.0f;            // |w| 2^24, exact
-  if (__ballot(dead)) {
-    if (dead) cx.L.w[slot] = 0.0f;
-    if (oob) atomicOr(cx.err, E_TILE);
-    if (absorbed) {
-      const int64_t Tw = lep_T(w);
-      atomic_add_i64(&cx.tubes[k.tube].dq, neg ? -Tw : Tw);
-      return_add(cx.ret, cx.ret_thr, k.tube, u, w);
-    }
-  }
-
-  if (t.per) {
-    if (live) atomic_add_i64(&cx.tubes[k.tube].dcur, (neg ? -lep_T(w) : lep_T(w)) * (int64_t)dfix);
-  }
-
-  // deposit at the new position: node noff gets s (T - A), node noff + 1
-  // gets s A (LDS window; exact integers)
-  const uint32_t nfrac = np & 0xFFFFFFu;
-  if (!__ballot(ts >= 2147483648.0f)) {
-    // T < 2^31: the split in 32-bit integers
-    const uint32_t T = (uint32_t)__float2int_rn(ts);
-    const uint32_t A = (uint32_t)(((unsigned long long)T * nfrac + (1ull << 23)) >> FRAC);
-    const int32_t a = neg ? -(int32_t)A : (int32_t)A;
-    const int32_t ta = neg ? -(int32_t)(T - A) : (int32_t)(T - A);
-    if (live) {
-      atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)(long long)ta);
-      atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)(long long)a);
-    }
-  } else if (live) {
-    const int64_t T = lep_T(w);
-    const int64_t A = lep_A(T, nfrac);
-    atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)(neg ? A - T : T - A));
-    atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)(neg ? -A : A));
-  }
-
-  // photon births at the post-drift position, inside the QED zone
-  bool keep;
-  if (t.per) {
-    const int ncg = wrap_cell(k.base + noff, k.N);
-    keep = live && ((int64_t)ncg << FRAC) + nfrac < k.hfix;
-  } else {
-    keep = live && (t.zall || np < t.zl);
-  }
-  const int nst = keep ? ncand : 0;
-  if (__ballot(nst > 0)) lep_births(cx, k, nst, id, evmask, upk, q.xc, w, np, lcn);
-
-  if (live) {
-    cx.L.pos[slot] = np;
-    cx.L.u[slot] = u;
-  }
-  wc.alive += __popcll(__ballot(alive));
-  wc.eval += __popcll(__ballot(eval));
-  wc.absorbed += __popcll(__ballot(absorbed));
-  wc.outflow += __popcll(__ballot(outflow));
-}
-
-// One lepton of the tail (its own tile; global gather and deposit), the same
-// arithmetic as lepton_sorted.  `tile` < 0: no particle in this lane.
-__device__ void lepton_tail_one(const Ctx& cx, uint32_t slot, int tile, LocalCounts& lcn, float w, uint32_t pos,
-                                float u) {
-  const bool alive = tile >= 0 && w != 0.0f;
-  const KC k = lane_kc(cx, alive ? tile : 0, false);   // tile 0 always exists; no branch on the struct
   if (!alive) { pos = 0; u = 0.0f; }
   const int tube = alive ? k.tube : -1;
   const int N = k.N;
-  const bool per = (k.flags & F_PERIODIC) != 0;
-  const bool neg = w < 0.0f;
-  const float sg = neg ? -1.0f : 1.0f;
-  const int off = (int)(pos >> FRAC);
-  const uint32_t frac = pos & 0xFFFFFFu;
-  const int cg = per ? wrap_cell(k.base + off, N) : k.base + off;
-  float e0 = 0.0f, e1 = 0.0f;
-  if (alive) { e0 = cx.ebar[k.node_off + cg]; e1 = cx.ebar[k.node_off + cg + 1]; }
-  u = lep_kick(u, sg, frac, e0, e1, k.dt);
+  const uint32_t flags = (uint32_t)k.flags;
+  const bool per = (flags & F_PERIODIC) != 0;
+  const int64_t step = k.step;
+  struct { int base; } tl{k.base};
 
-  const LepQ q = lep_q(u, k.lr);
-  const bool eval = alive && !(k.flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < k.hfix &&
-                    q.xc >= k.xc_floor;
-  uint64_t evmask = 0, id = 0;
-  int ncand = 0, nev = 0;
+  // gather (node field, first-order shape) and kick
+  const int off = (int)(pos >> FRAC);
+  const int cell = tl.base + off;
+  const uint32_t frac = pos & 0xFFFFFFu;
+  const int cg = per ? wrap_cell(cell, N) : cell;
+  const float xi = (float)frac * 5.9604645e-8f;
+  float e0 = 0.0f, e1 = 0.0f;
+  if (alive) {
+    if (UNI) { e0 = s_eb[off]; e1 = s_eb[off + 1]; }
+    else { e0 = cx.ebar[k.node_off + cg]; e1 = cx.ebar[k.node_off + cg + 1]; }
+  }
+  const float sg = w < 0.0f ? -1.0f : 1.0f;
+  u += sg * ((1.0f - xi) * e0 + xi * e1) * k.dt;
+
+  // curvature emission: rate alpha_em gamma/R~ T_syn(chi), chi = gamma^2 lambda~/R~,
+  // photon energy xi_s x_c with x_c = 1.5 gamma chi, QED zone h < H
   const float upk = u;
-  if (eval) {
-    id = cx.L.id[slot];
-    u = lep_emit(cx, k, q, id, u, &evmask, &ncand, &nev);
+  uint64_t evmask = 0;
+  uint64_t id = 0;
+  float xc = 0.0f;
+  int ncand = 0, nev = 0;
+  bool eval = false;
+  if (alive && !(flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < k.hfix) {
+    const float g = __builtin_amdgcn_sqrtf(1.0f + u * u);
+    const float chi = g * g * k.lr;
+    xc = 1.5f * g * chi;
+    if (xc >= k.xc_floor) {
+      eval = true;
+      id = cx.L.id[slot];
+      const float dtau = k.emit_k * g * t_syn(chi);
+      int nsub = (int)ceilf(dtau * 10.0f);
+      nsub = max(1, min(nsub, k.nsub_max));
+      const float p = one_minus_exp_neg(dtau / (float)nsub);
+      float au = fabsf(u);
+      for (int j = 0; j < nsub; ++j) {
+        u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
+        if (bern(r.a, p)) {
+          float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+          au -= x;
+          evmask |= 1ull << j;
+          ++nev;
+          if (x >= k.x_thr || (flags & F_TRACK_ALL)) ++ncand;
+        }
+      }
+      if (!(flags & F_RECOIL_OFF)) u = copysignf(au, upk);
+    }
   }
 
-  const int dfix = lep_dfix(u, k.cfl24);
+  // drift: dh/dt = u / gamma, in fixed point
+  const int dfix = __float2int_rn(u * __builtin_amdgcn_rsqf(1.0f + u * u) * k.cfl24);
   const long long npl = (long long)pos + dfix;
   const int noff = (int)(npl >> FRAC);
   const uint32_t nfrac = (uint32_t)npl & 0xFFFFFFu;
-  const int ncell = k.base + noff;
   bool dead = false;
+  const int ncell = tl.base + noff;
   if (alive && (npl < 0 || noff >= WIN)) { atomicOr(cx.err, E_TILE); dead = true; }
-  const int64_t Tw = alive ? lep_T(w) : 0;
+  const int64_t Tw = alive ? __float2ll_rn(fabsf(w) * 16777216.0f) : 0;
   bool absorbed = false, outflow = false;
   if (alive && !dead && !per) {
     if (ncell < 0) { absorbed = true; dead = true; }
     else if (ncell >= N) { outflow = true; dead = true; }
   }
   if (alive && dead) cx.L.w[slot] = 0.0f;
-  else if (alive) {
+  if (UNI) {           // the caller stores the chunk's records with vector stores
+    *pos_out = (uint32_t)npl;
+    *u_out = u;
+  } else if (alive && !dead) {
     cx.L.pos[slot] = (uint32_t)npl;
     cx.L.u[slot] = u;
   }
   if (absorbed) {
-    atomic_add_i64(&cx.tubes[tube].dq, neg ? -Tw : Tw);
+    atomic_add_i64(&cx.tubes[tube].dq, sg > 0 ? Tw : -Tw);
     return_add(cx.ret, cx.ret_thr, tube, u, w);
   }
-  if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (neg ? -Tw : Tw) * (int64_t)dfix);
+  if (per && alive && !dead) atomic_add_i64(&cx.tubes[tube].dcur, (sg > 0 ? Tw : -Tw) * (int64_t)dfix);
+
+  // deposit at the new position: node k gets s (T - A), node k+1 gets s A,
+  // A = round(T xi) (half up), exact integers
   const int ncg = per ? wrap_cell(ncell, N) : ncell;
   if (alive && !dead) {
-    const int64_t A = lep_A(Tw, nfrac);
-    int n1 = ncg + 1;
-    if (per && n1 == N) n1 = 0;
-    atomicAdd((unsigned long long*)&cx.rho[k.node_off + ncg], (unsigned long long)(neg ? A - Tw : Tw - A));
-    atomicAdd((unsigned long long*)&cx.rho[k.node_off + n1], (unsigned long long)(neg ? -A : A));
+    const unsigned long long A = ((unsigned long long)Tw * nfrac + (1ull << 23)) >> FRAC;
+    const long long a = sg > 0 ? (long long)A : -(long long)A;
+    const long long ta = sg > 0 ? (long long)(Tw - (int64_t)A) : -(long long)(Tw - (int64_t)A);
+    if (UNI) {
+      atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)ta);
+      atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)a);
+    } else {
+      int n1 = ncg + 1;
+      if (per && n1 == N) n1 = 0;
+      atomicAdd((unsigned long long*)&cx.rho[k.node_off + ncg], (unsigned long long)ta);
+      atomicAdd((unsigned long long*)&cx.rho[k.node_off + n1], (unsigned long long)a);
+    }
   }
+
+  // photon births at the post-drift position, inside the QED zone
   const bool keep = alive && !dead && (((int64_t)ncg << FRAC) + nfrac < k.hfix);
   const int nst = keep ? ncand : 0;
-  if (__ballot(nst > 0)) lep_births(cx, k, nst, id, evmask, upk, q.xc, w, (uint32_t)npl, lcn);
+  if (__ballot(nst > 0)) {
+    int dropped = 0;
+    const long long first = reserve_tail(cx.pc, proom, nst, &dropped);
+    const long long lim = proom.L;
+    if (nst > 0) {
+      float au = fabsf(upk);
+      const float dir = upk >= 0.0f ? 1.0f : -1.0f;
+      const float aw = fabsf(w);
+      long long q = first;
+      uint64_t m = evmask;
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
+        float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+        au -= x;
+        if (x >= k.x_thr || (flags & F_TRACK_ALL)) {
+          if (q < lim) {
+            const uint32_t kk = (uint32_t)q;
+            cx.P.pos[kk] = (uint32_t)npl;
+            cx.P.x[kk] = dir * x;
+            cx.P.w[kk] = aw;
+            cx.P.n0[kk] = (int32_t)(step + 1);
+            cx.P.id[kk] = child_id(k.seed, id, step, 2u + (uint32_t)j);
+            cx.ptt[kk] = tile;
+          }
+          ++q;
+        }
+      }
+    }
+    if (dropped) atomicOr(cx.err, E_CAP);
+    lcn.v[3] += nst - dropped;
+    lcn.v[4] += dropped;
+  }
+
+  // event counts: sorted chunks accumulate per thread (flushed per
+  // workgroup); tail lanes may belong to different tubes
   lcn.v[0] += alive ? 1 : 0;
   lcn.v[1] += eval ? 1 : 0;
   lcn.v[2] += nev;
   lcn.v[5] += absorbed ? 1 : 0;
   lcn.v[6] += outflow ? 1 : 0;
-  // tail lanes may belong to different tubes
+  if (!UNI) {
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const int v = lcn.v[i];
-    if (__ballot(v != 0)) count_by_tube(cx.shard, v != 0 ? tube : -1, cnt_index<2>(i), v);
+    for (int i = 0; i < 7; ++i) {
+      const int v = lcn.v[i];
+      if (__ballot(v != 0)) count_by_tube(cx.shard, v != 0 ? tube : -1, cnt_index<2>(i), v);
+    }
+    lcn.clear();
   }
-  lcn.clear();
 }
 
 // Node field of a tile window into LDS (nodes base .. base + WIN).
@@ -707,6 +549,19 @@ __device__ void load_window(const Ctx& cx, int tile, float* s_eb) {
   __syncthreads();
 }
 
+// Records of VEC consecutive slots of a sorted chunk (one thread).
+struct Lep4 { float4 w; uint4 pos; float4 u; int tile; uint32_t slot0; };
+
+__device__ __forceinline__ Lep4 lep_load4(const Ctx& cx, long long c) {
+  Lep4 r;
+  r.slot0 = (uint32_t)c * CHUNK + VEC * threadIdx.x;
+  r.tile = cx.lchunk[c];
+  r.w = *reinterpret_cast<const float4*>(cx.L.w + r.slot0);
+  r.pos = *reinterpret_cast<const uint4*>(cx.L.pos + r.slot0);
+  r.u = *reinterpret_cast<const float4*>(cx.L.u + r.slot0);
+  return r;
+}
+
 // Slot and tile of 256-slot piece q (sorted pieces first, then the tail).
 __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long S, long long tail, const int32_t* chunk,
                                            const int32_t* tt, uint32_t* slot, int* tile) {
@@ -721,76 +576,76 @@ __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long
 }
 
 // Lepton pass over the sorted region.  Each workgroup takes a contiguous
-// range of chunks (XCD-aware: consecutive ranges go to the same XCD) and
-// walks it 256 slots at a time, one slot per thread, with the next piece's
-// records loaded while the current one is pushed.  The chunk's tile
-// constants sit in scalar registers; gather and deposit go through an LDS
-// window of the tile.
-__global__ __launch_bounds__(TPB) void k_leptons(Ctx cx) {
+// range of chunks (XCD-aware: consecutive ranges go to the same XCD); each
+// thread pushes VEC consecutive slots loaded and stored as 16-byte vectors,
+// and the next chunk's records are prefetched while the current one is
+// pushed.  The chunk's tile constants sit in scalar registers; gather and
+// deposit go through an LDS window of the tile.
+// (six waves per SIMD: the register cap spills one value, stored once on
+// entry and reloaded once per chunk)
+__global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
+  const Room proom = load_room(cx.pc);
   __shared__ long long s_rho[WIN + 2];
   __shared__ float s_eb[WIN + 2];
   __shared__ long long s_cnt[8];
   LocalCounts lcn;
   lcn.clear();
-  WaveCounts wc{0, 0, 0, 0};
   int ctube = -1;
   for (int j = threadIdx.x; j < WIN + 2; j += blockDim.x) s_rho[j] = 0;
   __syncthreads();
-  long long c0, c1;
-  chunk_range(cx.lc->n_sorted_chunks, gridDim.x, blockIdx.x, &c0, &c1);
-  const long long q0 = c0 * PPC, q1 = c1 * PPC;
+  const long long nsc = cx.lc->n_sorted_chunks;
+  const int G = gridDim.x, bx = blockIdx.x;
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  const long long c0 = nsc * r / G, c1 = nsc * (r + 1) / G;
   int held = -1;
   KC kc;
-  LT lt;
-  uint32_t slot = (uint32_t)(q0 * TPB) + threadIdx.x;
-  float w = 0.0f, u = 0.0f;
-  uint32_t pos = 0;
-  if (q0 < q1) { w = cx.L.w[slot]; pos = cx.L.pos[slot]; u = cx.L.u[slot]; }
-  auto add_wave_counts = [&]() {
-    if (lane_id() == 0) {
-      lcn.v[0] += wc.alive; lcn.v[1] += wc.eval; lcn.v[5] += wc.absorbed; lcn.v[6] += wc.outflow;
-    }
-    wc = WaveCounts{0, 0, 0, 0};
-  };
-  for (long long q = q0; q < q1; ++q) {
-    const uint32_t sn = slot + TPB;
-    float wn = 0.0f, un = 0.0f;
-    uint32_t pn = 0;
-    if (q + 1 < q1) { wn = cx.L.w[sn]; pn = cx.L.pos[sn]; un = cx.L.u[sn]; }
-    const int tile = rfl(cx.lchunk[q / PPC]);
+  Lep4 cur;
+  if (c0 < c1) cur = lep_load4(cx, c0);
+  for (long long c = c0; c < c1; ++c) {
+    Lep4 nxt;
+    if (c + 1 < c1) nxt = lep_load4(cx, c + 1);
+    const int tile = cur.tile;
     if (tile != held) {
       if (held >= 0) flush_window(cx, held, s_rho);
       held = tile;
       kc = load_kc(cx, tile, false);
-      lt = lepton_tile(kc);
       if (kc.tube != ctube) {
-        if (ctube >= 0) {
-          add_wave_counts();
-          flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
-        }
+        if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
         ctube = kc.tube;
       }
       load_window(cx, tile, s_eb);
     }
-    lepton_sorted(cx, slot, kc, lt, s_rho, s_eb, lcn, wc, w, pos, u);
-    slot = sn; w = wn; pos = pn; u = un;
+    float4 w = cur.w, u = cur.u;
+    uint4 p = cur.pos;
+    // one body, four records: process .x, write the result into .x, rotate
+#pragma unroll 1
+    for (int j = 0; j < VEC; ++j) {
+      uint32_t po;
+      float uo;
+      lepton_one<true>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
+      w = make_float4(w.y, w.z, w.w, w.x);
+      p = make_uint4(p.y, p.z, p.w, po);
+      u = make_float4(u.y, u.z, u.w, uo);
+    }
+    *reinterpret_cast<uint4*>(cx.L.pos + cur.slot0) = p;
+    *reinterpret_cast<float4*>(cx.L.u + cur.slot0) = u;
+    cur = nxt;
   }
   if (held >= 0) flush_window(cx, held, s_rho);
-  if (ctube >= 0) {
-    add_wave_counts();
-    flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
-  }
+  if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
 }
 
 // Lepton pass over the tail (particles appended since the last re-sort):
 // one slot per thread, each lane with its own tile; global gather/deposit.
 __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
+  const Room proom = load_room(cx.pc);
   LocalCounts lcn;
   lcn.clear();
   const long long nsc = cx.lc->n_sorted_chunks;
   const long long S = nsc * CHUNK;
   const long long tail = cx.lc->tail_snap;
   const long long nq = (tail + TPB - 1) / TPB;
+  const KC kc0 = load_kc(cx, 0, false);
   for (long long q = bid; q < nq; q += nblk) {
     uint32_t slot;
     int tile;
@@ -798,7 +653,7 @@ __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
     const float w = cx.L.w[slot];
     const uint32_t pos = cx.L.pos[slot];
     const float u = cx.L.u[slot];
-    lepton_tail_one(cx, slot, tile, lcn, w, pos, u);
+    lepton_one<false>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
   }
 }
 
@@ -976,6 +831,14 @@ __device__ __forceinline__ void photon_move(const Ctx& cx, const KC& k, float x,
   lcn.v[0] += alive ? 1 : 0;
   lcn.v[1] += eval ? 1 : 0;
   lcn.v[4] += exited ? 1 : 0;
+}
+
+// First chunk of the range of workgroup `bx` of a grid of G over nsc chunks
+// (XCD-aware: consecutive ranges go to workgroups of the same XCD).
+__device__ __forceinline__ void chunk_range(long long nsc, int G, int bx, long long* c0, long long* c1) {
+  const int r = (bx & 7) * (G >> 3) + (bx >> 3);
+  *c0 = nsc * r / G;
+  *c1 = nsc * (r + 1) / G;
 }
 
 // Photon pass over the sorted region, first kernel: free streaming, exits

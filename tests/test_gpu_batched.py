@@ -148,7 +148,12 @@ def _qed_active(cfg):
     """A tube of the batched recipe at its own size, with the tiny gap's QED
     rescale so that emission, transport and conversion all run within 100
     steps."""
-    return dict(cfg, lambda_c_scale=workloads.TINY["lambda_c_scale"], r_curv_scale=workloads.TINY["r_curv_scale"])
+    # photon store as large as the lepton store: the QED-active tube makes
+    # more photons than the recipe's physical run is sized for, and a cap
+    # reached on one side only would split the two runs
+    cap = max(cfg["cap_leptons"], 1 << 20)
+    return dict(cfg, lambda_c_scale=workloads.TINY["lambda_c_scale"], r_curv_scale=workloads.TINY["r_curv_scale"],
+                cap_leptons=cap, cap_photons=cap)
 
 
 def test_batched_tubes_match_the_oracle(torch_gpu):
@@ -178,7 +183,8 @@ def test_batched_tubes_match_the_oracle(torch_gpu):
         _say("  tube %d: worst field err %.2e; emit %d/%d born %d/%d conv %d/%d leptons %d/%d" % (
             pick[t], worst[t], cg["n_emit"], co["n_emit"], cg["n_pho_born"], co["n_pho_born"], cg["n_conv"],
             co["n_conv"], cg["n_lep"], co["n_lep"]))
-        assert cg["err"] == 0
+        assert cg["err"] == 0 and co["err"] == 0
+        assert cg["n_dropped"] == 0 and co["n_dropped"] == 0
         assert co["n_emit"] > 10000 and co["n_conv"] > 500
         for k in ("n_emit", "n_pho_born", "n_conv"):
             assert abs(cg[k] - co[k]) <= max(2, 1e-3 * co[k]), (pick[t], k)
@@ -188,5 +194,14 @@ def test_batched_tubes_match_the_oracle(torch_gpu):
         common, ia, ib = np.intersect1d(P["id"], Q["id"], return_indices=True)
         assert common.size >= 0.998 * max(P["id"].size, Q["id"].size)
         assert np.all(P["n0"][ia] == Q["n0"][ib])
-        assert np.allclose(P["x"][ia], Q["x"][ib], rtol=2e-4, atol=0)
+        # energies within the table accuracy, except photons of leptons whose
+        # history split at an FP32/FP64 near-tie (a draw on the other side of
+        # u < p changes the lepton's later momentum and so its later photons)
+        rel = np.abs(P["x"][ia] - Q["x"][ib]) / np.abs(Q["x"][ib])
+        _say("  tube %d: %d common photons, %d outside 2e-4, median rel %.1e" % (
+            pick[t], common.size, int((rel > 2e-4).sum()), float(np.median(rel))))
+        for k in np.argsort(rel)[-3:]:
+            _say("    n0 %d x gpu %.7e oracle %.7e" % (Q["n0"][ib[k]], P["x"][ia[k]], Q["x"][ib[k]]))
+        assert (rel > 2e-4).sum() <= max(4, 2e-3 * common.size)
+        assert np.median(rel) <= 1e-6
     g.close()
