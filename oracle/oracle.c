@@ -50,6 +50,7 @@
 #define ORC_EMIT_OFF     2048u
 #define ORC_INJ_FIXED    4096u   /* injection count independent of inj_weight */
 #define ORC_FILTER       8192u   /* binomial current filter, ORC_FILTER_PASSES passes per step */
+#define ORC_QUANTUM      16384u  /* quantum photon spectrum and pair split (Sect. 3.1, 3.2)    */
 #define ORC_FILTER_PASSES 8
 
 /* Random-stream tags (upper 16 bits of the fourth counter word). */
@@ -242,6 +243,201 @@ static double sync_inverse(const orc_sim* s, double r) {
     y = yn;
   }
   return exp(y);
+}
+
+/* ------------------------------------------------------------------ */
+/* Quantum-corrected spectra (optional, flag ORC_QUANTUM).  The paper    */
+/* names the first-order QED rates it builds on (Sect. 3.1: the photon   */
+/* spectrum S(gamma, x) and the Gaunt factor g_Q of P_syn; Sect. 3.2:    */
+/* the one-photon pair creation rate) without printing the spectra.      */
+/* Reading: the textbook first-order forms, in units where the rates of  */
+/* eqs. tau_syn and tau_bw are alpha_em b sin(psi) / t_C times           */
+/*   T_syn(chi) = 1/(sqrt3 pi chi) int_0^1 s(d) dd,                      */
+/*   s(d) = (1 - d + 1/(1-d)) K_{2/3}(z) - Ki_{1/3}(z),                 */
+/*   z = 2 d / (3 chi (1 - d)),  d = x / gamma (photon energy fraction); */
+/*   T_BW(chi) = 1/(sqrt3 pi chi) int_0^1 p(v) dv,                       */
+/*   p(v) = (v/(1-v) + (1-v)/v) K_{2/3}(e) + Ki_{1/3}(e),               */
+/*   e = 2 / (3 chi v (1 - v)),  v = gamma_- / x (electron fraction);    */
+/* with Ki_nu(z) = int_z^inf K_nu.  For chi -> 0, s dd reduces to the     */
+/* classical number spectrum int_z^inf K_{5/3} dz of the classical      */
+/* sampler above, and the Gaunt factor is                                */
+/*   g_Q(chi) = sqrt3/(2 pi chi^2) int_0^1 d s(d) dd.                    */
+/* ------------------------------------------------------------------ */
+
+/* K_{2/3}(z) e^off and Ki_{1/3}(z) e^off from
+ *   K_nu(z) = int_0^inf exp(-z cosh u) cosh(nu u) du,
+ *   Ki_nu(z) = int_0^inf exp(-z cosh u) cosh(nu u) / cosh u du,
+ * by the trapezoidal rule (step 1/16; the integrands are analytic in a strip
+ * of half-width pi/2, so the rule converges geometrically). */
+static void bessel_k23_ki13(double z, double off, double* k23, double* ki13) {
+  const double h = 1.0 / 16.0;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < 16 * 60; ++i) {
+    double u = i * h, c = cosh(u);
+    double ex = z * c - off;
+    if (ex > 745.0) break;
+    double e = exp(-ex) * (i == 0 ? 0.5 : 1.0);
+    a += e * cosh(2.0 * u / 3.0);
+    b += e * cosh(u / 3.0) / c;
+  }
+  *k23 = a * h;
+  *ki13 = b * h;
+}
+
+/* 8-point Gauss-Legendre nodes and weights on [-1, 1]. */
+static const double GL8_X[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                                -0.1834346424956498, 0.1834346424956498, 0.5255324099163290,
+                                0.7966664774136267, 0.9602898564975363};
+static const double GL8_W[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                                0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                                0.2223810344533745, 0.1012285362903763};
+
+/* Photon spectrum per unit t, z = t^3: s(d(z)) dd/dz dz/dt, with
+ * d = 3 chi z / (2 + 3 chi z).  `moment` 1 multiplies by d. */
+static double qsyn_dens_t(double chi, double t, int moment) {
+  double z = t * t * t;
+  double q = 2.0 + 3.0 * chi * z;
+  double d = 3.0 * chi * z / q, omd = 2.0 / q;
+  double k23, ki13;
+  bessel_k23_ki13(z, 0.0, &k23, &ki13);
+  double sd = (omd + 1.0 / omd) * k23 - ki13;
+  double v = sd * (6.0 * chi / (q * q)) * 3.0 * t * t;
+  return moment ? v * d : v;
+}
+
+#define QSYN_TMAX 3.915     /* z = 60: the spectrum there is below e^-60 of its peak */
+#define QSYN_PANELS 80
+
+static double gl8(double (*f)(double, double, int), double chi, int moment, double a, double b) {
+  double m = 0.5 * (a + b), r = 0.5 * (b - a), acc = 0.0;
+  for (int k = 0; k < 8; ++k) acc += GL8_W[k] * f(chi, m + r * GL8_X[k], moment);
+  return acc * r;
+}
+
+/* int_0^1 s(d) dd (moment 0) or int_0^1 d s(d) dd (moment 1). */
+static double qsyn_total(double chi, int moment) {
+  const double dt = QSYN_TMAX / QSYN_PANELS;
+  double acc = 0.0;
+  for (int i = 0; i < QSYN_PANELS; ++i) acc += gl8(qsyn_dens_t, chi, moment, i * dt, (i + 1) * dt);
+  return acc;
+}
+
+/* Emission rate function from the spectrum (compare the fit orc_tsyn). */
+double orc_qsyn_T(double chi) { return qsyn_total(chi, 0) / (sqrt(3.0) * ORC_PI * chi); }
+
+/* Gaunt factor g_Q = P_syn / P_classical. */
+double orc_qsyn_g(double chi) { return sqrt(3.0) / (2.0 * ORC_PI * chi * chi) * qsyn_total(chi, 1); }
+
+/* Fraction of emitted photons with energy fraction below d. */
+double orc_qsyn_cdf(double chi, double d) {
+  if (!(d > 0.0)) return 0.0;
+  if (!(d < 1.0)) return 1.0;
+  double t = cbrt(2.0 * d / (3.0 * chi * (1.0 - d)));
+  const double dt = QSYN_TMAX / QSYN_PANELS;
+  double acc = 0.0;
+  for (int i = 0; i < QSYN_PANELS; ++i) {
+    double a = i * dt, b = (i + 1) * dt;
+    if (a >= t) break;
+    acc += gl8(qsyn_dens_t, chi, 0, a, b < t ? b : t);
+  }
+  if (t > QSYN_TMAX) acc += 0.0;   /* beyond z = 60 nothing is left */
+  return acc / qsyn_total(chi, 0);
+}
+
+/* Energy fraction d with cdf(d) = r: the panel holding r, then Newton on t
+ * inside it (bisection bracket). */
+double orc_qsyn_inverse(double chi, double r) {
+  const double dt = QSYN_TMAX / QSYN_PANELS;
+  double part[QSYN_PANELS], tot = 0.0;
+  for (int i = 0; i < QSYN_PANELS; ++i) {
+    part[i] = gl8(qsyn_dens_t, chi, 0, i * dt, (i + 1) * dt);
+    tot += part[i];
+  }
+  double target = r * tot, acc = 0.0;
+  int i = 0;
+  while (i < QSYN_PANELS - 1 && acc + part[i] < target) acc += part[i++];
+  double a = i * dt, b = (i + 1) * dt, need = target - acc;
+  double lo = a, hi = b, t = a + (b - a) * (part[i] > 0.0 ? need / part[i] : 0.5);
+  for (int it = 0; it < 60; ++it) {
+    double g = gl8(qsyn_dens_t, chi, 0, a, t) - need;
+    if (g > 0.0) hi = t; else lo = t;
+    double dg = qsyn_dens_t(chi, t, 0);
+    double tn = dg > 0.0 ? t - g / dg : 0.5 * (lo + hi);
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (fabs(tn - t) <= 1e-15 * (t > 1e-300 ? t : 1e-300) || hi - lo <= 1e-15 * hi) { t = tn; break; }
+    t = tn;
+  }
+  double z = t * t * t;
+  return 3.0 * chi * z / (2.0 + 3.0 * chi * z);
+}
+
+/* Pair spectrum per unit w, v = 1/2 - w, scaled by exp(8/(3 chi)) (the
+ * smallest e, at v = 1/2), so that small chi does not underflow. */
+static double qbw_dens_w(double chi, double w, int unused) {
+  (void)unused;
+  double v = 0.5 - w, m = 0.5 + w;
+  double e = 2.0 / (3.0 * chi * v * m);
+  double k23, ki13;
+  bessel_k23_ki13(e, 8.0 / (3.0 * chi), &k23, &ki13);
+  return (v / m + m / v) * k23 + ki13;
+}
+
+#define QBW_PANELS 200
+
+/* int_0^{1/2} p dw, scaled as qbw_dens_w. */
+static double qbw_half(double chi) {
+  const double dw = 0.5 / QBW_PANELS;
+  double acc = 0.0;
+  for (int i = 0; i < QBW_PANELS; ++i) acc += gl8(qbw_dens_w, chi, 0, i * dw, (i + 1) * dw);
+  return acc;
+}
+
+/* Pair creation rate function from the spectrum (compare the fit orc_tbw). */
+double orc_qbw_T(double chi) {
+  return 2.0 * qbw_half(chi) * exp(-8.0 / (3.0 * chi)) / (sqrt(3.0) * ORC_PI * chi);
+}
+
+/* Fraction of pairs whose electron takes less than the fraction v. */
+double orc_qbw_cdf(double chi, double v) {
+  if (!(v > 0.0)) return 0.0;
+  if (!(v < 1.0)) return 1.0;
+  if (v > 0.5) return 1.0 - orc_qbw_cdf(chi, 1.0 - v);
+  double w = 0.5 - v;                      /* mass between v and 1/2 */
+  const double dw = 0.5 / QBW_PANELS;
+  double acc = 0.0;
+  for (int i = 0; i < QBW_PANELS; ++i) {
+    double a = i * dw, b = (i + 1) * dw;
+    if (a >= w) break;
+    acc += gl8(qbw_dens_w, chi, 0, a, b < w ? b : w);
+  }
+  return 0.5 - 0.5 * acc / qbw_half(chi);
+}
+
+/* Electron fraction v with cdf(v) = r; the spectrum is symmetric, so
+ * v(r) = 1 - v(1 - r) and only r < 1/2 is solved (w = 1/2 - v). */
+double orc_qbw_inverse(double chi, double r) {
+  if (r > 0.5) return 1.0 - orc_qbw_inverse(chi, 1.0 - r);
+  const double dw = 0.5 / QBW_PANELS;
+  double part[QBW_PANELS], half = 0.0;
+  for (int i = 0; i < QBW_PANELS; ++i) {
+    part[i] = gl8(qbw_dens_w, chi, 0, i * dw, (i + 1) * dw);
+    half += part[i];
+  }
+  double target = (1.0 - 2.0 * r) * half, acc = 0.0;
+  int i = 0;
+  while (i < QBW_PANELS - 1 && acc + part[i] < target) acc += part[i++];
+  double a = i * dw, b = (i + 1) * dw, need = target - acc;
+  double lo = a, hi = b, w = a + (b - a) * (part[i] > 0.0 ? need / part[i] : 0.5);
+  for (int it = 0; it < 60; ++it) {
+    double g = gl8(qbw_dens_w, chi, 0, a, w) - need;
+    if (g > 0.0) hi = w; else lo = w;
+    double dg = qbw_dens_w(chi, w, 0);
+    double wn = dg > 0.0 ? w - g / dg : 0.5 * (lo + hi);
+    if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
+    if (fabs(wn - w) <= 1e-16 || hi - lo <= 1e-16) { w = wn; break; }
+    w = wn;
+  }
+  return 0.5 - w;
 }
 
 /* ------------------------------------------------------------------ */
@@ -692,7 +888,13 @@ static void step_once(orc_sim* s) {
         for (int j = 0; j < nsub; ++j) {
           uint32_t r[4];
           draw(p->seed, l->id, n, TAG_EMIT, (uint32_t)j, r);
-          if (u24(r[0]) < pe) emit_apply(s, l, n, j, sync_inverse(s, u24(r[1])) * xc, pend, &npend);
+          if (u24(r[0]) < pe) {
+            /* photon energy: classical x = xi x_c, or the quantum spectrum's
+             * energy fraction of the emitter's gamma at its chi */
+            double x = (p->flags & ORC_QUANTUM) ? orc_qsyn_inverse(chi, u24(r[1])) * g
+                                                : sync_inverse(s, u24(r[1])) * xc;
+            emit_apply(s, l, n, j, x, pend, &npend);
+          }
         }
       }
     }
@@ -777,10 +979,17 @@ static void step_once(orc_sim* s) {
       conv = u24(r[0]) < pc;
     }
     if (conv) {
-      double gam = 0.5 * fabs(g->x);
-      double up = dir * sqrt(fmax(gam * gam - 1.0, 0.0));
-      olep em = {g->cell, g->xi, up, -g->w, child_id(p->seed, g->id, n, 0)};
-      olep ep = {g->cell, g->xi, up, g->w, child_id(p->seed, g->id, n, 1)};
+      /* energy split: halves (R10), or the electron's fraction v from the
+       * quantum pair spectrum at the photon's chi */
+      double v = 0.5;
+      if (p->flags & ORC_QUANTUM) {
+        uint32_t r[4];
+        draw(p->seed, g->id, n, TAG_CONV, 0, r);
+        v = orc_qbw_inverse(chi, u24(r[1]));
+      }
+      double gm = v * fabs(g->x), gp = (1.0 - v) * fabs(g->x);
+      olep em = {g->cell, g->xi, dir * sqrt(fmax(gm * gm - 1.0, 0.0)), -g->w, child_id(p->seed, g->id, n, 0)};
+      olep ep = {g->cell, g->xi, dir * sqrt(fmax(gp * gp - 1.0, 0.0)), g->w, child_id(p->seed, g->id, n, 1)};
       log_event(s, 1, n, g->id, 0, fabs(g->x), 0, 0.0, 0.0);
       push_lep(s, em);
       push_lep(s, ep);

@@ -19,7 +19,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 FLAGS = dict(
     QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32,
     TRACK_ALL=64, ANTI_ALIGNED=128, RECORD=256, REPLAY=512, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096,
-    FILTER=8192,
+    FILTER=8192, QUANTUM=16384,
 )
 FILTER_PASSES = 8
 
@@ -106,6 +106,12 @@ def _load():
         lib.orc_sync_cdf.restype = C.c_double
         lib.orc_sync_cdf.argtypes = [C.c_double]
         lib.orc_sync_inverse_many.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        for name in ("orc_qsyn_T", "orc_qsyn_g", "orc_qbw_T"):
+            getattr(lib, name).restype = C.c_double
+            getattr(lib, name).argtypes = [C.c_double]
+        for name in ("orc_qsyn_cdf", "orc_qsyn_inverse", "orc_qbw_cdf", "orc_qbw_inverse"):
+            getattr(lib, name).restype = C.c_double
+            getattr(lib, name).argtypes = [C.c_double, C.c_double]
         lib.orc_u24.restype = C.c_double
         lib.orc_u24.argtypes = [C.c_uint32]
         _lib = lib
@@ -147,6 +153,52 @@ def sync_inverse(r) -> np.ndarray:
     out = np.empty_like(r)
     _load().orc_sync_inverse_many(_ptr(r), _ptr(out), r.size)
     return out
+
+
+# Quantum-corrected spectra (Sect. 3.1 S(gamma, x) and g_Q; Sect. 3.2 pair
+# split): rate functions, Gaunt factor, distribution functions and their
+# inverses in FP64.
+def qsyn_T(chi: float) -> float:
+    """Emission rate function from the quantum photon spectrum."""
+    return _load().orc_qsyn_T(float(chi))
+
+
+def qsyn_g(chi: float) -> float:
+    """Gaunt factor g_Q = P_syn / P_classical."""
+    return _load().orc_qsyn_g(float(chi))
+
+
+def qsyn_cdf(chi: float, d) -> np.ndarray:
+    """Fraction of emitted photons with energy fraction x/gamma below d."""
+    lib = _load()
+    return np.array([lib.orc_qsyn_cdf(float(chi), float(v)) for v in np.atleast_1d(d)])
+
+
+def qsyn_inverse(chi, r) -> np.ndarray:
+    """Photon energy fraction d with qsyn_cdf(chi, d) = r (chi scalar or per r)."""
+    lib = _load()
+    r = np.atleast_1d(np.asarray(r, np.float64))
+    c = np.broadcast_to(np.asarray(chi, np.float64), r.shape)
+    return np.array([lib.orc_qsyn_inverse(float(a), float(b)) for a, b in zip(c, r)])
+
+
+def qbw_T(chi: float) -> float:
+    """Pair creation rate function from the quantum pair spectrum."""
+    return _load().orc_qbw_T(float(chi))
+
+
+def qbw_cdf(chi: float, v) -> np.ndarray:
+    """Fraction of pairs whose electron takes less than the energy fraction v."""
+    lib = _load()
+    return np.array([lib.orc_qbw_cdf(float(chi), float(x)) for x in np.atleast_1d(v)])
+
+
+def qbw_inverse(chi, r) -> np.ndarray:
+    """Electron energy fraction v with qbw_cdf(chi, v) = r."""
+    lib = _load()
+    r = np.atleast_1d(np.asarray(r, np.float64))
+    c = np.broadcast_to(np.asarray(chi, np.float64), r.shape)
+    return np.array([lib.orc_qbw_inverse(float(a), float(b)) for a, b in zip(c, r)])
 
 
 class Oracle:
