@@ -74,6 +74,16 @@ extern "C" {
                                    Gauss field and E0 the field when the state was last
                                    set; E_s itself is not filtered.  Not with the
                                    differentiable window (GAP_EINVAL)                   */
+#define GAP_QUANTUM      16384u /* quantum-corrected energies (Sect. 3.1, 3.2): an emitted
+                                   photon takes the energy fraction x/gamma drawn from the
+                                   first-order synchrotron spectrum at the lepton's chi
+                                   (its mean carries the Gaunt factor g_Q into the recoil),
+                                   and a pair's electron the fraction drawn from the
+                                   one-photon pair spectrum at the photon's chi (the
+                                   positron the rest).  The rates stay the fits T_syn and
+                                   T_BW.  Without it: the classical spectrum and halves.
+                                   Tables (~0.9 MB of device memory) are built on the host
+                                   at the first handle that needs them                 */
 
 /* initial states (gap_params.init_kind) */
 #define GAP_INIT_GAP      0  /* vacuum below H, electrons at ppc_init per cell above H  */
@@ -345,6 +355,15 @@ const char* gap_strerror(int code);
  * device shares that workspace: calls that may overlap on one device (two
  * streams, two handles) race and must be ordered by the caller. */
 int gap_e_spectrum_noalloc(gap_t* g, int32_t tube, double* power, int64_t power_len);
+
+/* The quantum samplers the particle passes use (GAP_QUANTUM), evaluated on
+ * the device at n given points: kind 0 gives the photon energy fraction
+ * x/gamma for a lepton at chi[i], kind 1 the electron's energy fraction of a
+ * pair created by a photon at chi[i]; words[i] is the Philox word whose top
+ * 24 bits make the uniform r = (k + 1/2) 2^-24 (Sect. 3.1 spectrum S, Sect.
+ * 3.2 pair creation).  Host pointers, out[i] as double; the call allocates
+ * and waits.  GAP_EINVAL for another kind or a negative or non-finite chi. */
+int gap_qed_sample(gap_t* g, int32_t kind, const double* chi, const uint32_t* words, int64_t n, double* out);
 
 /* Host utility: invert the cumulative classical synchrotron photon-number
  * spectrum with the library's own table (the sampler the device uses):

@@ -272,7 +272,7 @@ static double sync_inverse(const orc_sim* s, double r) {
 static void bessel_k23_ki13(double z, double off, double* k23, double* ki13) {
   const double h = 1.0 / 16.0;
   double a = 0.0, b = 0.0;
-  for (int i = 0; i < 16 * 60; ++i) {
+  for (int i = 0; i < 16 * 100; ++i) {      /* u < 100: z cosh u > 745 for every z > 1e-40 */
     double u = i * h, c = cosh(u);
     double ex = z * c - off;
     if (ex > 745.0) break;

@@ -6,6 +6,7 @@
 #include "gap_merge.hpp"
 #include "gap_adjoint.hpp"
 #include "gap_diag.hpp"
+#include "gap_qtab.hpp"
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -132,6 +133,11 @@ float sync_sample_host(float r, const float* tab) {
   return h[i] + f * (h[i + 1] - h[i]);
 }
 
+const qtab::Tables& quantum_tables() {
+  return qtab::tables(QS_COLS, QS_ROW, QS_NR, QS_CHI_LO, QS_PER_DEC, QS_ALO, QS_AHI, QS_YLO, QS_YHI, QB_COLS, QB_NR,
+                      QB_CHI_LO, QB_PER_DEC);
+}
+
 // ---------------------------------------------------------------- static workspace
 // Workspace of the allocation-free spectrum entry point: the two ping-pong
 // buffers of the largest FFT it accepts (2^18 points, 8 MiB per device, held
@@ -251,6 +257,8 @@ struct gap_t {
   long long* part2 = nullptr;
   unsigned long long* fscan = nullptr;   // single-pass field: 4 words per block, epoch, done count
   float* tab = nullptr;
+  float* qs = nullptr;     // quantum photon-spectrum table (tubes with GAP_QUANTUM)
+  float* qb = nullptr;     // quantum pair-split table
   int* err = nullptr;
   long long* live = nullptr;
   long long* shard = nullptr;   // [tube][NSHARD][C_N] event counters
@@ -298,6 +306,7 @@ struct gap_t {
   int rmax = 64;                                            // longest re-sort interval the tile margin allows
   bool any_periodic = false;
   bool any_filter = false;
+  bool any_quantum = false;
   double* E0 = nullptr;   // filtered tubes: reference field; Du: E_u - E0 of the step
   double* Du = nullptr;
   int sticky = 0;
@@ -326,6 +335,38 @@ void* dalloc(gap_t* g, size_t bytes) {
     (void)hipMemsetAsync(p, 0, bytes, g->s);
   }
   return p;
+}
+
+// The quantum samplers of the particle passes on given (chi, Philox word)
+// pairs: kind 0 the photon energy fraction, kind 1 the pair's electron
+// fraction.
+__global__ void k_qed_sample(int kind, const float* chi, const uint32_t* w, int64_t n, const float* qs,
+                             const float* qb, float* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = kind == 0 ? qsyn_fraction(chi[i], w[i], qs) : qbw_fraction(chi[i], w[i], qb);
+}
+
+// Device copies of the quantum tables (built once per process on the host).
+int upload_quantum_tables(gap_t* g) {
+  if (g->qs) return GAP_OK;
+  const qtab::Tables& t = quantum_tables();
+  g->qs = (float*)dalloc(g, sizeof(float) * t.syn.size());
+  g->qb = (float*)dalloc(g, sizeof(float) * t.bw.size());
+  if (!g->qs || !g->qb) return GAP_ENOMEM;
+  HIPCHK(hipMemcpyAsync(g->qs, t.syn.data(), sizeof(float) * t.syn.size(), hipMemcpyHostToDevice, g->s));
+  HIPCHK(hipMemcpyAsync(g->qb, t.bw.data(), sizeof(float) * t.bw.size(), hipMemcpyHostToDevice, g->s));
+  HIPCHK(hipStreamSynchronize(g->s));
+  return GAP_OK;
+}
+
+// Returns one allocation of dalloc (the caller has waited for work using it).
+void dfree(gap_t* g, void* p) {
+  if (!p) return;
+  auto it = std::find(g->owned.begin(), g->owned.end(), p);
+  if (it == g->owned.end()) return;
+  g->owned.erase(it);
+  if (g->custom_alloc) g->al.free(p, g->al.ctx);
+  else (void)hipFree(p);
 }
 
 void win_release(gap_t* g);
@@ -434,6 +475,8 @@ Ctx make_ctx(gap_t* g) {
   c.rho = g->rho;
   c.ebar = g->ebar;
   c.tab = g->tab;
+  c.qs = g->qs;
+  c.qb = g->qb;
   c.err = g->err;
   c.shard = g->shard;
   c.pq = g->pq;
@@ -631,14 +674,30 @@ void win_release(gap_t* g) {
 // count rounded up to a multiple of eight (the roles alternate in eights).
 int tails_grid(const gap_t* g) { return 2 * ((g->grid_tail + 7) / 8 * 8); }
 
+// The particle kernels with the quantum branches only for handles that have
+// quantum tubes.
+void launch_leptons(gap_t* g, const Ctx& cx, hipStream_t s) {
+  if (g->any_quantum) k_leptons<true><<<g->grid_lep, TPB, 0, s>>>(cx);
+  else k_leptons<false><<<g->grid_lep, TPB, 0, s>>>(cx);
+}
+void launch_conversions(gap_t* g, const Ctx& cx, hipStream_t s) {
+  const int grid = (g->grid_pho + CONV_SEGS - 1) / CONV_SEGS;
+  if (g->any_quantum) k_conversions<true><<<grid, TPB, 0, s>>>(cx, g->grid_pho);
+  else k_conversions<false><<<grid, TPB, 0, s>>>(cx, g->grid_pho);
+}
+void launch_tails(gap_t* g, const Ctx& cx, hipStream_t s) {
+  if (g->any_quantum) k_tails<true><<<tails_grid(g), TPB, 0, s>>>(cx);
+  else k_tails<false><<<tails_grid(g), TPB, 0, s>>>(cx);
+}
+
 // One step of a window: no merge, no re-sort (slots stay put).
 void enqueue_window_step(gap_t* g) {
   Ctx cx = make_ctx(g);
   k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
-  k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
+  launch_leptons(g, cx, g->s);
   k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-  k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
-  k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx);
+  launch_conversions(g, cx, g->s);
+  launch_tails(g, cx, g->s);
   field_pass(g, 0);
   ++g->host_step;
 }
@@ -822,10 +881,10 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
       k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + j * M, w.tu + j * M, w.wlast, w.meta + j,
                                       w.M, 0, g->err);
       D2D(w.teb + j * (size_t)g->total_nodes, g->ebar, sizeof(float) * g->total_nodes);
-      k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx);
+      launch_leptons(g, cx, g->s);
       k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-      k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, g->s>>>(cx, g->grid_pho);
-      k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx);
+      launch_conversions(g, cx, g->s);
+      launch_tails(g, cx, g->s);
       field_pass(g, 0);
       ++g->host_step;
       D2D(w.tE + (j + 1) * (size_t)g->total_cells, g->E, sizeof(float) * g->total_cells);
@@ -937,14 +996,14 @@ void enqueue_step(gap_t* g, bool more) {
     else k_pre<<<1, PRE_THREADS, 0, ps>>>(cx, g->n_tubes);
   }
   { Timer t(g, KT_PHOTONS, ps); k_photons<<<g->grid_pho, TPB, 0, ps>>>(cx); }
-  { Timer t(g, KT_CONV, ps); k_conversions<<<(g->grid_pho + CONV_SEGS - 1) / CONV_SEGS, TPB, 0, ps>>>(cx, g->grid_pho); }
+  { Timer t(g, KT_CONV, ps); launch_conversions(g, cx, ps); }
   if (two) {
     (void)hipEventRecord(g->ev_p, g->s2);
     g->s2_pending = true;
   }
-  { Timer t(g, KT_LEPTONS); k_leptons<<<g->grid_lep, TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_LEPTONS); launch_leptons(g, cx, g->s); }
   if (two) (void)hipStreamWaitEvent(g->s, g->ev_pre, 0);
-  { Timer t(g, KT_TAILS); k_tails<<<tails_grid(g), TPB, 0, g->s>>>(cx); }
+  { Timer t(g, KT_TAILS); launch_tails(g, cx, g->s); }
   {
     // another step follows at once, with no re-sort or merge in between:
     // its photon side can wait on the field kernel itself
@@ -1096,6 +1155,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     cap_p += q.cap_photons;
     if (q.flags & GAP_PERIODIC) g->any_periodic = true;
     if (q.flags & GAP_FILTER) g->any_filter = true;
+    if (q.flags & GAP_QUANTUM) g->any_quantum = true;
     g->max_cells = std::max(g->max_cells, q.n_cells);
     const int rmax = std::max(1, (int)std::floor((MARGIN - 2) / q.cfl) - 1);
     rmin = std::min(rmin, q.rebucket_every > 0 ? std::min(q.rebucket_every, rmax) : rmax);
@@ -1110,7 +1170,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     int dev = 0, cus = 0, nl = 0, np = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons, TPB, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons<false>, TPB, 0));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
     // defaults measured on the production gap (2e7 particles): one resident
     // round for the lepton pass, four for the photon pass (short ranges keep
@@ -1219,6 +1279,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   HIPCHK(hipMemcpy(g->fb, g->fb_h.data(), sizeof(FBlk) * g->n_fb, hipMemcpyHostToDevice));
   const std::vector<float>& tab = sync_table();
   HIPCHK(hipMemcpy(g->tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+  if (g->any_quantum && (e = upload_quantum_tables(g))) return e;
 
   // initial particles into the lepton tail, then sort and solve the field
   std::vector<long long> off(n_tubes + 1, 0);
@@ -2025,6 +2086,36 @@ int gap_e_spectrum_noalloc(gap_t* g, int32_t tube, double* power, int64_t power_
   }
   k_fft_power<<<grid, 256, 0, g->s>>>(x, M, power);
   return hipGetLastError() == hipSuccess ? GAP_OK : GAP_EDEVICE;
+}
+
+int gap_qed_sample(gap_t* g, int32_t kind, const double* chi, const uint32_t* words, int64_t n, double* out) {
+  if (!g || (kind != 0 && kind != 1) || n < 0 || (n > 0 && (!chi || !words || !out))) return GAP_EINVAL;
+  if (n == 0) return GAP_OK;
+  if (g->sticky) return g->sticky;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(chi[i] >= 0.0) || !std::isfinite(chi[i])) return GAP_EINVAL;
+  int e;
+  if ((e = upload_quantum_tables(g))) return e;
+  float* dchi = (float*)dalloc(g, sizeof(float) * n);
+  uint32_t* dw = (uint32_t*)dalloc(g, sizeof(uint32_t) * n);
+  float* dout = (float*)dalloc(g, sizeof(float) * n);
+  std::vector<float> hchi(chi, chi + n), hout(n);
+  e = GAP_OK;
+  if (!dchi || !dw || !dout) e = GAP_ENOMEM;
+  if (!e && hipMemcpyAsync(dchi, hchi.data(), sizeof(float) * n, hipMemcpyHostToDevice, g->s) != hipSuccess) e = GAP_EDEVICE;
+  if (!e && hipMemcpyAsync(dw, words, sizeof(uint32_t) * n, hipMemcpyHostToDevice, g->s) != hipSuccess) e = GAP_EDEVICE;
+  if (!e) {
+    const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    k_qed_sample<<<grid, 256, 0, g->s>>>(kind, dchi, dw, n, g->qs, g->qb, dout);
+    if (hipMemcpyAsync(hout.data(), dout, sizeof(float) * n, hipMemcpyDeviceToHost, g->s) != hipSuccess ||
+        hipStreamSynchronize(g->s) != hipSuccess)
+      e = GAP_EDEVICE;
+  }
+  (void)hipStreamSynchronize(g->s);
+  for (void* p : {(void*)dchi, (void*)dw, (void*)dout}) dfree(g, p);
+  if (e) return e;
+  for (int64_t i = 0; i < n; ++i) out[i] = hout[i];
+  return GAP_OK;
 }
 
 int gap_sync_inverse_host(const float* r, float* xi, int64_t n) {

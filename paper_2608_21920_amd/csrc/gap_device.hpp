@@ -41,7 +41,7 @@ enum : int {
 enum : uint32_t {
   F_QED_OFF = 1u, F_ETA_CO_OFF = 2u, F_FIELD_FROZEN = 4u, F_RECOIL_OFF = 8u, F_PERIODIC = 16u,
   F_MERGE_ON = 32u, F_TRACK_ALL = 64u, F_ANTI_ALIGNED = 128u, F_CONV_OFF = 1024u, F_EMIT_OFF = 2048u,
-  F_INJ_FIXED = 4096u, F_FILTER = 8192u
+  F_INJ_FIXED = 4096u, F_FILTER = 8192u, F_QUANTUM = 16384u
 };
 
 // sticky device error bits
@@ -192,6 +192,97 @@ __device__ __forceinline__ float sync_sample(float r, const float* __restrict__ 
   float f = t - (float)i;
   const float* h = tab + NTAB + 1;
   return h[i] + f * (h[i + 1] - h[i]);
+}
+
+// ---------------------------------------------------------------- quantum spectra
+// Tables of the quantum-corrected photon spectrum and pair split (tubes with
+// F_QUANTUM), built on the host at initialisation.
+//
+// Photon energy fraction d = x/gamma: column c holds ln z at the rows below,
+// z = 2 d / (3 chi (1 - d)); column 0 is chi = 0 (the classical spectrum),
+// column c >= 1 is chi = QS_CHI_LO 10^((c-1)/QS_PER_DEC).  Rows: r <= 1/2 at
+// ln r uniform on [QS_ALO, ln 1/2] (QS_NR + 1 nodes), r > 1/2 at y = -ln(1-r)
+// uniform on [ln 2, QS_YHI].  ln z is nearly linear in ln r for small r, in
+// ln chi at both ends of the chi range (z -> its classical value as chi -> 0,
+// z ~ 1/chi as chi -> inf), and columns are blended linearly in ln chi
+// (linearly in chi between columns 0 and 1).
+constexpr int QS_NR = 1024;
+constexpr int QS_PER_DEC = 16;
+constexpr int QS_COLS = 1 + 6 * QS_PER_DEC + 1;      // chi = 0 and 1e-3 .. 1e3
+constexpr int QS_ROW = 2 * (QS_NR + 1);
+constexpr float QS_CHI_LO = 1e-3f;
+constexpr float QS_ALO = -17.328679513998633f;       // ln 2^-25, the smallest 24-bit midpoint uniform
+constexpr float QS_AHI = -0.69314718055994531f;      // ln 1/2
+constexpr float QS_YLO = 0.69314718055994531f;       // ln 2
+constexpr float QS_YHI = 17.328679513998633f;        // -ln 2^-25
+// Pair split, electron fraction v: by the symmetry v <-> 1 - v only r <= 1/2
+// is tabulated, as s = w sqrt((1 + chi)/chi), w = 1/2 - v, at q = (2 r)^(1/4)
+// uniform on [0, 1] (QB_NR + 1 nodes); column c is chi = QB_CHI_LO
+// 10^(c/QB_PER_DEC), clamped to the table's range.
+constexpr int QB_NR = 512;
+constexpr int QB_PER_DEC = 16;
+constexpr int QB_COLS = 5 * QB_PER_DEC + 1;           // chi = 1e-2 .. 1e3
+constexpr float QB_CHI_LO = 1e-2f;
+
+__device__ __forceinline__ float qtab_row(const float* __restrict__ col, int i, float f) {
+  return col[i] + f * (col[i + 1] - col[i]);
+}
+
+// 1 - r for the 24-bit midpoint uniform r = unif(w), exact in FP32 (the
+// difference 1 - r formed in FP32 is not: r rounds to 1 for the top word).
+__device__ __forceinline__ float unif_hi(uint32_t w) { return ((float)(0xFFFFFFu - (w >> 8)) + 0.5f) * 5.9604645e-8f; }
+
+// Photon energy fraction of the quantum spectrum at chi for the uniform of
+// the Philox word rw.
+__device__ __forceinline__ float qsyn_fraction(float chi, uint32_t rw, const float* __restrict__ qs) {
+  int c;
+  float fc;
+  if (chi < QS_CHI_LO) {
+    c = 0;
+    fc = chi * (1.0f / QS_CHI_LO);
+  } else {
+    float pc = 1.0f + log2f(chi * (1.0f / QS_CHI_LO)) * (QS_PER_DEC / 3.3219280948873623f);
+    pc = fminf(pc, (float)(QS_COLS - 1));
+    c = min((int)pc, QS_COLS - 2);
+    fc = pc - (float)c;
+  }
+  int half;
+  float t;
+  if ((rw >> 8) < 0x800000u) {          // r < 1/2
+    half = 0;
+    t = (logf(unif(rw)) - QS_ALO) * ((float)QS_NR / (QS_AHI - QS_ALO));
+  } else {
+    half = QS_NR + 1;
+    t = (-logf(unif_hi(rw)) - QS_YLO) * ((float)QS_NR / (QS_YHI - QS_YLO));
+  }
+  t = fminf(fmaxf(t, 0.0f), (float)QS_NR - 1e-3f);
+  const int i = (int)t;
+  const float f = t - (float)i;
+  const float a = qtab_row(qs + c * QS_ROW + half, i, f);
+  const float b = qtab_row(qs + (c + 1) * QS_ROW + half, i, f);
+  const float z = expf(a + fc * (b - a));
+  const float q = 3.0f * chi * z;
+  return q / (2.0f + q);
+}
+
+// Electron energy fraction of a pair created by a photon at chi, for the
+// uniform of the Philox word rw.
+__device__ __forceinline__ float qbw_fraction(float chi, uint32_t rw, const float* __restrict__ qb) {
+  float pc = log2f(fmaxf(chi, QB_CHI_LO) * (1.0f / QB_CHI_LO)) * (QB_PER_DEC / 3.3219280948873623f);
+  pc = fminf(pc, (float)(QB_COLS - 1));
+  const int c = min((int)pc, QB_COLS - 2);
+  const float fc = pc - (float)c;
+  const bool upper = (rw >> 8) >= 0x800000u;
+  const float rr = upper ? unif_hi(rw) : unif(rw);
+  float t = sqrtf(sqrtf(2.0f * rr)) * (float)QB_NR;
+  t = fminf(t, (float)QB_NR - 1e-3f);
+  const int i = (int)t;
+  const float f = t - (float)i;
+  const float a = qtab_row(qb + c * (QB_NR + 1), i, f);
+  const float b = qtab_row(qb + (c + 1) * (QB_NR + 1), i, f);
+  // (below the first column s keeps its small-chi limit; w scales with chi)
+  const float w = (a + fc * (b - a)) * sqrtf(chi / (1.0f + chi));
+  return upper ? 0.5f + w : 0.5f - w;
 }
 
 // ---------------------------------------------------------------- wave utils

@@ -25,6 +25,8 @@ struct Ctx {
   long long* rho;         // node charge accumulator, sum_t (N_t + 1)
   const float* ebar;      // node field, sum_t (N_t + 1)
   const float* tab;       // photon spectrum table
+  const float* qs;        // quantum photon-spectrum table (tubes with F_QUANTUM), else null
+  const float* qb;        // quantum pair-split table
   int* err;
   long long* shard;       // event counters [tube][NSHARD][C_N], summed by the host
   // conversion queue of the sorted photon pass: workgroup b of the photon
@@ -359,12 +361,48 @@ __device__ __forceinline__ float one_minus_exp_neg(float x) {   // 1 - exp(-x), 
   return r;
 }
 
+// Energy of an emitted photon from the Philox word rb: classical x = xi x_c
+// (reading of the spectrum S), or with F_QUANTUM the quantum spectrum's
+// energy fraction at the emitter's chi times its gamma (Sect. 3.1: the mean
+// of this spectrum carries the Gaunt factor g_Q of P_syn into the recoil).
+// gamma and chi are formed from the post-kick momentum with explicit
+// roundings, so that the evaluation and the photon birth agree bit for bit.
+// Q: the kernels are built for handles with quantum tubes (the branch is
+// compiled out of the classical kernels, whose registers it would cost).
+template <bool Q>
+__device__ __forceinline__ float photon_energy(const Ctx& cx, uint32_t flags, uint32_t rb, float xc, float up,
+                                               float lr) {
+  if (Q && (flags & F_QUANTUM)) {
+    const float g = __builtin_amdgcn_sqrtf(__fmaf_rn(up, up, 1.0f));
+    return __fmul_rn(qsyn_fraction(__fmul_rn(__fmul_rn(g, g), lr), rb, cx.qs), g);
+  }
+  return sync_sample(unif(rb), cx.tab) * xc;
+}
+
+// Momenta of the pair a photon of energy |x| along dir creates: halves
+// (reading of the split), or with F_QUANTUM the electron takes the fraction
+// v of the quantum pair spectrum at the photon's chi (Sect. 3.2).
+template <bool Q>
+__device__ __forceinline__ void pair_momenta(const Ctx& cx, uint32_t flags, uint32_t rb, float chi, float x,
+                                             float* ue, float* up) {
+  const float dir = x >= 0.0f ? 1.0f : -1.0f;
+  const float ax = fabsf(x);
+  float ge = 0.5f * ax, gp = ge;
+  if (Q && (flags & F_QUANTUM)) {
+    const float v = qbw_fraction(chi, rb, cx.qb);
+    ge = v * ax;
+    gp = (1.0f - v) * ax;
+  }
+  *ue = dir * sqrtf(fmaxf(ge * ge - 1.0f, 0.0f));
+  *up = dir * sqrtf(fmaxf(gp * gp - 1.0f, 0.0f));
+}
+
 // One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
 // boundaries, deposit, photon births.  UNI: the lane's tile is the
 // wave-uniform tile of a sorted chunk (tube constants come through scalar
 // loads, gather and deposit go through the LDS window); otherwise the lane's
 // own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
-template <bool UNI>
+template <bool UNI, bool Q>
 __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
                            LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out,
                            const Room& proom) {
@@ -422,7 +460,7 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
       for (int j = 0; j < nsub; ++j) {
         u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
         if (bern(r.a, p)) {
-          float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+          float x = fminf(photon_energy<Q>(cx, flags, r.b, xc, upk, k.lr), au);
           au -= x;
           evmask |= 1ull << j;
           ++nev;
@@ -496,7 +534,7 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
         const int j = __ffsll((long long)m) - 1;
         m &= m - 1;
         u4 r = draw(k.seed, id, step, T_EMIT, (uint32_t)j);
-        float x = fminf(sync_sample(unif(r.b), cx.tab) * xc, au);
+        float x = fminf(photon_energy<Q>(cx, flags, r.b, xc, upk, k.lr), au);
         au -= x;
         if (x >= k.x_thr || (flags & F_TRACK_ALL)) {
           if (q < lim) {
@@ -583,6 +621,7 @@ __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long
 // deposit go through an LDS window of the tile.
 // (six waves per SIMD: the register cap spills one value, stored once on
 // entry and reloaded once per chunk)
+template <bool Q>
 __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
   const Room proom = load_room(cx.pc);
   __shared__ long long s_rho[WIN + 2];
@@ -622,7 +661,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float uo;
-      lepton_one<true>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
+      lepton_one<true, Q>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
       w = make_float4(w.y, w.z, w.w, w.x);
       p = make_uint4(p.y, p.z, p.w, po);
       u = make_float4(u.y, u.z, u.w, uo);
@@ -637,6 +676,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
 
 // Lepton pass over the tail (particles appended since the last re-sort):
 // one slot per thread, each lane with its own tile; global gather/deposit.
+template <bool Q>
 __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
   const Room proom = load_room(cx.pc);
   LocalCounts lcn;
@@ -653,7 +693,7 @@ __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
     const float w = cx.L.w[slot];
     const uint32_t pos = cx.L.pos[slot];
     const float u = cx.L.u[slot];
-    lepton_one<false>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
+    lepton_one<false, Q>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
   }
 }
 
@@ -675,10 +715,16 @@ __device__ __forceinline__ float sin_small(float a) {
 // birth.  Below chi_skip the fit gives p < 2^-27, under every 24-bit uniform:
 // 0 is returned and no draw is made.  The age is taken in 32 bits, wrapping
 // like the stored 32-bit birth step.
+__device__ __forceinline__ float photon_chi(int64_t step, float dt, float inv_rc, float b, float x, int32_t n0,
+                                            float* sp_out) {
+  const int32_t age = (int32_t)((uint32_t)step + 1u - (uint32_t)n0);
+  const float sp = fabsf(sin_small((float)age * dt * inv_rc));
+  *sp_out = sp;
+  return fabsf(x) * b * sp;
+}
 __device__ __forceinline__ float photon_prob(const KC& k, float x, int32_t n0) {
-  const int32_t age = (int32_t)((uint32_t)k.step + 1u - (uint32_t)n0);
-  const float sp = fabsf(sin_small((float)age * k.dt * k.inv_rc));
-  const float chi = fabsf(x) * k.b * sp;
+  float sp;
+  const float chi = photon_chi(k.step, k.dt, k.inv_rc, k.b, x, n0, &sp);
   const float p = one_minus_exp_neg(k.conv_k * sp * t_bw(chi));
   return chi > k.chi_skip ? p : 0.0f;
 }
@@ -687,7 +733,7 @@ __device__ __forceinline__ float photon_prob(const KC& k, float x, int32_t n0) {
 // rate alpha_em (b/lambda~) sin(psi) T_BW(x b sin psi), sin(psi) = |sin(s/R~)|.
 // Below chi_skip the fit gives p < 2^-27, under every 24-bit uniform: no
 // draw is needed and none is made.
-template <bool UNI>
+template <bool UNI, bool Q>
 __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, LocalCounts& lcn, float x, uint32_t pos,
                            int32_t n0, uint32_t* pos_out, float* x_out, const Room& lroom) {
   bool alive;
@@ -721,6 +767,7 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   bool eval = false, conv = false;
   float w = 0.0f;
   uint64_t id = 0;
+  uint32_t rsplit = 0;
   if (alive && !dead && !(flags & (F_QED_OFF | F_CONV_OFF))) {
     const float p = photon_prob(k, x, n0);
     if (p > 2.9802322e-8f) {   // below 2^-25 no 24-bit uniform can fall under p
@@ -729,6 +776,7 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
       u4 r = draw<true>(k.seed, id, step, T_CONV, 0);
       conv = bern(r.a, p);
       if (conv) w = cx.P.w[slot];
+      rsplit = r.b;
     }
   }
   if (UNI) {           // the caller stores the chunk's records with vector stores
@@ -744,14 +792,16 @@ __device__ void photon_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
     const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
     const long long lim = lroom.L;
     if (conv) {
-      const float gm = 0.5f * fabsf(x);
-      const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+      float chi = 0.0f, sp;
+      if (Q && (flags & F_QUANTUM)) chi = photon_chi(step, k.dt, k.inv_rc, k.b, x, n0, &sp);
+      float ue, upo;
+      pair_momenta<Q>(cx, flags, rsplit, chi, x, &ue, &upo);
       for (int e = 0; e < 2; ++e) {
         const long long sl = first + e;
         if (sl < lim) {
           const uint32_t s32 = (uint32_t)sl;
           cx.L.pos[s32] = (uint32_t)np;
-          cx.L.u[s32] = up;
+          cx.L.u[s32] = e == 0 ? ue : upo;
           cx.L.w[s32] = e == 0 ? -w : w;
           cx.L.id[s32] = child_id(k.seed, id, step, (uint32_t)e);
           cx.ltt[s32] = tile;
@@ -915,6 +965,7 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 // each segment per thread and round, with all loads issued before the draws.
 constexpr int CONV_SEGS = 2;
 
+template <bool Q>
 __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   const Room lroom = load_room(cx.lc);
   const long long nsc = cx.pc->n_sorted_chunks;
@@ -953,9 +1004,11 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
 #pragma unroll
     for (int j = 0; j < CONV_SEGS; ++j) {
       bool conv = false;
+      uint32_t rsplit = 0;
       if (act[j]) {
         const u4 r = draw<true>(seed[j], id[j], step[j], T_CONV, 0);
         conv = bern(r.a, __uint_as_float(e[j].y));
+        rsplit = r.b;
       }
       if (__ballot(conv)) {
         const uint32_t slot = e[j].x;
@@ -965,15 +1018,18 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
         if (conv) {
           const float x = cx.P.x[slot], w = cx.P.w[slot];
           const uint32_t np = cx.P.pos[slot];
-          const float dir = x >= 0.0f ? 1.0f : -1.0f;
-          const float gm = 0.5f * fabsf(x);
-          const float up = dir * sqrtf(fmaxf(gm * gm - 1.0f, 0.0f));
+          const Tube& T = cx.tubes[e[j].w];
+          const uint32_t tflags = (uint32_t)T.flags;
+          float chi = 0.0f, sp;
+          if (Q && (tflags & F_QUANTUM)) chi = photon_chi(step[j], T.dt, T.inv_rc, T.b, x, cx.P.n0[slot], &sp);
+          float ue, upo;
+          pair_momenta<Q>(cx, tflags, rsplit, chi, x, &ue, &upo);
           for (int b = 0; b < 2; ++b) {
             const long long sl = first + b;
             if (sl < lroom.L) {
               const uint32_t s32 = (uint32_t)sl;
               cx.L.pos[s32] = np;
-              cx.L.u[s32] = up;
+              cx.L.u[s32] = b == 0 ? ue : upo;
               cx.L.w[s32] = b == 0 ? -w : w;
               cx.L.id[s32] = child_id(seed[j], id[j], step[j], (uint32_t)b);
               cx.ltt[s32] = (int32_t)e[j].z;
@@ -989,6 +1045,7 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   }
 }
 
+template <bool Q>
 __device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
   const Room lroom = load_room(cx.lc);
   LocalCounts lcn;
@@ -1005,7 +1062,7 @@ __device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
     const float x = cx.P.x[slot];
     const uint32_t pos = cx.P.pos[slot];
     const int32_t n0 = cx.P.n0[slot];
-    photon_one<false>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr, lroom);
+    photon_one<false, Q>(cx, slot, tile, kc0, lcn, x, pos, n0, nullptr, nullptr, lroom);
   }
 }
 
@@ -1015,12 +1072,13 @@ __device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
 // Workgroups alternate roles in groups of eight, so both species spread over
 // every XCD; the grid is a multiple of 16, so each role gets half of it with
 // indexes 0 .. half - 1.
+template <bool Q>
 __global__ __launch_bounds__(TPB) void k_tails(Ctx cx) {
   const int bx = blockIdx.x;
   const int bid = ((bx >> 4) << 3) | (bx & 7);
   const int nblk = (int)(gridDim.x >> 1);
-  if ((bx >> 3) & 1) photons_tail(cx, bid, nblk);
-  else leptons_tail(cx, bid, nblk);
+  if ((bx >> 3) & 1) photons_tail<Q>(cx, bid, nblk);
+  else leptons_tail<Q>(cx, bid, nblk);
 }
 
 // ------------------------------------------------------------------ field

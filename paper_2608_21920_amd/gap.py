@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libgap.so")
 
 QED_OFF, ETA_CO_OFF, FIELD_FROZEN, RECOIL_OFF, PERIODIC, MERGE_ON, TRACK_ALL, ANTI_ALIGNED = \
     1, 2, 4, 8, 16, 32, 64, 128
-CONV_OFF, EMIT_OFF, INJ_FIXED, FILTER = 1024, 2048, 4096, 8192
+CONV_OFF, EMIT_OFF, INJ_FIXED, FILTER, QUANTUM = 1024, 2048, 4096, 8192, 16384
 FLAGS = dict(QED_OFF=1, ETA_CO_OFF=2, FIELD_FROZEN=4, RECOIL_OFF=8, PERIODIC=16, MERGE_ON=32, TRACK_ALL=64,
-             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096, FILTER=8192)
+             ANTI_ALIGNED=128, CONV_OFF=1024, EMIT_OFF=2048, INJ_FIXED=4096, FILTER=8192, QUANTUM=16384)
 
 ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "GAP_ETILE", -5: "GAP_ENAN",
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
@@ -118,6 +118,8 @@ def load_library():
     lib.gap_backward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.gap_e_spectrum_noalloc.restype = C.c_int
     lib.gap_e_spectrum_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]
+    lib.gap_qed_sample.restype = C.c_int
+    lib.gap_qed_sample.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     lib.gap_sync_inverse_host.restype = C.c_int
     lib.gap_sync_inverse_host.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
     _lib = lib
@@ -338,6 +340,17 @@ class Gap:
         nothing (gap_e_spectrum_noalloc)."""
         _check(self.lib.gap_e_spectrum_noalloc(self.h, int(tube), C.c_void_p(power.data_ptr()), int(power.numel())),
                "gap_e_spectrum_noalloc")
+
+    def qed_sample(self, kind: int, chi, words) -> np.ndarray:
+        """The device's quantum samplers at given points (gap_qed_sample):
+        kind 0 the photon energy fraction x/gamma, kind 1 the pair electron's
+        energy fraction, at quantum parameter chi for the Philox word."""
+        words = np.ascontiguousarray(np.atleast_1d(words), dtype=np.uint32)
+        chi = np.ascontiguousarray(np.broadcast_to(np.asarray(chi, np.float64), words.shape))
+        out = np.empty(words.shape, np.float64)
+        _check(self.lib.gap_qed_sample(self.h, int(kind), chi.ctypes.data, words.ctypes.data, words.size,
+                                       out.ctypes.data), "gap_qed_sample")
+        return out
 
     def set_launch(self, grid_leptons: int, grid_photons: int, grid_tails: int, resort_every: int):
         """Launch shapes and re-sort interval (the keys autotune() returns)."""

@@ -64,6 +64,8 @@ def test_null_arguments():
     assert lib.gap_init(C.byref(p), 0, None, None, C.byref(h)) == -1
     assert lib.gap_step(None, 1) == -1
     assert lib.gap_sync(None) == -1
+    chi, w, out = np.ones(2), np.zeros(2, np.uint32), np.zeros(2)
+    assert lib.gap_qed_sample(None, 0, chi.ctypes.data, w.ctypes.data, 2, out.ctypes.data) == -1
 
 
 def test_host_sampler_matches_oracle_cdf():
