@@ -62,6 +62,9 @@
 #define TAG_CHILD 6u
 
 #define INJ_ID_BASE (1ull << 62)
+#define ATM_ID_BASE (3ull << 61)
+#define TAG_ATM   7u
+#define ORC_MASS_P 1836.0      /* proton to electron mass ratio (Sect. 6.1) */
 
 /* error codes */
 #define ORC_OK     0
@@ -88,6 +91,9 @@ typedef struct {
   int32_t nsub_max;      /* sub-cycling cap */
   int32_t merge_every;   /* merge check period (steps) */
   int32_t pad_;
+  double atm_temp;       /* atmosphere temperature k_B T / (m_e c^2) */
+  int32_t atm_ppc;       /* atmosphere: electrons and protons kept in cell 0 (0: none) */
+  int32_t pad2_;
 } orc_params;
 
 typedef struct { int32_t cell; double xi, u, w; uint64_t id; } olep;
@@ -106,6 +112,7 @@ typedef struct {
   /* state */
   olep* lep; int64_t nlep, lep_alloc;
   opho* pho; int64_t npho, pho_alloc;
+  olep* pro; int64_t npro, pro_alloc;   /* protons (charge +1, mass ORC_MASS_P) */
   double* E;     /* E at cell centres k+1/2, k = 0..N-1 */
   double* E0;    /* filtered runs: the field when the state was last set */
   double* Eb;    /* node field, nodes 0..N */
@@ -120,6 +127,9 @@ typedef struct {
   /* counters */
   int64_t n_emit, n_pho_born, n_conv, n_absorbed, n_outflow, n_pho_exit, n_dropped, n_merged;
   int64_t n_emit_eval, n_conv_eval;
+  int64_t n_pro_absorbed, n_pro_outflow, n_atm_e, n_atm_p;
+  int64_t atm_prev[2];   /* electrons / protons in cell 0 after the last push */
+  uint64_t atm_count;    /* atmosphere particles created (their ids) */
   double e_rad;  /* radiated energy (m_e c^2 units, weighted) */
   /* return flux (Sect. 5, Fig. 7): weight of the leptons absorbed at h = 0
    * per 1/8 decade of gamma in [1, 1e8), then total weight and weight x gamma */
@@ -475,6 +485,16 @@ static int push_lep(orc_sim* s, olep l) {
   return 1;
 }
 
+static int push_pro(orc_sim* s, olep l) {
+  if (s->npro >= s->p.cap_leptons) { s->n_dropped++; s->err = ORC_ECAP; return 0; }
+  if (s->npro == s->pro_alloc) {
+    s->pro_alloc = s->pro_alloc ? 2 * s->pro_alloc : 1024;
+    s->pro = (olep*)realloc(s->pro, sizeof(olep) * s->pro_alloc);
+  }
+  s->pro[s->npro++] = l;
+  return 1;
+}
+
 static int push_pho(orc_sim* s, opho g) {
   if (s->npho >= s->p.cap_photons) { s->n_dropped++; s->err = ORC_ECAP; return 0; }
   if (s->npho == s->pho_alloc) {
@@ -519,6 +539,7 @@ static void deposit_one(orc_sim* s, int32_t k, double xi, double w) {
 static void deposit_all(orc_sim* s) {
   memset(s->rho, 0, sizeof(int64_t) * (s->N + 1));
   for (int64_t i = 0; i < s->nlep; ++i) deposit_one(s, s->lep[i].cell, s->lep[i].xi, s->lep[i].w);
+  for (int64_t i = 0; i < s->npro; ++i) deposit_one(s, s->pro[i].cell, s->pro[i].xi, s->pro[i].w);
 }
 
 /* Gauss's law, dE/dh = rho - eta_co, integrated from the surface:
@@ -604,7 +625,7 @@ static void init_particles(orc_sim* s) {
   double sign[2] = {-1.0, 1.0};
   if (p->init_kind == 0) { k_lo = (int)ceil(s->H / p->dx - 1e-9); nspecies = 1; }
   else if (p->init_kind == 1) nspecies = 2;
-  else if (p->init_kind == 3) nspecies = 1;
+  else if (p->init_kind == 3 || p->init_kind == 4) nspecies = 1;
   uint64_t id = 1;
   for (int sp = 0; sp < nspecies; ++sp)
     for (int k = k_lo; k < N; ++k)
@@ -614,6 +635,84 @@ static void init_particles(orc_sim* s) {
         olep l = {k, xi24(r[0]), p->u_init, sign[sp], id};
         push_lep(s, l);
       }
+  /* kind 4 (Sect. 6.1 initial condition with protons): electrons everywhere
+   * and as many protons below H, so that eta = 0 below H and eta_co above */
+  if (p->init_kind == 4) {
+    int k_h = (int)ceil(s->H / p->dx - 1e-9);
+    if (k_h > N) k_h = N;
+    for (int k = 0; k < k_h; ++k)
+      for (int j = 0; j < p->ppc_init; ++j, ++id) {
+        uint32_t r[4];
+        draw(p->seed, id, 0, TAG_INIT, 0, r);
+        olep l = {k, xi24(r[0]), p->u_init, 1.0, id};
+        push_pro(s, l);
+      }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Thermal atmosphere (Sect. 2.3 atmospheric boundary; Sect. 6.1:        */
+/* k_B T / m_e c^2 = 0.3, protons with m_p / m_e = 1836).                */
+/* Reading: the atmosphere is a reservoir in cell 0 holding atm_ppc      */
+/* electrons and atm_ppc protons (weight 1 each): every step, before     */
+/* the push, each species is refilled to atm_ppc from the count left in  */
+/* cell 0 by the previous push; new particles are uniform in the cell,   */
+/* with momenta of the one-dimensional relativistic thermal distribution */
+/* f(u) ~ exp(-gamma / Theta), Theta = k_B T / (m c^2) of the species.   */
+/* The charge they bring leaves the star (surface field bookkeeping as   */
+/* for the injected electrons).                                          */
+/* ------------------------------------------------------------------ */
+/* One momentum of f(u) ~ exp(-gamma/Theta) by rejection.  In the kinetic
+ * energy e = gamma - 1 the density is exp(-e/Theta) h(e), h = (1+e) /
+ * sqrt(e (2+e)) <= 1/sqrt(2e) + 1; the envelope exp(-e/Theta) (1/sqrt(2e)
+ * + 1) is a mixture of e = Theta Z^2/2 (Z standard normal, Box-Muller) of
+ * weight sqrt(pi Theta / 2) and e = -Theta ln U of weight Theta.  Attempt j
+ * uses the words of draw(seed, id, step, TAG_ATM, j): u24 of word 0 picks
+ * the component, words 1 and 2 make e, word 3 accepts with probability
+ * h/(1/sqrt(2e) + 1), and bit 0 of word 0 gives the sign of u.  After 64
+ * rejections (probability below 1e-30) u = 0. */
+double orc_atm_momentum(uint64_t seed, uint64_t id, int64_t step, double theta) {
+  const double wa = sqrt(ORC_PI * theta / 2.0), wb = theta;
+  for (uint32_t j = 0; j < 64; ++j) {
+    uint32_t r[4];
+    draw(seed, id, step, TAG_ATM, j, r);
+    double e;
+    if (u24(r[0]) * (wa + wb) < wa) {
+      double c = cos(2.0 * ORC_PI * u24(r[2]));
+      e = -theta * log(u24(r[1])) * c * c;
+    } else {
+      e = -theta * log(u24(r[1]));
+    }
+    if (!(e > 0.0)) continue;
+    double h = (1.0 + e) / sqrt(e * (2.0 + e));
+    double bnd = 1.0 / sqrt(2.0 * e) + 1.0;
+    if (u24(r[3]) * bnd < h) {
+      double u = sqrt(e * (2.0 + e));
+      return (r[0] & 1u) ? u : -u;
+    }
+  }
+  return 0.0;
+}
+
+static void atmosphere_refill(orc_sim* s, int64_t n) {
+  const orc_params* p = &s->p;
+  for (int sp = 0; sp < 2; ++sp) {
+    int64_t m = (int64_t)p->atm_ppc - s->atm_prev[sp];
+    double theta = sp == 0 ? p->atm_temp : p->atm_temp / ORC_MASS_P;
+    for (int64_t j = 0; j < m; ++j) {
+      uint64_t id = ATM_ID_BASE + s->atm_count++;
+      uint32_t r[4];
+      draw(p->seed, id, n, TAG_ATM, 0xFFFFu, r);
+      double u = orc_atm_momentum(p->seed, id, n, theta);
+      if (sp == 0) {
+        olep l = {0, xi24(r[0]), u, -1.0, id};
+        if (push_lep(s, l)) { s->dq += wt_fixed(1.0); s->n_atm_e++; }
+      } else {
+        olep l = {0, xi24(r[0]), u, 1.0, id};
+        if (push_pro(s, l)) { s->dq -= wt_fixed(1.0); s->n_atm_p++; }
+      }
+    }
+  }
 }
 
 orc_sim* orc_create(const orc_params* p, int32_t* err) {
@@ -629,6 +728,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
   s->rho = (int64_t*)calloc(s->N + 1, sizeof(int64_t));
   sync_nodes(s);
   init_particles(s);
+  s->atm_prev[0] = s->atm_prev[1] = s->p.atm_ppc;   /* no refill before the first push */
   s->Es = 0.0;
   deposit_all(s);
   field_from_rho(s);
@@ -640,7 +740,7 @@ orc_sim* orc_create(const orc_params* p, int32_t* err) {
 
 void orc_free(orc_sim* s) {
   if (!s) return;
-  free(s->lep); free(s->pho); free(s->E); free(s->E0); free(s->Eb); free(s->rho); free(s->ev);
+  free(s->lep); free(s->pho); free(s->pro); free(s->E); free(s->E0); free(s->Eb); free(s->rho); free(s->ev);
   free(s->q_cosh); free(s->q_g); free((void*)s->rep);
   free(s);
 }
@@ -834,6 +934,9 @@ static void step_once(orc_sim* s) {
     if ((double)s->npho > p->merge_frac * (double)p->cap_photons) merge_photons(s);
   }
 
+  /* (1a) the thermal atmosphere refills cell 0 */
+  if (p->atm_ppc > 0 && !periodic) atmosphere_refill(s, n);
+
   /* (1) surface injection of cold electrons into cell 0 (Sect. 2.3: the
    * atmosphere supplies charges; here a deterministic accumulator). */
   if (p->inj_rate > 0.0 && !periodic) {
@@ -851,6 +954,7 @@ static void step_once(orc_sim* s) {
 
   /* (2) leptons: gather + kick, emission, drift, boundaries, deposit */
   memset(s->rho, 0, sizeof(int64_t) * (N + 1));
+  s->atm_prev[0] = s->atm_prev[1] = 0;
   int64_t nl = s->nlep;
   int64_t npho0 = s->npho;
   pending_ph pend[64];
@@ -926,6 +1030,7 @@ static void step_once(orc_sim* s) {
       l->w = 0.0;
       continue;
     }
+    if (l->w < 0.0 && l->cell == 0) s->atm_prev[0]++;
     double hn = (l->cell + l->xi) * p->dx;
     for (int j = 0; j < npend; ++j) {
       if (hn < s->H) {
@@ -938,6 +1043,31 @@ static void step_once(orc_sim* s) {
       }
     }
     deposit_one(s, l->cell, l->xi, l->w);
+  }
+
+  /* (2c) protons (Sect. 6.1: charge +1, m_p/m_e = 1836; no QED): kick
+   * du/dt = E / 1836, drift dh/dt = u / gamma, boundaries, deposit */
+  for (int64_t i = 0; i < s->npro; ++i) {
+    olep* q = &s->pro[i];
+    double Ep = (1.0 - q->xi) * s->Eb[q->cell] + q->xi * s->Eb[q->cell + 1];
+    q->u += Ep * s->dt / ORC_MASS_P;
+    double disp = q->u / sqrt(1.0 + q->u * q->u) * p->cfl;
+    q->xi += disp;
+    s->dcur += fabs(q->w) * disp;
+    wrap_cell(s, &q->cell, &q->xi);
+    if (!periodic && q->cell < 0) {
+      s->dq += wt_fixed(q->w);
+      s->n_pro_absorbed++;
+      q->w = 0.0;
+      continue;
+    }
+    if (!periodic && q->cell >= N) {
+      s->n_pro_outflow++;
+      q->w = 0.0;
+      continue;
+    }
+    if (q->cell == 0) s->atm_prev[1]++;
+    deposit_one(s, q->cell, q->xi, q->w);
   }
 
   /* (2b) frozen realisation: the recorded photon births of this step, with
@@ -1007,6 +1137,9 @@ static void step_once(orc_sim* s) {
     j = 0;
     for (int64_t i = 0; i < s->npho; ++i) if (s->pho[i].w != 0.0) s->pho[j++] = s->pho[i];
     s->npho = j;
+    j = 0;
+    for (int64_t i = 0; i < s->npro; ++i) if (s->pro[i].w != 0.0) s->pro[j++] = s->pro[i];
+    s->npro = j;
   }
 
   /* (4) field: Ampere drive and surface flux enter through E_s, then Gauss */
@@ -1080,6 +1213,7 @@ int32_t orc_set_state(orc_sim* s, int64_t nl, const int32_t* cell, const double*
                       const double* pxi, const double* px, const double* pw, const int64_t* pn0,
                       const uint64_t* pid, double Es, int64_t step) {
   s->nlep = 0; s->npho = 0;
+  s->atm_prev[0] = s->atm_prev[1] = s->p.atm_ppc;
   for (int64_t i = 0; i < nl; ++i) { olep l = {cell[i], xi[i], u[i], w[i], id[i]}; push_lep(s, l); }
   for (int64_t i = 0; i < np; ++i) { opho g = {pcell[i], pxi[i], px[i], pw[i], pn0[i], pid[i]}; push_pho(s, g); }
   s->Es = Es;
@@ -1090,6 +1224,30 @@ int32_t orc_set_state(orc_sim* s, int64_t nl, const int32_t* cell, const double*
   memcpy(s->E0, s->E, sizeof(double) * s->N);
   node_field(s);
   return s->err;
+}
+
+/* Protons: counts, state and replacement (the field is re-solved). */
+void orc_proton_counts(const orc_sim* s, int64_t out[8]) {
+  out[0] = s->npro; out[1] = s->n_pro_absorbed; out[2] = s->n_pro_outflow; out[3] = s->n_atm_e;
+  out[4] = s->n_atm_p; out[5] = s->atm_prev[0]; out[6] = s->atm_prev[1]; out[7] = (int64_t)s->atm_count;
+}
+void orc_get_protons(const orc_sim* s, int32_t* cell, double* xi, double* u, double* w, uint64_t* id) {
+  for (int64_t i = 0; i < s->npro; ++i) {
+    cell[i] = s->pro[i].cell; xi[i] = s->pro[i].xi; u[i] = s->pro[i].u; w[i] = s->pro[i].w; id[i] = s->pro[i].id;
+  }
+}
+int32_t orc_set_protons(orc_sim* s, int64_t n, const int32_t* cell, const double* xi, const double* u,
+                        const double* w, const uint64_t* id) {
+  s->npro = 0;
+  for (int64_t i = 0; i < n; ++i) { olep l = {cell[i], xi[i], u[i], w[i], id[i]}; push_pro(s, l); }
+  deposit_all(s);
+  field_from_rho(s);
+  memcpy(s->E0, s->E, sizeof(double) * s->N);
+  node_field(s);
+  return s->err;
+}
+void orc_set_atmosphere(orc_sim* s, int64_t prev_e, int64_t prev_p, uint64_t count) {
+  s->atm_prev[0] = prev_e; s->atm_prev[1] = prev_p; s->atm_count = count;
 }
 
 /* Overwrite the cell field (FIELD_FROZEN tests). */

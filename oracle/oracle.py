@@ -43,6 +43,7 @@ class OracleParams(C.Structure):
         ("xc_floor", C.c_double), ("u_init", C.c_double), ("merge_frac", C.c_double),
         ("seed", C.c_uint64), ("cap_leptons", C.c_int64), ("cap_photons", C.c_int64),
         ("flags", C.c_uint32), ("nsub_max", C.c_int32), ("merge_every", C.c_int32), ("pad_", C.c_int32),
+        ("atm_temp", C.c_double), ("atm_ppc", C.c_int32), ("pad2_", C.c_int32),
     ]
 
 
@@ -51,6 +52,7 @@ _DEFAULTS = dict(
     r_curv_cm=1e7, period_s=1.0, lambda_c_scale=1.0, r_curv_scale=1.0, h_gap_frac=0.8,
     inj_rate=0.0, inj_weight=1.0, x_thr=2.0, xc_floor=1e-2, u_init=0.0, merge_frac=0.9,
     seed=0, cap_leptons=1 << 40, cap_photons=1 << 40, flags=0, nsub_max=64, merge_every=64,
+    atm_temp=0.3, atm_ppc=0,
 )
 
 
@@ -89,6 +91,13 @@ def _load():
             getattr(lib, f).argtypes = [C.c_void_p, C.c_void_p]
         lib.orc_rho.argtypes = [C.c_void_p, C.c_void_p]
         lib.orc_get_leptons.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+        lib.orc_get_protons.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+        lib.orc_set_protons.restype = C.c_int32
+        lib.orc_set_protons.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 5
+        lib.orc_proton_counts.argtypes = [C.c_void_p, P(C.c_int64)]
+        lib.orc_set_atmosphere.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64]
+        lib.orc_atm_momentum.restype = C.c_double
+        lib.orc_atm_momentum.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_double]
         lib.orc_get_photons.argtypes = [C.c_void_p] + [C.c_void_p] * 6
         lib.orc_get_events.argtypes = [C.c_void_p] + [C.c_void_p] * 8
         lib.orc_set_state.restype = C.c_int32
@@ -142,6 +151,12 @@ def tsyn(chi: float) -> float:
 
 def tbw(chi: float) -> float:
     return _load().orc_tbw(chi)
+
+
+def atm_momentum(seed: int, pid: int, step: int, theta: float) -> float:
+    """Momentum u of an atmosphere particle drawn from the one-dimensional
+    relativistic thermal distribution exp(-gamma/Theta) (Sect. 6.1)."""
+    return _load().orc_atm_momentum(int(seed), int(pid), int(step), float(theta))
 
 
 def sync_cdf(xi: float) -> float:
@@ -272,6 +287,30 @@ class Oracle:
                  id=np.empty(n, np.uint64))
         self.lib.orc_get_leptons(self.h, *[_ptr(a[k]) for k in ("cell", "xi", "u", "w", "id")])
         return a
+
+    def proton_counts(self) -> dict:
+        o = (C.c_int64 * 8)()
+        self.lib.orc_proton_counts(self.h, o)
+        keys = ["n_pro", "n_pro_absorbed", "n_pro_outflow", "n_atm_e", "n_atm_p", "atm_prev_e", "atm_prev_p",
+                "atm_count"]
+        return dict(zip(keys, [int(v) for v in o]))
+
+    def protons(self) -> dict:
+        n = self.proton_counts()["n_pro"]
+        a = dict(cell=np.empty(n, np.int32), xi=np.empty(n), u=np.empty(n), w=np.empty(n),
+                 id=np.empty(n, np.uint64))
+        self.lib.orc_get_protons(self.h, *[_ptr(a[k]) for k in ("cell", "xi", "u", "w", "id")])
+        return a
+
+    def set_protons(self, pro: dict) -> int:
+        A = {k: np.ascontiguousarray(pro[k], dtype=dt) for k, dt in (("cell", np.int32), ("xi", np.float64),
+                                                                      ("u", np.float64), ("w", np.float64),
+                                                                      ("id", np.uint64))}
+        self._keep_pro = A
+        return self.lib.orc_set_protons(self.h, A["cell"].size, *[_ptr(A[k]) for k in ("cell", "xi", "u", "w", "id")])
+
+    def set_atmosphere(self, prev_e: int, prev_p: int, count: int) -> None:
+        self.lib.orc_set_atmosphere(self.h, int(prev_e), int(prev_p), int(count))
 
     def photons(self) -> dict:
         n = self.counts()["n_pho"]

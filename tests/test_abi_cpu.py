@@ -35,7 +35,7 @@ def test_params_struct_matches_header():
     fields = re.findall(r"^\s*(?:int32_t|uint32_t|int64_t|uint64_t|double)\s+([\w, ]+);", body, re.M)
     names = [n.strip() for f in fields for n in f.split(",")]
     assert names == [f[0] for f in G.GapParams._fields_]
-    assert C.sizeof(G.GapParams) == 8 * 4 // 2 + 8 * 15 + 8 + 16 + 16
+    assert C.sizeof(G.GapParams) == 8 * 4 // 2 + 8 * 15 + 8 + 16 + 16 + 16
 
 
 def test_strerror():
@@ -45,7 +45,9 @@ def test_strerror():
 
 
 @pytest.mark.parametrize("bad", [dict(n_cells=1), dict(cfl=1.0), dict(cfl=0.0), dict(ppc_ref=0), dict(b=0.0),
-                                 dict(nsub_max=0), dict(init_kind=7), dict(inj_weight=0.0), dict(cap_leptons=0)])
+                                 dict(nsub_max=0), dict(init_kind=7), dict(inj_weight=0.0), dict(cap_leptons=0),
+                                 dict(atm_ppc=-1), dict(atm_ppc=4, atm_temp=0.0), dict(atm_ppc=4, flags=16),
+                                 dict(init_kind=4, flags=16)])
 def test_invalid_params_rejected_on_host(bad):
     lib = _lib()
     cfg = dict(n_cells=64)
