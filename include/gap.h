@@ -90,6 +90,10 @@ extern "C" {
 #define GAP_INIT_UNIFORM  1  /* ppc_init electrons and ppc_init positrons in every cell */
 #define GAP_INIT_EMPTY    2  /* no particles                                            */
 #define GAP_INIT_ELECTRON 3  /* ppc_init electrons in every cell                        */
+#define GAP_INIT_ATMOSPHERE 4 /* Sect. 6.1 initial state: ppc_init electrons in every cell
+                                and ppc_init protons (weight 1, at rest) in every cell
+                                below H, so that the charge is 0 below H and the
+                                co-rotation charge above; not with GAP_PERIODIC     */
 
 /* Physical inputs of one flux tube (the statement of the problem in Sects.
  * 2-3 and 6.1: grid, alpha, B/B_Q, curvature radius, injection, QED knobs). */
@@ -121,6 +125,19 @@ typedef struct gap_params {
   int32_t merge_every;    /* steps between merge checks                                */
   int32_t rebucket_every; /* steps between re-sorts of the stores (0 = the longest the
                              tile margin allows, (64 - 2)/cfl - 1 steps)                */
+  double atm_temp;        /* thermal atmosphere: k_B T / (m_e c^2) of its particles (the
+                             paper's 0.3); protons at the same temperature           */
+  int32_t atm_ppc;        /* thermal atmosphere (Sect. 2.3, 6.1): 0 = none; else before
+                             every push cell 0 is refilled to atm_ppc electrons and
+                             atm_ppc protons (weight 1 each) from the count the previous
+                             push left there, new particles uniform in the cell with
+                             momenta from the 1D relativistic thermal distribution
+                             exp(-gamma/Theta), Theta = atm_temp m_e/m, the charge they
+                             bring taken from the star.  Protons (charge +1, m_p/m_e =
+                             1836, no QED) are pushed by the field like the leptons,
+                             absorbed at h = 0 and free to leave at h = L.  Not with
+                             GAP_PERIODIC, nor with the differentiable window      */
+  int32_t pad_atm;
 } gap_params;
 
 /* Optional device allocator (e.g. backed by torch's caching allocator). */
@@ -197,6 +214,9 @@ int gap_sync(gap_t* g);
                                   and signed momentum column: 90 + b for p > 0 and 89 - b
                                   for p <= 0 (p = u, photons x), b the spectrum bin of |p|;
                                   the first call for a bin width allocates device memory  */
+#define GAP_DIAG_PROTONS 17    /* n x {int32 cell, uint32 frac24, float u, float w, uint64 id}:
+                                  the tube's live protons (none without an atmosphere or the
+                                  proton initial state)                                  */
 #define GAP_DIAG_LAUNCH  16    /* int32[4]: the handle's launch shape, as GAP_STATE_LAUNCH sets it
                                   (workgroups of the sorted lepton pass, of the sorted photon
                                   pass and of the tail passes, re-sort interval; tube ignored) */
@@ -236,6 +256,11 @@ int gap_sync(gap_t* g);
 #define GAP_C_EMIT_EVAL_TAIL 19  /* part of GAP_C_EMIT_EVAL taken by the tail pass   */
 #define GAP_C_PHO_STEPS_TAIL 20  /* part of GAP_C_PHO_STEPS taken by the tail pass   */
 #define GAP_C_CONV_EVAL_TAIL 21  /* part of GAP_C_CONV_EVAL taken by the tail pass   */
+#define GAP_C_PROTONS     22  /* live protons                      */
+#define GAP_C_PRO_ABSORBED 23 /* protons absorbed at h = 0         */
+#define GAP_C_PRO_OUTFLOW 24  /* protons leaving at h = L          */
+#define GAP_C_ATM_E       25  /* electrons the atmosphere supplied */
+#define GAP_C_ATM_P       26  /* protons the atmosphere supplied   */
 
 /* Copy a diagnostic of tube `tube` into host_buf (buf_bytes long); waits for
  * queued work.  *bytes_written receives the size used.  GAP_EINVAL if the
@@ -262,6 +287,15 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
                                   stops recording and frees the record.  Allocates device
                                   memory (GAP_ENOMEM if it cannot), drops a captured graph,
                                   waits for queued work and empties the record              */
+#define GAP_STATE_PROTONS  10  /* int64 n, then n records as GAP_DIAG_PROTONS: the protons of
+                                  the (single) tube, replacing all; the field is re-solved
+                                  (FIELD_FROZEN: only the node charge).  GAP_ESTATE without
+                                  proton storage (no atmosphere, no proton initial state) */
+#define GAP_STATE_ATMOSPHERE 11 /* int32 electrons, int32 protons, uint64 count: what the last
+                                  push left in cell 0 (the next refill tops up to atm_ppc)
+                                  and the atmosphere particles made so far (their ids).
+                                  Setting particles, protons or the step resets the counts
+                                  to atm_ppc (no refill before the next push)           */
 #define GAP_STATE_RAISE     9  /* int32 bits: OR them into the device error word, as a kernel
                                   that meets the condition does (1 store overflow -> GAP_ECAP,
                                   2 particle outside its tile window -> GAP_ETILE, 4 non-finite

@@ -7,6 +7,7 @@
 #include "gap_adjoint.hpp"
 #include "gap_diag.hpp"
 #include "gap_qtab.hpp"
+#include "gap_protons.hpp"
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -307,6 +308,12 @@ struct gap_t {
   bool any_periodic = false;
   bool any_filter = false;
   bool any_quantum = false;
+  bool any_protons = false;   // a tube with an atmosphere or the proton initial state
+  bool any_atm = false;       // a tube with a thermal atmosphere
+  ProBuf pr[2]{};             // protons (double buffer for the compaction at re-sorts)
+  int pr_cur = 0;
+  long long* pr_n = nullptr;  // device: proton slots in use
+  int64_t pr_cap = 0;
   double* E0 = nullptr;   // filtered tubes: reference field; Du: E_u - E0 of the step
   double* Du = nullptr;
   int sticky = 0;
@@ -315,7 +322,7 @@ struct gap_t {
   WinState win;
   hipGraphExec_t gexec = nullptr;
   int64_t gsteps = -1;
-  int gs_l = -1, gs_p = -1, ge_l = -1, ge_p = -1;
+  int gs_l = -1, gs_p = -1, ge_l = -1, ge_p = -1, gs_r = -1, ge_r = -1;
   int64_t gs_since = -1, ge_since = -1, gs_step = -1;
 };
 
@@ -420,7 +427,10 @@ int validate(const gap_params& p) {
   if (!(p.b > 0) || !(p.r_curv_cm > 0) || !(p.period_s > 0)) return GAP_EINVAL;
   if (!(p.lambda_c_scale > 0) || !(p.r_curv_scale > 0)) return GAP_EINVAL;
   if (!(p.h_gap_frac >= 0)) return GAP_EINVAL;
-  if (p.init_kind < 0 || p.init_kind > 3) return GAP_EINVAL;
+  if (p.init_kind < 0 || p.init_kind > GAP_INIT_ATMOSPHERE) return GAP_EINVAL;
+  if (p.atm_ppc < 0 || p.atm_ppc > (1 << 20)) return GAP_EINVAL;
+  if (p.atm_ppc > 0 && (!(p.atm_temp > 0) || !std::isfinite(p.atm_temp))) return GAP_EINVAL;
+  if ((p.atm_ppc > 0 || p.init_kind == GAP_INIT_ATMOSPHERE) && (p.flags & GAP_PERIODIC)) return GAP_EINVAL;
   if (!(p.inj_rate >= 0) || !(p.inj_weight > 0) || p.inj_weight >= 65536.0) return GAP_EINVAL;
   if (p.cap_leptons < 1 || p.cap_photons < 1) return GAP_EINVAL;
   if (p.nsub_max < 1 || p.nsub_max > 64) return GAP_EINVAL;
@@ -455,7 +465,25 @@ int64_t init_count(const gap_params& p, const Derived& d) {
     case GAP_INIT_GAP: return ncell * p.ppc_init;
     case GAP_INIT_UNIFORM: return 2 * ncell * p.ppc_init;
     case GAP_INIT_ELECTRON: return ncell * p.ppc_init;
+    case GAP_INIT_ATMOSPHERE: return ncell * p.ppc_init;
     default: return 0;
+  }
+}
+
+// Initial protons of a tube (proton initial state): ppc_init per cell below H.
+int64_t init_protons(const gap_params& p, const Derived& d) {
+  if (p.init_kind != GAP_INIT_ATMOSPHERE) return 0;
+  const int64_t k_h = std::min<int64_t>(p.n_cells, (int64_t)std::ceil(d.H / p.dx - 1e-9));
+  return std::max<int64_t>(0, k_h) * p.ppc_init;
+}
+
+// The atmosphere's counts of the previous push: as if it had left the
+// reservoir full (no refill before the next push); the other parity clear.
+void atm_reset(Tube& T) {
+  const int prev = (int)((T.step - 1) & 1);
+  for (int sp = 0; sp < 2; ++sp) {
+    T.atm_cnt[2 * sp + prev] = T.atm_ppc;
+    T.atm_cnt[2 * sp + (prev ^ 1)] = 0;
   }
 }
 
@@ -477,6 +505,9 @@ Ctx make_ctx(gap_t* g) {
   c.tab = g->tab;
   c.qs = g->qs;
   c.qb = g->qb;
+  c.R = g->pr[g->pr_cur];
+  c.pr_n = g->pr_n;
+  c.pr_cap = g->pr_cap;
   c.err = g->err;
   c.shard = g->shard;
   c.pq = g->pq;
@@ -584,6 +615,10 @@ void rebucket_all(gap_t* g) {
   rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1));
   rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1));
   k_count_resort<<<(g->n_tubes + 255) / 256, 256, 0, g->s>>>(g->tubes, g->n_tubes);
+  if (g->any_protons) {
+    k_pro_compact<<<1, PRO_COMPACT_THREADS, 0, g->s>>>(g->pr[g->pr_cur], g->pr[g->pr_cur ^ 1], g->pr_n, g->pr_cap);
+    g->pr_cur ^= 1;
+  }
 }
 
 // With `done`, the single-pass kernel's own completion is recorded into that
@@ -612,6 +647,7 @@ void rebuild_field(gap_t* g) {
   const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
   k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
   k_deposit_all<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
+  if (g->any_protons) k_deposit_protons<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
   field_pass(g, 1);
 }
 
@@ -677,8 +713,13 @@ int tails_grid(const gap_t* g) { return 2 * ((g->grid_tail + 7) / 8 * 8); }
 // The particle kernels with the quantum branches only for handles that have
 // quantum tubes.
 void launch_leptons(gap_t* g, const Ctx& cx, hipStream_t s) {
-  if (g->any_quantum) k_leptons<true><<<g->grid_lep, TPB, 0, s>>>(cx);
-  else k_leptons<false><<<g->grid_lep, TPB, 0, s>>>(cx);
+  if (g->any_quantum) {
+    if (g->any_atm) k_leptons<true, true><<<g->grid_lep, TPB, 0, s>>>(cx);
+    else k_leptons<true, false><<<g->grid_lep, TPB, 0, s>>>(cx);
+  } else {
+    if (g->any_atm) k_leptons<false, true><<<g->grid_lep, TPB, 0, s>>>(cx);
+    else k_leptons<false, false><<<g->grid_lep, TPB, 0, s>>>(cx);
+  }
 }
 void launch_conversions(gap_t* g, const Ctx& cx, hipStream_t s) {
   const int grid = (g->grid_pho + CONV_SEGS - 1) / CONV_SEGS;
@@ -686,8 +727,13 @@ void launch_conversions(gap_t* g, const Ctx& cx, hipStream_t s) {
   else k_conversions<false><<<grid, TPB, 0, s>>>(cx, g->grid_pho);
 }
 void launch_tails(gap_t* g, const Ctx& cx, hipStream_t s) {
-  if (g->any_quantum) k_tails<true><<<tails_grid(g), TPB, 0, s>>>(cx);
-  else k_tails<false><<<tails_grid(g), TPB, 0, s>>>(cx);
+  if (g->any_quantum) {
+    if (g->any_atm) k_tails<true, true><<<tails_grid(g), TPB, 0, s>>>(cx);
+    else k_tails<true, false><<<tails_grid(g), TPB, 0, s>>>(cx);
+  } else {
+    if (g->any_atm) k_tails<false, true><<<tails_grid(g), TPB, 0, s>>>(cx);
+    else k_tails<false, false><<<tails_grid(g), TPB, 0, s>>>(cx);
+  }
 }
 
 // One step of a window: no merge, no re-sort (slots stay put).
@@ -775,6 +821,7 @@ int restore_ckpt(gap_t* g, const WinCkpt& c) {
 }
 
 int window_forward(gap_t* g, int64_t W, int64_t K, double* loss) {
+  if (g->any_protons) return GAP_EINVAL;   // the differentiated map has leptons only
   for (int t = 0; t < g->n_tubes; ++t) {
     const gap_params& q = g->P[t];
     if (q.flags & (GAP_PERIODIC | GAP_FIELD_FROZEN)) return GAP_EINVAL;
@@ -1004,6 +1051,10 @@ void enqueue_step(gap_t* g, bool more) {
   { Timer t(g, KT_LEPTONS); launch_leptons(g, cx, g->s); }
   if (two) (void)hipStreamWaitEvent(g->s, g->ev_pre, 0);
   { Timer t(g, KT_TAILS); launch_tails(g, cx, g->s); }
+  if (g->any_protons) {
+    Timer t(g, KT_TAILS);
+    k_protons<<<std::max(8, g->grid_tail), TPB, 0, g->s>>>(cx);
+  }
   {
     // another step follows at once, with no re-sort or merge in between:
     // its photon side can wait on the field kernel itself
@@ -1137,6 +1188,16 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     T.inj_w = (float)q.inj_weight;
     T.inj_T = std::llrint((double)T.inj_w * kTwo24);
     T.seed = q.seed;
+    T.atm_ppc = q.atm_ppc;
+    T.atm_theta_e = q.atm_temp;
+    T.atm_theta_p = q.atm_temp / (double)MASS_P;
+    atm_reset(T);
+    T.cnt[C_PROTONS] = init_protons(q, d);
+    if (q.atm_ppc > 0) g->any_atm = true;
+    if (q.atm_ppc > 0 || q.init_kind == GAP_INIT_ATMOSPHERE) {
+      g->any_protons = true;
+      g->pr_cap += q.cap_leptons;
+    }
     for (int j = 0; j < T.n_tiles; ++j) {
       Tile tl;
       tl.tube = t;
@@ -1170,7 +1231,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     int dev = 0, cus = 0, nl = 0, np = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons<false>, TPB, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons<false, false>, TPB, 0));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
     // defaults measured on the production gap (2e7 particles): one resident
     // round for the lepton pass, four for the photon pass (short ranges keep
@@ -1216,6 +1277,21 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->pq = (uint4*)dalloc(g, (size_t)g->pho.capacity * sizeof(uint4));
   g->pq_count = (int*)dalloc(g, (size_t)g->pq_groups * 4);
   if (!g->pq || !g->pq_count) return GAP_ENOMEM;
+  if (g->any_protons) {
+    const size_t n = (size_t)g->pr_cap;
+    for (int b = 0; b < 2; ++b) {
+      ProBuf& r = g->pr[b];
+      r.cell = (int32_t*)dalloc(g, n * 4);
+      r.frac = (uint32_t*)dalloc(g, n * 4);
+      r.u = (float*)dalloc(g, n * 4);
+      r.w = (float*)dalloc(g, n * 4);
+      r.id = (uint64_t*)dalloc(g, n * 8);
+      r.tube = (int32_t*)dalloc(g, n * 4);
+      if (!r.cell || !r.frac || !r.u || !r.w || !r.id || !r.tube) return GAP_ENOMEM;
+    }
+    g->pr_n = (long long*)dalloc(g, sizeof(long long));
+    if (!g->pr_n) return GAP_ENOMEM;
+  }
   int max_n = 1;
   for (int t = 0; t < n_tubes; ++t) max_n = std::max(max_n, p[t].n_cells);
   g->ret = (double*)dalloc(g, sizeof(double) * RET_N * (size_t)n_tubes);
@@ -1329,6 +1405,33 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     c.cold_steps = -1;
     HIPCHK(hipMemcpyAsync(g->lep.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, g->s));
   }
+  if (g->any_protons) {
+    // initial protons: ids after each tube's initial electrons
+    std::vector<long long> poff(n_tubes + 1, 0);
+    std::vector<int32_t> pppc(n_tubes);
+    std::vector<int64_t> id0(n_tubes);
+    for (int t = 0; t < n_tubes; ++t) {
+      poff[t + 1] = poff[t] + init_protons(g->P[t], g->D[t]);
+      pppc[t] = std::max(1, g->P[t].ppc_init);
+      id0[t] = init_count(g->P[t], g->D[t]) + 1;
+    }
+    const long long np = poff[n_tubes];
+    if (np > g->pr_cap) return GAP_ECAP;
+    if (np > 0) {
+      long long* d_off = (long long*)dalloc(g, sizeof(long long) * (n_tubes + 1));
+      int32_t* d_ppc = (int32_t*)dalloc(g, 4 * n_tubes);
+      int64_t* d_id0 = (int64_t*)dalloc(g, 8 * n_tubes);
+      if (!d_off || !d_ppc || !d_id0) return GAP_ENOMEM;
+      HIPCHK(hipStreamSynchronize(g->s));
+      HIPCHK(hipMemcpy(d_off, poff.data(), sizeof(long long) * (n_tubes + 1), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d_ppc, pppc.data(), 4 * n_tubes, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d_id0, id0.data(), 8 * n_tubes, hipMemcpyHostToDevice));
+      ProInit pi{g->tubes, g->pr[g->pr_cur], d_off, d_ppc, d_id0, n_tubes};
+      k_init_protons<<<kGrid, 256, 0, g->s>>>(pi);
+    }
+    HIPCHK(hipMemcpyAsync(g->pr_n, &np, sizeof(long long), hipMemcpyHostToDevice, g->s));
+    HIPCHK(hipStreamSynchronize(g->s));
+  }
   rebucket_all(g);
   rebuild_field(g);
   return sync_and_err(g);
@@ -1372,16 +1475,16 @@ int export_store(gap_t* g, const Store& st, bool photon, int tube, std::vector<H
 
 int graph_capture(gap_t* g, int64_t n) {
   drop_graph(g);
-  g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_since = g->since_rb; g->gs_step = g->host_step;
+  g->gs_l = g->lep.cur; g->gs_p = g->pho.cur; g->gs_r = g->pr_cur; g->gs_since = g->since_rb; g->gs_step = g->host_step;
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(g->s, hipStreamCaptureModeThreadLocal));
   g->capturing = true;
   for (int64_t i = 0; i < n; ++i) enqueue_step(g, i + 1 < n);
   g->capturing = false;
   hipError_t e = hipStreamEndCapture(g->s, &graph);
-  g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_since = g->since_rb;
+  g->ge_l = g->lep.cur; g->ge_p = g->pho.cur; g->ge_r = g->pr_cur; g->ge_since = g->since_rb;
   // nothing ran yet: back to the start state
-  g->lep.cur = g->gs_l; g->pho.cur = g->gs_p; g->since_rb = g->gs_since; g->host_step = g->gs_step;
+  g->lep.cur = g->gs_l; g->pho.cur = g->gs_p; g->pr_cur = g->gs_r; g->since_rb = g->gs_since; g->host_step = g->gs_step;
   if (e != hipSuccess) return GAP_EDEVICE;
   e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
@@ -1543,6 +1646,7 @@ int gap_step_graph(gap_t* g, int64_t n_steps) {
   if (g->s == nullptr) return GAP_ESTATE;   // stream capture needs a non-default stream
   join_photon_side(g);
   const bool valid = g->gexec && g->gsteps == n_steps && g->lep.cur == g->gs_l && g->pho.cur == g->gs_p &&
+                     g->pr_cur == g->gs_r &&
                      g->since_rb == g->gs_since &&
                      (!g->merge_on || (g->host_step - g->gs_step) % g->merge_every == 0);
   if (!valid) {
@@ -1550,7 +1654,7 @@ int gap_step_graph(gap_t* g, int64_t n_steps) {
     if (e) return e;
   }
   HIPCHK(hipGraphLaunch(g->gexec, g->s));
-  g->lep.cur = g->ge_l; g->pho.cur = g->ge_p; g->since_rb = g->ge_since;
+  g->lep.cur = g->ge_l; g->pho.cur = g->ge_p; g->pr_cur = g->ge_r; g->since_rb = g->ge_since;
   g->host_step += n_steps;
   return g->sticky;
 }
@@ -1764,6 +1868,40 @@ int gap_diag(gap_t* g, int32_t kind, int32_t tube, void* host_buf, size_t buf_by
       std::memcpy(host_buf, v, sizeof(v));
       return GAP_OK;
     }
+    case GAP_DIAG_PROTONS: {
+      std::vector<char> recs;
+      if (g->any_protons) {
+        long long n = 0;
+        HIPCHK(hipMemcpy(&n, g->pr_n, sizeof(long long), hipMemcpyDeviceToHost));
+        n = std::min<long long>(n, g->pr_cap);
+        const ProBuf& R = g->pr[g->pr_cur];
+        std::vector<int32_t> cell(n), tb(n);
+        std::vector<uint32_t> frac(n);
+        std::vector<float> u(n), w(n);
+        std::vector<uint64_t> id(n);
+        if (n > 0) {
+          HIPCHK(hipMemcpy(cell.data(), R.cell, 4 * n, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(frac.data(), R.frac, 4 * n, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(u.data(), R.u, 4 * n, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(w.data(), R.w, 4 * n, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(id.data(), R.id, 8 * n, hipMemcpyDeviceToHost));
+          HIPCHK(hipMemcpy(tb.data(), R.tube, 4 * n, hipMemcpyDeviceToHost));
+        }
+        for (long long i = 0; i < n; ++i) {
+          if (w[i] == 0.0f || tb[i] != tube) continue;
+          char r[24];
+          std::memcpy(r, &cell[i], 4);
+          std::memcpy(r + 4, &frac[i], 4);
+          std::memcpy(r + 8, &u[i], 4);
+          std::memcpy(r + 12, &w[i], 4);
+          std::memcpy(r + 16, &id[i], 8);
+          recs.insert(recs.end(), r, r + 24);
+        }
+      }
+      if (!fits(recs.size())) return GAP_EINVAL;
+      if (!recs.empty()) std::memcpy(host_buf, recs.data(), recs.size());
+      return GAP_OK;
+    }
     case GAP_DIAG_LEPTONS:
     case GAP_DIAG_PHOTONS: {
       const bool ph = kind == GAP_DIAG_PHOTONS;
@@ -1957,6 +2095,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
       }
       T.dq = 0;
       T.dcur = 0;
+      atm_reset(T);
       if ((e = upload_tubes(g))) return e;
       rebucket_all(g);
       g->since_rb = 0;
@@ -1964,6 +2103,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
         const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
         k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
         k_deposit_all<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
+        if (g->any_protons) k_deposit_protons<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
         // keep E: only record the node charge
         FieldCtx f = make_fctx(g, 1);
         k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
@@ -1978,6 +2118,7 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
       std::memcpy(&T.Es, b, 8);
       std::memcpy(&T.step, b + 8, 8);
       g->host_step = T.step;
+      atm_reset(T);
       if ((e = upload_tubes(g))) return e;
       if (!frozen) rebuild_field(g);
       return sync_and_err(g);
@@ -2003,6 +2144,69 @@ int gap_set_state(gap_t* g, int32_t kind, int32_t tube, const void* host_buf, si
         std::vector<double> e0(E.begin(), E.end());
         HIPCHK(hipMemcpy(g->E0 + T.cell_off, e0.data(), sizeof(double) * N, hipMemcpyHostToDevice));
       }
+      if ((e = upload_tubes(g))) return e;
+      return sync_and_err(g);
+    }
+    case GAP_STATE_PROTONS: {
+      if (!g->any_protons) return GAP_ESTATE;
+      if (bytes < 8) return GAP_EINVAL;
+      int64_t n;
+      std::memcpy(&n, b, 8);
+      if (n < 0 || bytes < 8 + (size_t)n * 24) return GAP_EINVAL;
+      if (n > g->pr_cap) return GAP_ECAP;
+      std::vector<int32_t> cell(n), tb(n, 0);
+      std::vector<uint32_t> frac(n);
+      std::vector<float> u(n), w(n);
+      std::vector<uint64_t> id(n);
+      const char* r = b + 8;
+      for (int64_t i = 0; i < n; ++i, r += 24) {
+        std::memcpy(&cell[i], r, 4);
+        std::memcpy(&frac[i], r + 4, 4);
+        std::memcpy(&u[i], r + 8, 4);
+        std::memcpy(&w[i], r + 12, 4);
+        std::memcpy(&id[i], r + 16, 8);
+        if (cell[i] < 0 || cell[i] >= N || frac[i] >= (1u << FRAC) || !(w[i] != 0.0f)) return GAP_EINVAL;
+      }
+      const ProBuf& R = g->pr[g->pr_cur];
+      if (n > 0) {
+        HIPCHK(hipMemcpy(R.cell, cell.data(), 4 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(R.frac, frac.data(), 4 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(R.u, u.data(), 4 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(R.w, w.data(), 4 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(R.id, id.data(), 8 * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(R.tube, tb.data(), 4 * n, hipMemcpyHostToDevice));
+      }
+      const long long nn = n;
+      HIPCHK(hipMemcpy(g->pr_n, &nn, sizeof(long long), hipMemcpyHostToDevice));
+      T.cnt[C_PROTONS] = n;
+      T.dq = 0;
+      T.dcur = 0;
+      atm_reset(T);
+      if ((e = upload_tubes(g))) return e;
+      if (frozen) {
+        const int grid = std::max(1, (int)std::min<long long>(1024, (g->total_nodes + 255) / 256));
+        k_fill_i64<<<grid, 256, 0, g->s>>>(g->rho, g->total_nodes, 0);
+        k_deposit_all<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
+        k_deposit_protons<<<kGrid, TPB, 0, g->s>>>(make_ctx(g));
+        FieldCtx f = make_fctx(g, 1);
+        k_field_a<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+        k_field_b<<<g->n_fb, FB_THREADS, 0, g->s>>>(f);
+      } else {
+        rebuild_field(g);
+      }
+      return sync_and_err(g);
+    }
+    case GAP_STATE_ATMOSPHERE: {
+      if (bytes < 16) return GAP_EINVAL;
+      int32_t prev[2];
+      std::memcpy(prev, b, 8);
+      if (prev[0] < 0 || prev[1] < 0) return GAP_EINVAL;
+      const int par = (int)((T.step - 1) & 1);
+      for (int sp = 0; sp < 2; ++sp) {
+        T.atm_cnt[2 * sp + par] = prev[sp];
+        T.atm_cnt[2 * sp + (par ^ 1)] = 0;
+      }
+      std::memcpy(&T.atm_count, b + 8, 8);
       if ((e = upload_tubes(g))) return e;
       return sync_and_err(g);
     }

@@ -35,7 +35,8 @@ enum : int {
   C_LEPTONS = 0, C_PHOTONS = 1, C_STEP = 2, C_EMIT = 3, C_PHO_BORN = 4, C_CONV = 5, C_ABSORBED = 6,
   C_OUTFLOW = 7, C_PHO_EXIT = 8, C_DROPPED = 9, C_MERGED = 10, C_ERR = 11, C_INJECTED = 12,
   C_EMIT_EVAL = 13, C_CONV_EVAL = 14, C_LEP_STEPS = 15, C_PHO_STEPS = 16, C_REBUCKETS = 17,
-  C_LEP_STEPS_TAIL = 18, C_EMIT_EVAL_TAIL = 19, C_PHO_STEPS_TAIL = 20, C_CONV_EVAL_TAIL = 21, C_N = 32
+  C_LEP_STEPS_TAIL = 18, C_EMIT_EVAL_TAIL = 19, C_PHO_STEPS_TAIL = 20, C_CONV_EVAL_TAIL = 21,
+  C_PROTONS = 22, C_PRO_ABSORBED = 23, C_PRO_OUTFLOW = 24, C_ATM_E = 25, C_ATM_P = 26, C_N = 32
 };
 
 enum : uint32_t {
@@ -80,6 +81,13 @@ struct Tube {
   int64_t step_now;         // index of the step being taken (set by the prologue; read by the passes)
   uint64_t inj_count;
   int64_t cnt[C_N];
+  // thermal atmosphere (atm_ppc > 0): Theta of its electrons and protons,
+  // particles made so far (their ids), and the electrons (0, 1) and protons
+  // (2, 3) in cell 0 after the push of a step of parity 0 or 1
+  double atm_theta_e, atm_theta_p;
+  int32_t atm_ppc, pad5;
+  uint64_t atm_count;
+  int32_t atm_cnt[4];
 };
 
 struct Tile {
@@ -102,6 +110,8 @@ struct Ctl {                  // control block of one store
 };
 
 struct LepBuf { uint32_t* pos; float* u; float* w; uint64_t* id; };
+// protons: absolute cell and 24-bit fraction, momentum, weight, id, tube
+struct ProBuf { int32_t* cell; uint32_t* frac; float* u; float* w; uint64_t* id; int32_t* tube; };
 struct PhoBuf { uint32_t* pos; float* x; float* w; int32_t* n0; uint64_t* id; };
 
 // ---------------------------------------------------------------- Philox
@@ -140,7 +150,10 @@ __device__ __forceinline__ u4 draw(uint64_t seed, uint64_t id, int64_t step, uin
                       (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-enum : uint32_t { T_INIT = 1, T_EMIT = 2, T_CONV = 3, T_INJ = 4, T_MERGE = 5, T_CHILD = 6 };
+enum : uint32_t { T_INIT = 1, T_EMIT = 2, T_CONV = 3, T_INJ = 4, T_MERGE = 5, T_CHILD = 6, T_ATM = 7 };
+
+constexpr float MASS_P = 1836.0f;                 // proton to electron mass ratio (Sect. 6.1)
+constexpr uint64_t ATM_ID_BASE = 3ull << 61;      // ids of atmosphere particles
 
 // Bernoulli decision u < p with u = (k + 1/2) 2^-24, k = top 24 bits of r,
 // taken exactly: 2k + 1 < p 2^25 (FP64 compare of exact values).

@@ -27,6 +27,11 @@ struct Ctx {
   const float* tab;       // photon spectrum table
   const float* qs;        // quantum photon-spectrum table (tubes with F_QUANTUM), else null
   const float* qb;        // quantum pair-split table
+  // protons (tubes with an atmosphere or the proton initial state): slots
+  // [0, *pr_n) of R, dead ones with w = 0 until the next compaction
+  ProBuf R;
+  long long* pr_n;
+  long long pr_cap;
   int* err;
   long long* shard;       // event counters [tube][NSHARD][C_N], summed by the host
   // conversion queue of the sorted photon pass: workgroup b of the photon
@@ -202,6 +207,91 @@ __device__ __forceinline__ void clamp_tail(Ctl* c) {
   if (c->tail > room) c->tail = room;
 }
 
+// ---- Thermal atmosphere (Sect. 2.3 atmospheric boundary; Sect. 6.1: k_B T
+// = 0.3 m_e c^2, protons with m_p/m_e = 1836).  Reading: a reservoir in
+// cell 0 holding atm_ppc electrons and atm_ppc protons (weight 1 each),
+// refilled before each push from the count the previous push left there;
+// new particles are uniform in the cell with momenta of the one-dimensional
+// relativistic thermal distribution f(u) ~ exp(-gamma/Theta), and the charge
+// they bring leaves the star.
+
+__device__ __forceinline__ double u24d(uint32_t w) { return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+// One momentum of f(u) ~ exp(-gamma/Theta) by rejection, in FP64: in the
+// kinetic energy e = gamma - 1 the density is exp(-e/Theta) h(e), h = (1+e)
+// / sqrt(e(2+e)) <= 1/sqrt(2e) + 1, and the envelope exp(-e/Theta)
+// (1/sqrt(2e) + 1) is a mixture of e = Theta Z^2/2 (Z normal, Box-Muller),
+// weight sqrt(pi Theta/2), and e = -Theta ln U, weight Theta.  Attempt j
+// takes the words of draw(seed, id, step, T_ATM, j): a picks the component
+// (and its bit 0 the sign of u), b and c make e, d accepts with probability
+// h / (1/sqrt(2e) + 1).  After 64 rejections (probability below 1e-30) u = 0.
+__device__ double atm_momentum(uint64_t seed, uint64_t id, int64_t step, double theta) {
+  const double wa = sqrt(3.14159265358979323846 * theta / 2.0), wb = theta;
+  for (uint32_t j = 0; j < 64; ++j) {
+    const u4 r = draw(seed, id, step, T_ATM, j);
+    double e;
+    if (u24d(r.a) * (wa + wb) < wa) {
+      const double c = cos(2.0 * 3.14159265358979323846 * u24d(r.c));
+      e = -theta * log(u24d(r.b)) * c * c;
+    } else {
+      e = -theta * log(u24d(r.b));
+    }
+    if (!(e > 0.0)) continue;
+    const double h = (1.0 + e) / sqrt(e * (2.0 + e));
+    const double bnd = 1.0 / sqrt(2.0 * e) + 1.0;
+    if (u24d(r.d) * bnd < h) {
+      const double u = sqrt(e * (2.0 + e));
+      return (r.a & 1u) ? u : -u;
+    }
+  }
+  return 0.0;
+}
+
+// Refill of one tube's atmosphere (prologue thread of the tube): electrons
+// into the lepton tail, protons after the proton slots in use.  The counts
+// of the previous push are read from the slot of its step parity and
+// cleared for the push after this one.
+__device__ void atmosphere_refill(const Ctx& cx, Tube& T, int t, long long S, long long lim) {
+  const int par = (int)((T.step - 1) & 1);
+  const Tile& tl = cx.tiles[T.tile_first];
+  int64_t dq = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int m = T.atm_ppc - T.atm_cnt[2 * sp + par];
+    T.atm_cnt[2 * sp + par] = 0;
+    if (m <= 0) continue;
+    const double theta = sp == 0 ? T.atm_theta_e : T.atm_theta_p;
+    const long long first = sp == 0 ? S + (long long)atomicAdd((unsigned long long*)&cx.lc->tail, (unsigned long long)m)
+                                    : (long long)atomicAdd((unsigned long long*)cx.pr_n, (unsigned long long)m);
+    for (int j = 0; j < m; ++j) {
+      const uint64_t id = ATM_ID_BASE + T.atm_count++;
+      const long long slot = first + j;
+      if (slot >= (sp == 0 ? lim : cx.pr_cap)) { T.cnt[C_DROPPED]++; atomicOr(cx.err, E_CAP); continue; }
+      const u4 r = draw(T.seed, id, T.step, T_ATM, 0xFFFFu);
+      const float u = (float)atm_momentum(T.seed, id, T.step, theta);
+      if (sp == 0) {
+        cx.L.pos[slot] = ((uint32_t)(0 - tl.base) << FRAC) | (r.a >> 8);
+        cx.L.u[slot] = u;
+        cx.L.w[slot] = -1.0f;
+        cx.L.id[slot] = id;
+        cx.ltt[slot] = T.tile_first;
+        dq += 16777216;                // E_s -= q w0 of the electron (q < 0)
+        T.cnt[C_ATM_E]++;
+      } else {
+        cx.R.cell[slot] = 0;
+        cx.R.frac[slot] = r.a >> 8;
+        cx.R.u[slot] = u;
+        cx.R.w[slot] = 1.0f;
+        cx.R.id[slot] = id;
+        cx.R.tube[slot] = t;
+        dq -= 16777216;
+        T.cnt[C_ATM_P]++;
+        atomic_add_i64(&T.cnt[C_PROTONS], 1);
+      }
+    }
+  }
+  atomic_add_i64(&T.dq, dq);
+}
+
 constexpr int PRE_THREADS = 1024;
 
 // One workgroup; thread t handles tubes t, t + PRE_THREADS, ...  Each tube's
@@ -228,6 +318,7 @@ __global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
     // the photon passes of this step read its index from step_now: the
     // field update (which counts the step) may run beside them
     T.step_now = T.step;
+    if (T.atm_ppc > 0 && !(T.flags & F_PERIODIC)) atmosphere_refill(cx, T, t, S, lim);
     if (T.inj_per_step <= 0.0 || (T.flags & F_PERIODIC)) continue;
     T.inj_acc += T.inj_per_step;
     const double fl = floor(T.inj_acc);
@@ -402,7 +493,7 @@ __device__ __forceinline__ void pair_momenta(const Ctx& cx, uint32_t flags, uint
 // wave-uniform tile of a sorted chunk (tube constants come through scalar
 // loads, gather and deposit go through the LDS window); otherwise the lane's
 // own tile (tail) with global memory.  `tile` < 0: no particle in this lane.
-template <bool UNI, bool Q>
+template <bool UNI, bool Q, bool A>
 __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
                            LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out,
                            const Room& proom) {
@@ -502,10 +593,12 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   // deposit at the new position: node k gets s (T - A), node k+1 gets s A,
   // A = round(T xi) (half up), exact integers
   const int ncg = per ? wrap_cell(ncell, N) : ncell;
+  // electrons left in cell 0 by this push refill the atmosphere next step
+  if (A && alive && !dead && sg < 0.0f && ncg == 0) atomicAdd(&cx.tubes[tube].atm_cnt[step & 1], 1);
   if (alive && !dead) {
-    const unsigned long long A = ((unsigned long long)Tw * nfrac + (1ull << 23)) >> FRAC;
-    const long long a = sg > 0 ? (long long)A : -(long long)A;
-    const long long ta = sg > 0 ? (long long)(Tw - (int64_t)A) : -(long long)(Tw - (int64_t)A);
+    const unsigned long long Au = ((unsigned long long)Tw * nfrac + (1ull << 23)) >> FRAC;
+    const long long a = sg > 0 ? (long long)Au : -(long long)Au;
+    const long long ta = sg > 0 ? (long long)(Tw - (int64_t)Au) : -(long long)(Tw - (int64_t)Au);
     if (UNI) {
       atomicAdd((unsigned long long*)&s_rho[noff], (unsigned long long)ta);
       atomicAdd((unsigned long long*)&s_rho[noff + 1], (unsigned long long)a);
@@ -621,7 +714,7 @@ __device__ __forceinline__ void piece_slot(long long q, long long nsq, long long
 // deposit go through an LDS window of the tile.
 // (six waves per SIMD: the register cap spills one value, stored once on
 // entry and reloaded once per chunk)
-template <bool Q>
+template <bool Q, bool A>
 __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
   const Room proom = load_room(cx.pc);
   __shared__ long long s_rho[WIN + 2];
@@ -661,7 +754,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float uo;
-      lepton_one<true, Q>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
+      lepton_one<true, Q, A>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
       w = make_float4(w.y, w.z, w.w, w.x);
       p = make_uint4(p.y, p.z, p.w, po);
       u = make_float4(u.y, u.z, u.w, uo);
@@ -676,7 +769,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
 
 // Lepton pass over the tail (particles appended since the last re-sort):
 // one slot per thread, each lane with its own tile; global gather/deposit.
-template <bool Q>
+template <bool Q, bool A>
 __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
   const Room proom = load_room(cx.pc);
   LocalCounts lcn;
@@ -693,7 +786,7 @@ __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
     const float w = cx.L.w[slot];
     const uint32_t pos = cx.L.pos[slot];
     const float u = cx.L.u[slot];
-    lepton_one<false, Q>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
+    lepton_one<false, Q, A>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
   }
 }
 
@@ -1072,13 +1165,13 @@ __device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
 // Workgroups alternate roles in groups of eight, so both species spread over
 // every XCD; the grid is a multiple of 16, so each role gets half of it with
 // indexes 0 .. half - 1.
-template <bool Q>
+template <bool Q, bool A>
 __global__ __launch_bounds__(TPB) void k_tails(Ctx cx) {
   const int bx = blockIdx.x;
   const int bid = ((bx >> 4) << 3) | (bx & 7);
   const int nblk = (int)(gridDim.x >> 1);
   if ((bx >> 3) & 1) photons_tail<Q>(cx, bid, nblk);
-  else leptons_tail<Q>(cx, bid, nblk);
+  else leptons_tail<Q, A>(cx, bid, nblk);
 }
 
 // ------------------------------------------------------------------ field

@@ -25,9 +25,11 @@ ERRORS = {0: "GAP_OK", -1: "GAP_EINVAL", -2: "GAP_ENOMEM", -3: "GAP_ECAP", -4: "
           -6: "GAP_EDEVICE", -7: "GAP_ESTATE"}
 
 (DIAG_COUNTS, DIAG_FIELD, DIAG_ES, DIAG_RHO, DIAG_LEPTONS, DIAG_PHOTONS, DIAG_NODE_E, DIAG_DERIVED, DIAG_TIMING,
- DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE, DIAG_LAUNCH) = range(17)
+ DIAG_PROFILE, DIAG_PEAK, DIAG_RETURN, DIAG_WATERFALL, DIAG_ESPECTRUM, DIAG_SPECTRA, DIAG_PHASE, DIAG_LAUNCH,
+ DIAG_PROTONS) = range(18)
 (STATE_PARTICLES, STATE_ES_STEP, STATE_FIELD, STATE_INJECTION, STATE_TIMING, STATE_DRIVE, STATE_LAUNCH,
- STATE_PROFILE_BIN, STATE_WATERFALL, STATE_RAISE) = range(10)
+ STATE_PROFILE_BIN, STATE_WATERFALL, STATE_RAISE, STATE_PROTONS, STATE_ATMOSPHERE) = range(12)
+INIT_GAP, INIT_UNIFORM, INIT_EMPTY, INIT_ELECTRON, INIT_ATMOSPHERE = range(5)
 # discharge diagnostics: profile groups and the return spectrum's bins
 PROFILE_GROUPS = ["e-_up", "e-_down", "e+_up", "e+_down", "x>2_up", "x>2_down"]
 RETURN_BINS = 64                      # 1/8 decade of gamma each, gamma in [1, 1e8)
@@ -36,7 +38,7 @@ TIMING_KEYS = ["leptons", "photons", "field", "resort", "prologue", "tails", "me
 COUNT_KEYS = ["n_lep", "n_pho", "step", "n_emit", "n_pho_born", "n_conv", "n_absorbed", "n_outflow",
               "n_pho_exit", "n_dropped", "n_merged", "err", "n_injected", "n_emit_eval", "n_conv_eval",
               "lep_steps", "pho_steps", "rebuckets", "lep_steps_tail", "emit_eval_tail", "pho_steps_tail",
-              "conv_eval_tail"]
+              "conv_eval_tail", "n_pro", "n_pro_absorbed", "n_pro_outflow", "n_atm_e", "n_atm_p"]
 
 from .inputs import LEPTON_DTYPE, PHOTON_DTYPE  # noqa: E402  (record layouts of the C ABI)
 
@@ -56,6 +58,7 @@ class GapParams(C.Structure):
         ("inj_weight", C.c_double), ("x_thr", C.c_double), ("xc_floor", C.c_double), ("u_init", C.c_double),
         ("merge_frac", C.c_double), ("seed", C.c_uint64), ("cap_leptons", C.c_int64), ("cap_photons", C.c_int64),
         ("flags", C.c_uint32), ("nsub_max", C.c_int32), ("merge_every", C.c_int32), ("rebucket_every", C.c_int32),
+        ("atm_temp", C.c_double), ("atm_ppc", C.c_int32), ("pad_atm", C.c_int32),
     ]
 
 
@@ -68,7 +71,8 @@ class GapAllocator(C.Structure):
 _DEFAULTS = dict(n_cells=1024, init_kind=1, ppc_init=16, ppc_ref=16, dx=0.25, cfl=0.45, alpha=1.5, b=0.1,
                  r_curv_cm=1e7, period_s=1.0, lambda_c_scale=1.0, r_curv_scale=1.0, h_gap_frac=0.8, inj_rate=0.0,
                  inj_weight=1.0, x_thr=2.0, xc_floor=1e-2, u_init=0.0, merge_frac=0.9, seed=0,
-                 cap_leptons=1 << 22, cap_photons=1 << 22, flags=0, nsub_max=64, merge_every=64, rebucket_every=0)
+                 cap_leptons=1 << 22, cap_photons=1 << 22, flags=0, nsub_max=64, merge_every=64, rebucket_every=0,
+                 atm_temp=0.3, atm_ppc=0, pad_atm=0)
 
 
 def make_params(cfg: dict) -> GapParams:
@@ -241,6 +245,10 @@ class Gap:
     def photons(self, tube=0) -> np.ndarray:
         return self._diag(DIAG_PHOTONS, tube, 0).view(PHOTON_DTYPE).copy()
 
+    def protons(self, tube=0) -> np.ndarray:
+        """The tube's live protons, records as the leptons' (u = gamma beta)."""
+        return self._diag(DIAG_PROTONS, tube, 0).view(LEPTON_DTYPE).copy()
+
     def set_timing(self, on: bool):
         buf = np.array([1 if on else 0], np.int32)
         _check(self.lib.gap_set_state(self.h, STATE_TIMING, 0, buf.ctypes.data, buf.nbytes), "set_timing")
@@ -266,6 +274,17 @@ class Gap:
         buf = np.concatenate([np.ascontiguousarray(E, np.float32).view(np.uint8),
                               np.array([es], np.float64).view(np.uint8)])
         _check(self.lib.gap_set_state(self.h, STATE_FIELD, 0, buf.ctypes.data, buf.nbytes), "set_field")
+
+    def set_protons(self, pro: np.ndarray):
+        pro = np.ascontiguousarray(pro, dtype=LEPTON_DTYPE)
+        buf = np.concatenate([np.array([pro.size], np.int64).view(np.uint8), pro.view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_PROTONS, 0, buf.ctypes.data, buf.nbytes), "set_protons")
+
+    def set_atmosphere(self, prev_e: int, prev_p: int, count: int):
+        """What the last push left in cell 0, and the atmosphere particles made."""
+        buf = np.concatenate([np.array([prev_e, prev_p], np.int32).view(np.uint8),
+                              np.array([count], np.uint64).view(np.uint8)])
+        _check(self.lib.gap_set_state(self.h, STATE_ATMOSPHERE, 0, buf.ctypes.data, buf.nbytes), "set_atmosphere")
 
     def set_drive(self, alpha: float, inj_weight: float, tube: int = 0):
         buf = np.array([alpha, inj_weight], np.float64)
