@@ -53,11 +53,14 @@ ADJOINT = dict(BASE, n_cells=16384, init_kind=1, ppc_init=122, ppc_ref=16, alpha
 # particles per cell per species at n_co, the current filter on.  The gap is
 # sized so that gamma_gap = H^2/2 (E_rot = H in these units) is 3e7:
 # H = 7746 d, N = H / (0.8 dx) = 38730 cells.  With b = 0.02 and P = 1 s
-# the skin depth is 3.035 cm, so 30 H is 7.053e5 cm.  The thermal atmosphere
-# with protons is replaced by the cold surface injection of the other gaps.
-PAPER = dict(BASE, n_cells=38730, init_kind=0, ppc_init=2, ppc_ref=2, alpha=2.0, b=0.02, r_curv_cm=7.053e5,
-             inj_rate=0.1, seed=0, steps=10_000_000, cap_leptons=50_000_000, cap_photons=50_000_000,
-             merge=True, flags=8192)
+# the skin depth is 3.035 cm, so 30 H is 7.053e5 cm.  The initial state is
+# the paper's (electrons everywhere, as many protons below H) and the left
+# boundary its thermal atmosphere at k_B T = 0.3 m_e c^2, kept at 16
+# particles per species in cell 0 (8 n_co: a layer dense next to the gap
+# above it).
+PAPER = dict(BASE, n_cells=38730, init_kind=4, ppc_init=2, ppc_ref=2, alpha=2.0, b=0.02, r_curv_cm=7.053e5,
+             inj_rate=0.0, atm_ppc=16, atm_temp=0.3, seed=0, steps=10_000_000, cap_leptons=50_000_000,
+             cap_photons=50_000_000, merge=True, flags=8192)
 
 
 def batched_tubes(n_tubes: int = 256, seed: int = 1) -> list[dict]:

@@ -143,8 +143,9 @@ def test_graph_replays_with_filter_and_waterfall(torch_gpu):
 
 @pytest.mark.parametrize("alpha", [2.0, -2.0])
 def test_paper_preset_field_parity(torch_gpu, alpha):
-    # the paper's setup (b = 0.02, R_curv = 30 H, filter on, 38730 cells),
-    # with its fiducial alpha and the tested -2
+    # the paper's setup (b = 0.02, R_curv = 30 H, filter on, 38730 cells,
+    # protons and the thermal atmosphere), with its fiducial alpha and the
+    # tested -2
     _say("case: paper preset, alpha %+.0f, field parity over 100 steps" % alpha)
     cfg = dict(workloads.PAPER, alpha=alpha, cap_leptons=1 << 20, cap_photons=1 << 20, merge=False)
     g, o = Gap(cfg), Oracle(cfg)
@@ -153,7 +154,8 @@ def test_paper_preset_field_parity(torch_gpu, alpha):
         o.step(1)
         err = rel_field_err(g.field(), o.field())
         assert err <= 1e-5, (n, err)
-    cg, co = g.counts(), o.counts()
-    assert cg["n_lep"] == co["n_lep"] and cg["n_injected"] == co["n_injected"] and cg["err"] == 0
+    cg, co, pc = g.counts(), o.counts(), o.proton_counts()
+    assert cg["n_lep"] == co["n_lep"] and cg["err"] == 0
+    assert (cg["n_pro"], cg["n_atm_e"], cg["n_atm_p"]) == (pc["n_pro"], pc["n_atm_e"], pc["n_atm_p"])
     assert abs(g.es() - o.Es) <= 1e-12 * max(1.0, abs(o.Es))
     g.close()

@@ -17,6 +17,9 @@ def test_paper_preset_scales():
     assert abs(g_gap / 3e7 - 1) < 0.01
     g_rad = (3 * o.H * o.rc ** 2 / (2 * (1 / 137.035999084) * o.lam)) ** 0.25
     assert abs(g_rad / g_gap - 0.3) < 0.01
-    # two particles per cell per species at n_co above H, vacuum below
-    c = o.counts()
-    assert c["n_lep"] == 2 * (o.N - math.ceil(o.H / 0.25 - 1e-9))
+    # two electrons per cell everywhere and two protons per cell below H
+    # (charge 0 below H, n_co above), a thermal atmosphere at 0.3 m_e c^2
+    kh = math.ceil(o.H / 0.25 - 1e-9)
+    assert o.counts()["n_lep"] == 2 * o.N
+    assert o.proton_counts()["n_pro"] == 2 * kh
+    assert workloads.PAPER["atm_ppc"] > 0 and workloads.PAPER["atm_temp"] == 0.3
