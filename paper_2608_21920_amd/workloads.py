@@ -86,10 +86,10 @@ def batched_tubes(n_tubes: int = 256, seed: int = 1) -> list[dict]:
 def batched_qed_active(tubes: list[dict]) -> list[dict]:
     """The batched tubes with the QED rescaled so that each tube's emission,
     photon transport and pair creation run within a few hundred steps
-    (lambda~ x 3e4, R~ x 3e-4: lambda~/R~ = 1e8 times the physical value),
-    with the photon store as large as the lepton store and merging every 16
-    steps above half the cap: the cascade that follows ignition outgrows a
-    64-step check of 90 % of the cap, and with these settings every tube
-    stays below 65 % of its caps through step 600."""
-    return [dict(c, lambda_c_scale=3e4, r_curv_scale=3e-4, cap_photons=c["cap_leptons"], merge=True, merge_every=16,
-                 merge_frac=0.5) for c in tubes]
+    (lambda~ x 3e3, R~ x 3e-3: lambda~/R~ = 1e6 times the physical value;
+    by step 400 every tube emits and converts, about 0.4 photons per lepton),
+    with the photon store as large as the lepton store and a merge check
+    every 32 steps above 70 % of the cap (the cascade outgrows a 64-step
+    check of 90 %)."""
+    return [dict(c, lambda_c_scale=3e3, r_curv_scale=3e-3, cap_photons=c["cap_leptons"], merge=True, merge_every=32,
+                 merge_frac=0.7) for c in tubes]
