@@ -666,12 +666,12 @@ def main():
                   "window")
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(
-            torch, res["value"], workloads.batched_qed_active(recipe), ignite_steps=400, launch=phys["autotune"],
+            torch, res["value"], workloads.batched_qed_active(recipe), ignite_steps=400,
             label="256 tubes: cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q log-uniform in "
                   "[0.01, 0.3], ppc uniform in [4, 64] per species, seed 1; uniform e+- start, QED rescaled "
                   "(lambda~ x 3e3, R~ x 3e-3) so that emission, photon transport and conversion run, merge check every "
                   "32 steps above 70 % of the cap; "
-                  "timed after 400 steps, past ignition, with the physical run's tuned launch shape")
+                  "timed after 400 steps, past ignition, with its own autotuned launch shape")
         out["batched_physical_qed"] = phys
         torch.cuda.empty_cache()
     if not a.no_adjoint:

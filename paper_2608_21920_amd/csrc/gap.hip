@@ -301,6 +301,9 @@ struct gap_t {
   double2* fft_buf = nullptr;   // 2 M complex values of the largest tube, allocated on first use
   double* fft_pow = nullptr;
   int* pq_count = nullptr;
+  uint4* bq = nullptr;                 // birth queue of the sorted lepton pass: entries, and per
+  int* bq_count = nullptr;             // workgroup of the pass their number and first entry
+  long long* bq_start = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
   int round_lep = 2048, round_pho = 2048, cus = 256;        // one resident round of each pass; CUs
@@ -512,6 +515,10 @@ Ctx make_ctx(gap_t* g) {
   c.shard = g->shard;
   c.pq = g->pq;
   c.pq_count = g->pq_count;
+  c.bq = g->bq;
+  c.bq_count = g->bq_count;
+  c.bq_start = g->bq_start;
+  c.bq_groups = g->grid_lep;
   c.ret = g->ret;
   c.ret_thr = g->ret_thr;
   return c;
@@ -709,6 +716,9 @@ void win_release(gap_t* g) {
 // Workgroups of the fused tail launch: each role takes the tail workgroup
 // count rounded up to a multiple of eight (the roles alternate in eights).
 int tails_grid(const gap_t* g) { return 2 * ((g->grid_tail + 7) / 8 * 8); }
+// workgroups of the tail launch that write the sorted lepton pass's queued
+// photon births: one per CU
+int births_wg(const gap_t* g) { return std::max(16, g->cus); }
 
 // The particle kernels with the quantum branches only for handles that have
 // quantum tubes.
@@ -728,11 +738,11 @@ void launch_conversions(gap_t* g, const Ctx& cx, hipStream_t s) {
 }
 void launch_tails(gap_t* g, const Ctx& cx, hipStream_t s) {
   if (g->any_quantum) {
-    if (g->any_atm) k_tails<true, true><<<tails_grid(g), TPB, 0, s>>>(cx);
-    else k_tails<true, false><<<tails_grid(g), TPB, 0, s>>>(cx);
+    if (g->any_atm) k_tails<true, true><<<tails_grid(g) + births_wg(g), TPB, 0, s>>>(cx, births_wg(g));
+    else k_tails<true, false><<<tails_grid(g) + births_wg(g), TPB, 0, s>>>(cx, births_wg(g));
   } else {
-    if (g->any_atm) k_tails<false, true><<<tails_grid(g), TPB, 0, s>>>(cx);
-    else k_tails<false, false><<<tails_grid(g), TPB, 0, s>>>(cx);
+    if (g->any_atm) k_tails<false, true><<<tails_grid(g) + births_wg(g), TPB, 0, s>>>(cx, births_wg(g));
+    else k_tails<false, false><<<tails_grid(g) + births_wg(g), TPB, 0, s>>>(cx, births_wg(g));
   }
 }
 
@@ -1277,6 +1287,13 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
   g->pq = (uint4*)dalloc(g, (size_t)g->pho.capacity * sizeof(uint4));
   g->pq_count = (int*)dalloc(g, (size_t)g->pq_groups * 4);
   if (!g->pq || !g->pq_count) return GAP_ENOMEM;
+  // at most one entry per slot of the sorted lepton region; a count and a
+  // start per workgroup of the largest lepton grid the launch settings allow
+  // (4 rounds)
+  g->bq = (uint4*)dalloc(g, (size_t)g->lep.capacity * sizeof(uint4));
+  g->bq_count = (int*)dalloc(g, (size_t)(4 * g->round_lep + 64) * sizeof(int));
+  g->bq_start = (long long*)dalloc(g, (size_t)(4 * g->round_lep + 64) * sizeof(long long));
+  if (!g->bq || !g->bq_count || !g->bq_start) return GAP_ENOMEM;
   if (g->any_protons) {
     const size_t n = (size_t)g->pr_cap;
     for (int b = 0; b < 2; ++b) {

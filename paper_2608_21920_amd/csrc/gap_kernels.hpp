@@ -40,6 +40,14 @@ struct Ctx {
   // their number to pq_count[b]
   uint4* pq;
   int* pq_count;
+  // photon births of the sorted lepton pass, queued for the tail launch:
+  // entries {slot, post-kick u bits, event mask low word, high word};
+  // workgroup b of the pass (bq_groups of them) wrote bq_count[b] entries
+  // from entry bq_start[b] on
+  uint4* bq;
+  int* bq_count;
+  long long* bq_start;
+  int bq_groups;
   // return spectrum per tube (RET_N doubles): absorbed weight per bin of
   // log10 gamma, then the total weight and the total weight x gamma; the
   // bins' lower edges in u^2 = gamma^2 - 1 (ret_thr[b] = 10^(b/4) - 1)
@@ -488,6 +496,38 @@ __device__ __forceinline__ void pair_momenta(const Ctx& cx, uint32_t flags, uint
   *up = dir * sqrtf(fmaxf(gp * gp - 1.0f, 0.0f));
 }
 
+// gamma, chi = gamma^2 lambda~/R~ and the characteristic photon energy
+// x_c = 1.5 gamma chi of a lepton of momentum u, with explicit roundings: the
+// emission evaluation and the photon births (which may run in another
+// kernel) form them identically.
+__device__ __forceinline__ float emit_xc(float u, float lr, float* g, float* chi) {
+  *g = __builtin_amdgcn_sqrtf(__fmaf_rn(u, u, 1.0f));
+  *chi = __fmul_rn(__fmul_rn(*g, *g), lr);
+  return __fmul_rn(__fmul_rn(1.5f, *g), *chi);
+}
+
+// Birth queue of the sorted lepton pass.  Photon births take tail slots of
+// the photon store, and the tail counter is one word that every reservation
+// updates with a device-scope atomic; such atomics on one address are
+// served one at a time, and in a cascade (hundreds of thousands of births
+// per step) one reservation per wave and birth iteration made them the
+// largest cost of the pass.  The birth code also held registers that the
+// rest of the pass needs.  So the sorted pass only queues, per lepton with
+// photons to store, its slot, its post-kick momentum and its event mask; the
+// tail launch replays the events and writes the photons, one reservation per
+// dense wave.  Workgroup b of the pass writes its entries from the first
+// slot of its chunk range on (it has at most one entry per slot it pushes),
+// counted in LDS, and their number and start to bq_count[b], bq_start[b].
+__device__ __forceinline__ void queue_births(const Ctx& cx, int* s_bqn, long long seg0, bool has, uint32_t slot,
+                                             float upk, uint64_t evmask) {
+  const uint64_t m = __ballot(has);
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(s_bqn, __popcll(m));
+  base = __builtin_amdgcn_readfirstlane(base);
+  if (has) cx.bq[seg0 + base + rank_in(m)] = make_uint4(slot, __float_as_uint(upk), (uint32_t)evmask,
+                                                         (uint32_t)(evmask >> 32));
+}
+
 // One lepton: gather, kick, emission (Monte Carlo with recoil), drift,
 // boundaries, deposit, photon births.  UNI: the lane's tile is the
 // wave-uniform tile of a sorted chunk (tube constants come through scalar
@@ -496,7 +536,7 @@ __device__ __forceinline__ void pair_momenta(const Ctx& cx, uint32_t flags, uint
 template <bool UNI, bool Q, bool A>
 __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku, long long* s_rho, const float* s_eb,
                            LocalCounts& lcn, float w, uint32_t pos, float u, uint32_t* pos_out, float* u_out,
-                           const Room& proom) {
+                           const Room& proom, int* s_bqn, long long seg0) {
   bool alive;
   KC k;
   if (UNI) {
@@ -537,9 +577,8 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   int ncand = 0, nev = 0;
   bool eval = false;
   if (alive && !(flags & (F_QED_OFF | F_EMIT_OFF)) && ((int64_t)cg << FRAC) + frac < k.hfix) {
-    const float g = __builtin_amdgcn_sqrtf(1.0f + u * u);
-    const float chi = g * g * k.lr;
-    xc = 1.5f * g * chi;
+    float g, chi;
+    xc = emit_xc(u, k.lr, &g, &chi);
     if (xc >= k.xc_floor) {
       eval = true;
       id = cx.L.id[slot];
@@ -613,7 +652,9 @@ __device__ void lepton_one(const Ctx& cx, uint32_t slot, int tile, const KC& ku,
   // photon births at the post-drift position, inside the QED zone
   const bool keep = alive && !dead && (((int64_t)ncg << FRAC) + nfrac < k.hfix);
   const int nst = keep ? ncand : 0;
-  if (__ballot(nst > 0)) {
+  if (UNI) {
+    if (__ballot(nst > 0)) queue_births(cx, s_bqn, seg0, nst > 0, slot, upk, evmask);
+  } else if (__ballot(nst > 0)) {
     int dropped = 0;
     const long long first = reserve_tail(cx.pc, proom, nst, &dropped);
     const long long lim = proom.L;
@@ -722,8 +763,10 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
   __shared__ long long s_cnt[8];
   LocalCounts lcn;
   lcn.clear();
+  __shared__ int s_bqn;        // photon births queued by this workgroup
   int ctube = -1;
   for (int j = threadIdx.x; j < WIN + 2; j += blockDim.x) s_rho[j] = 0;
+  if (threadIdx.x == 0) s_bqn = 0;
   __syncthreads();
   const long long nsc = cx.lc->n_sorted_chunks;
   const int G = gridDim.x, bx = blockIdx.x;
@@ -754,7 +797,7 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
     for (int j = 0; j < VEC; ++j) {
       uint32_t po;
       float uo;
-      lepton_one<true, Q, A>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom);
+      lepton_one<true, Q, A>(cx, cur.slot0 + j, tile, kc, s_rho, s_eb, lcn, w.x, p.x, u.x, &po, &uo, proom, &s_bqn, c0 * CHUNK);
       w = make_float4(w.y, w.z, w.w, w.x);
       p = make_uint4(p.y, p.z, p.w, po);
       u = make_float4(u.y, u.z, u.w, uo);
@@ -765,6 +808,11 @@ __global__ __launch_bounds__(TPB, 6) void k_leptons(Ctx cx) {
   }
   if (held >= 0) flush_window(cx, held, s_rho);
   if (ctube >= 0) flush_counts<0>(cx.shard, ctube, lcn, s_cnt);
+  // (flush_counts ends with a barrier: every wave has queued its births)
+  if (threadIdx.x == 0) {
+    cx.bq_count[blockIdx.x] = c0 < c1 ? s_bqn : 0;
+    cx.bq_start[blockIdx.x] = c0 * CHUNK;
+  }
 }
 
 // Lepton pass over the tail (particles appended since the last re-sort):
@@ -786,7 +834,7 @@ __device__ __forceinline__ void leptons_tail(const Ctx& cx, int bid, int nblk) {
     const float w = cx.L.w[slot];
     const uint32_t pos = cx.L.pos[slot];
     const float u = cx.L.u[slot];
-    lepton_one<false, Q, A>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom);
+    lepton_one<false, Q, A>(cx, slot, tile, kc0, nullptr, nullptr, lcn, w, pos, u, nullptr, nullptr, proom, nullptr, 0);
   }
 }
 
@@ -1159,17 +1207,138 @@ __device__ __forceinline__ void photons_tail(const Ctx& cx, int bid, int nblk) {
   }
 }
 
+// The photon births queued by the sorted lepton pass (queue_births): a lane
+// takes one entry and replays its lepton's emission events in order, with
+// the draws, energies and recoil bookkeeping of the pass, once to count the
+// photons to store and once to write them; the wave reserves tail slots
+// once for all its lanes.  The lepton's position after its drift, weight and
+// id are read from its slot (the pass has stored them); the step index is
+// still the pass's, since the field update runs after this launch.
+// Workgroup b0 takes the segments b0, b0 + nb, ..., TPB segments at a time:
+// their counts are read together and scanned in LDS, and the entries of all
+// of them are taken in dense pieces of TPB (a lane finds its segment by a
+// binary search over the scan), so that a workgroup with few entries in many
+// segments pays one chain of dependent loads, not one per segment.
+template <bool Q>
+__device__ __forceinline__ void births_queue(const Ctx& cx, int b0, int nb) {
+  __shared__ int s_pre[TPB + 1];
+  __shared__ long long s_st[TPB];
+  __shared__ int s_wsum[TPB / WAVE];
+  const Room proom = load_room(cx.pc);
+  const long long lim = proom.L;
+  const int ns = b0 < cx.bq_groups ? (cx.bq_groups - b0 + nb - 1) / nb : 0;
+  for (int i0 = 0; i0 < ns; i0 += TPB) {
+    const int i = i0 + (int)threadIdx.x;
+    const int sg = b0 + i * nb;
+    const int c = i < ns ? cx.bq_count[sg] : 0;
+    s_st[threadIdx.x] = i < ns ? cx.bq_start[sg] : 0;
+    int wt;
+    const int ex = wave_excl_scan(c, &wt);
+    if (lane_id() == 0) s_wsum[threadIdx.x / WAVE] = wt;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < TPB / WAVE; ++w) {
+      if (w < (int)threadIdx.x / WAVE) before += s_wsum[w];
+      total += s_wsum[w];
+    }
+    s_pre[threadIdx.x] = before + ex;
+    if (threadIdx.x == 0) s_pre[TPB] = total;
+    __syncthreads();
+    for (int p = 0; p < total; p += TPB) {
+      const int e = p + (int)threadIdx.x;
+      const bool valid = e < total;
+      // last segment whose first entry is at or before e (empty ones repeat
+      // their successor's start, so the search lands on a segment that has e)
+      int lo = 0, hi = TPB;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= e) lo = mid; else hi = mid;
+      }
+      const uint4 q = valid ? cx.bq[s_st[lo] + (e - s_pre[lo])] : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t slot = q.x;
+      const int tile = valid ? cx.lchunk[slot / CHUNK] : 0;
+      const KC k = lane_kc(cx, tile, false);
+      const uint32_t flags = (uint32_t)k.flags;
+      const float upk = __uint_as_float(q.y);
+      const uint64_t evmask = (uint64_t)q.z | ((uint64_t)q.w << 32);
+      uint64_t id = 0;
+      float aw = 0.0f;
+      uint32_t npl = 0;
+      if (valid) {
+        id = cx.L.id[slot];
+        aw = fabsf(cx.L.w[slot]);
+        npl = cx.L.pos[slot];
+      }
+      float g, chi;
+      const float xc = emit_xc(upk, k.lr, &g, &chi);
+      int nst = 0;
+      {
+        float au = fabsf(upk);
+        uint64_t m = evmask;
+        while (m) {
+          const int j = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const u4 r = draw(k.seed, id, k.step, T_EMIT, (uint32_t)j);
+          const float x = fminf(photon_energy<Q>(cx, flags, r.b, xc, upk, k.lr), au);
+          au -= x;
+          if (x >= k.x_thr || (flags & F_TRACK_ALL)) ++nst;
+        }
+      }
+      int dropped = 0;
+      const long long first = reserve_tail(cx.pc, proom, nst, &dropped);
+      if (nst > 0) {
+        float au = fabsf(upk);
+        const float dir = upk >= 0.0f ? 1.0f : -1.0f;
+        long long qq = first;
+        uint64_t m = evmask;
+        while (m) {
+          const int j = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const u4 r = draw(k.seed, id, k.step, T_EMIT, (uint32_t)j);
+          const float x = fminf(photon_energy<Q>(cx, flags, r.b, xc, upk, k.lr), au);
+          au -= x;
+          if (x >= k.x_thr || (flags & F_TRACK_ALL)) {
+            if (qq < lim) {
+              const uint32_t kk = (uint32_t)qq;
+              cx.P.pos[kk] = npl;
+              cx.P.x[kk] = dir * x;
+              cx.P.w[kk] = aw;
+              cx.P.n0[kk] = (int32_t)(k.step + 1);
+              cx.P.id[kk] = child_id(k.seed, id, k.step, 2u + (uint32_t)j);
+              cx.ptt[kk] = tile;
+            }
+            ++qq;
+          }
+        }
+      }
+      if (__ballot(dropped != 0)) {
+        if (dropped) atomicOr(cx.err, E_CAP);
+        count_by_tube(cx.shard, dropped ? k.tube : -1, C_DROPPED, dropped);
+      }
+      if (__ballot(nst - dropped != 0)) count_by_tube(cx.shard, nst - dropped != 0 ? k.tube : -1, C_PHO_BORN, nst - dropped);
+    }
+    __syncthreads();                  // (s_pre and s_st are rewritten by the next batch)
+  }
+}
+
 // Both tail passes in one launch.  They touch disjoint data: each reads its
 // own store up to the snapshot taken before it, and its births (photons from
 // the leptons, pairs from the photons) go past the other store's snapshot.
 // Workgroups alternate roles in groups of eight, so both species spread over
 // every XCD; the grid is a multiple of 16, so each role gets half of it with
-// indexes 0 .. half - 1.
+// indexes 0 .. half - 1.  The first bq_wg workgroups, dispatched first,
+// write the photon births that the sorted lepton pass queued instead (they
+// go past the photon tail's snapshot, like every birth of the step): their
+// chain of dependent loads then runs beside the tail passes.
 template <bool Q, bool A>
-__global__ __launch_bounds__(TPB) void k_tails(Ctx cx) {
-  const int bx = blockIdx.x;
+__global__ __launch_bounds__(TPB) void k_tails(Ctx cx, int bq_wg) {
+  if ((int)blockIdx.x < bq_wg) {
+    births_queue<Q>(cx, (int)blockIdx.x, bq_wg);
+    return;
+  }
+  const int bx = (int)blockIdx.x - bq_wg;
   const int bid = ((bx >> 4) << 3) | (bx & 7);
-  const int nblk = (int)(gridDim.x >> 1);
+  const int nblk = ((int)gridDim.x - bq_wg) >> 1;
   if ((bx >> 3) & 1) photons_tail<Q>(cx, bid, nblk);
   else leptons_tail<Q, A>(cx, bid, nblk);
 }
