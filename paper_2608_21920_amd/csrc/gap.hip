@@ -276,6 +276,7 @@ struct gap_t {
   int merge_every = 64;
   SortBuf sort_l{}, sort_p{};
   uint32_t* merge_start = nullptr;
+  uint32_t* merge_bmax = nullptr;      // per block of the max-scan: its maximum, then its carry
   double* thresh_l = nullptr;
   double* thresh_p = nullptr;
   double tmin_l = 0.0, tmin_p = 0.0;   // smallest tube threshold of each store
@@ -676,7 +677,9 @@ void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, 
     src ^= 1;
   }
   k_merge_bounds<<<kGrid, 256, 0, g->s>>>(sb, src, g->merge_start);
-  k_merge_maxscan<<<1, 1024, 0, g->s>>>(sb, g->merge_start);
+  k_mx_reduce<<<kGrid, RS_TPB, 0, g->s>>>(sb, g->merge_start, g->merge_bmax);
+  k_mx_carry<<<1, 1024, 0, g->s>>>(sb, g->merge_bmax);
+  k_mx_apply<<<kGrid, RS_TPB, 0, g->s>>>(sb, g->merge_start, g->merge_bmax);
   k_merge_pairs<B><<<kGrid, 256, 0, g->s>>>(buf, sb, src, g->merge_start, g->tubes, g->tiles, st.chunk[st.cur], st.tt,
                                             st.ctl, g->shard);
 }
@@ -1351,9 +1354,10 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
       if (!sb.bhist || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
     }
     g->merge_start = (uint32_t*)dalloc(g, (size_t)std::max(g->lep.capacity, g->pho.capacity) * 4);
+    g->merge_bmax = (uint32_t*)dalloc(g, ((size_t)std::max(g->lep.capacity, g->pho.capacity) / MX_ITEMS + 2) * 4);
     g->thresh_l = (double*)dalloc(g, sizeof(double) * n_tubes);
     g->thresh_p = (double*)dalloc(g, sizeof(double) * n_tubes);
-    if (!g->merge_start || !g->thresh_l || !g->thresh_p) return GAP_ENOMEM;
+    if (!g->merge_start || !g->merge_bmax || !g->thresh_l || !g->thresh_p) return GAP_ENOMEM;
     std::vector<double> tl(n_tubes), tp(n_tubes);
     for (int t = 0; t < n_tubes; ++t) {
       const bool on = (g->P[t].flags & GAP_MERGE_ON) != 0;

@@ -10,7 +10,7 @@
 namespace gap {
 
 constexpr int RS_TPB = 256;
-constexpr int RS_TILES = 16;                    // 256-item tiles per block
+constexpr int RS_TILES = 64;                    // 256-item tiles per block
 constexpr int RS_ITEMS = RS_TPB * RS_TILES;     // items per block
 
 struct SortBuf {
@@ -230,18 +230,50 @@ __global__ void k_merge_bounds(SortBuf sb, int src, uint32_t* start) {
     start[i] = (i == 0 || sb.major[src][i] != sb.major[src][i - 1]) ? (uint32_t)i : 0u;
 }
 
-// Inclusive max-scan of start[] in place (one workgroup, sequential blocks).
-__global__ __launch_bounds__(1024) void k_merge_maxscan(SortBuf sb, uint32_t* start) {
+// Inclusive max-scan of start[] in place, in three launches over blocks of
+// MX_ITEMS entries: each block's maximum, an exclusive max-scan of those (one
+// workgroup, over n / MX_ITEMS values), and each block's own scan from that
+// carry.  (One workgroup over all n entries took milliseconds per merge of
+// 1e8 candidates.)
+constexpr int MX_TILES = 16;
+constexpr int MX_ITEMS = RS_TPB * MX_TILES;
+
+__global__ __launch_bounds__(RS_TPB) void k_mx_reduce(SortBuf sb, const uint32_t* start, uint32_t* bmax) {
+  __shared__ uint32_t sh[RS_TPB / WAVE];
+  const long long n = *sb.n;
+  const int nb = (int)((n + MX_ITEMS - 1) / MX_ITEMS);
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    uint32_t m = 0;
+    for (int k = threadIdx.x; k < MX_ITEMS; k += RS_TPB) {
+      const long long i = (long long)b * MX_ITEMS + k;
+      if (i < n) m = max(m, start[i]);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d));
+    if (lane_id() == 0) sh[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < RS_TPB / WAVE; ++w) t = max(t, sh[w]);
+      bmax[b] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive max-scan of bmax[0, nb) in place (one workgroup).
+__global__ __launch_bounds__(1024) void k_mx_carry(SortBuf sb, uint32_t* bmax) {
   __shared__ uint32_t sh[1024 / WAVE];
   const long long n = *sb.n;
+  const int nb = (int)((n + MX_ITEMS - 1) / MX_ITEMS);
   uint32_t carry = 0;
-  for (long long base = 0; base < n; base += 1024) {
-    const long long i = base + threadIdx.x;
-    uint32_t v = i < n ? start[i] : 0u;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    const uint32_t v = i < nb ? bmax[i] : 0u;
     uint32_t incl = v;
 #pragma unroll
     for (int k = 1; k < WAVE; k <<= 1) {
-      uint32_t o = __shfl_up(incl, k);
+      const uint32_t o = (uint32_t)__shfl_up((int)incl, k);
       if (lane_id() >= k) incl = max(incl, o);
     }
     const int wv = threadIdx.x / WAVE;
@@ -249,13 +281,44 @@ __global__ __launch_bounds__(1024) void k_merge_maxscan(SortBuf sb, uint32_t* st
     __syncthreads();
     uint32_t pre = carry;
     for (int ww = 0; ww < wv; ++ww) pre = max(pre, sh[ww]);
-    const uint32_t r = max(pre, incl);
-    if (i < n) start[i] = r;
+    // exclusive: the maximum of everything before entry i
+    const uint32_t up = (uint32_t)__shfl_up((int)incl, 1);
+    const uint32_t ex = lane_id() == 0 ? pre : max(pre, up);
+    uint32_t tot = carry;
+    for (int ww = 0; ww < 1024 / WAVE; ++ww) tot = max(tot, sh[ww]);
     __syncthreads();
-    if (threadIdx.x == 1023) sh[0] = r;
-    __syncthreads();
-    carry = max(carry, sh[0]);
-    __syncthreads();
+    if (i < nb) bmax[i] = ex;
+    carry = tot;
+  }
+}
+
+__global__ __launch_bounds__(RS_TPB) void k_mx_apply(SortBuf sb, uint32_t* start, const uint32_t* bcarry) {
+  __shared__ uint32_t sh[RS_TPB / WAVE];
+  const long long n = *sb.n;
+  const int nb = (int)((n + MX_ITEMS - 1) / MX_ITEMS);
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    uint32_t carry = bcarry[b];
+    for (int tile = 0; tile < MX_TILES; ++tile) {
+      const long long i = (long long)b * MX_ITEMS + (long long)tile * RS_TPB + threadIdx.x;
+      const uint32_t v = i < n ? start[i] : 0u;
+      uint32_t incl = v;
+#pragma unroll
+      for (int k = 1; k < WAVE; k <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)incl, k);
+        if (lane_id() >= k) incl = max(incl, o);
+      }
+      const int wv = threadIdx.x / WAVE;
+      if (lane_id() == WAVE - 1) sh[wv] = incl;
+      __syncthreads();
+      uint32_t pre = carry, tot = carry;
+      for (int ww = 0; ww < RS_TPB / WAVE; ++ww) {
+        if (ww < wv) pre = max(pre, sh[ww]);
+        tot = max(tot, sh[ww]);
+      }
+      if (i < n) start[i] = max(pre, incl);
+      __syncthreads();
+      carry = tot;
+    }
   }
 }
 
