@@ -1105,11 +1105,26 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 // + CONV_SEGS - 1 of the photon kernel (a grid of nseg) wrote, one entry of
 // each segment per thread and round, with all loads issued before the draws.
 constexpr int CONV_SEGS = 2;
+//
+// The pairs take lepton tail slots from a block per wave (LDS state, one
+// entry per wave): a new block is reserved with one atomic on the lepton
+// tail counter only when the block cannot hold the iteration's pairs, which
+// then fill the old block and continue in the new one.  The first block
+// holds exactly the wave's first pairs; each later one is at least twice the
+// last, up to PAIR_BLOCK_MAX.  The unused end of a wave's last block is
+// written as dead leptons (weight 0, tile 0), which every pass skips and the
+// re-sort drops.  (One atomic per wave and conversion iteration, on the one
+// counter every reservation updates, cost a cascade of 1e5 conversions per
+// step about a millisecond.)
+constexpr int PAIR_BLOCK_MAX = 128;
 
 template <bool Q>
 __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   const Room lroom = load_room(cx.lc);
   const long long nsc = cx.pc->n_sorted_chunks;
+  __shared__ long long s_blk[TPB / WAVE][3];    // per wave: next slot, block end, next block size
+  long long* blk = s_blk[threadIdx.x / WAVE];
+  if (lane_id() == 0) { blk[0] = 0; blk[1] = 0; blk[2] = 2; }
   long long q0[CONV_SEGS];
   int n[CONV_SEGS];
   int nmax = 0;
@@ -1151,11 +1166,31 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
         conv = bern(r.a, __uint_as_float(e[j].y));
         rsplit = r.b;
       }
-      if (__ballot(conv)) {
+      const uint64_t cm = __ballot(conv);
+      if (cm) {
         const uint32_t slot = e[j].x;
         const int tube = conv ? (int)e[j].w : -1;
+        // this lane's pair takes the wave's pair slots ex and ex + 1
+        const long long total = 2 * __popcll(cm);
+        const long long ex = 2 * rank_in(cm);
+        const long long next = rfl64(blk[0]);
+        const long long rem = rfl64(blk[1]) - next;
+        long long nb = 0;
+        if (total > rem) {
+          const long long need = total - rem;
+          const long long req = max(need, rfl64(blk[2]));
+          long long base = 0;
+          if (lane_id() == WAVE - 1) {
+            base = (long long)atomicAdd((unsigned long long*)&cx.lc->tail, (unsigned long long)req);
+            const long long room = lroom.L > lroom.S ? lroom.L - lroom.S : 0;
+            if (base + req > room) atomicMin((unsigned long long*)&cx.lc->tail, (unsigned long long)room);
+          }
+          nb = lroom.S + rfl64(__shfl(base, WAVE - 1));
+          if (lane_id() == 0) { blk[0] = nb + need; blk[1] = nb + req; blk[2] = min(2 * req, (long long)PAIR_BLOCK_MAX); }
+        } else if (lane_id() == 0) {
+          blk[0] = next + total;
+        }
         int dropped = 0;
-        const long long first = reserve_tail(cx.lc, lroom, conv ? 2 : 0, &dropped);
         if (conv) {
           const float x = cx.P.x[slot], w = cx.P.w[slot];
           const uint32_t np = cx.P.pos[slot];
@@ -1166,8 +1201,11 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
           float ue, upo;
           pair_momenta<Q>(cx, tflags, rsplit, chi, x, &ue, &upo);
           for (int b = 0; b < 2; ++b) {
-            const long long sl = first + b;
-            if (sl < lroom.L) {
+            const long long g = ex + b;
+            const long long sl = g < rem ? next + g : nb + (g - rem);
+            if (sl >= lroom.L) {
+              ++dropped;
+            } else {
               const uint32_t s32 = (uint32_t)sl;
               cx.L.pos[s32] = np;
               cx.L.u[s32] = b == 0 ? ue : upo;
@@ -1183,6 +1221,16 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
         if (__ballot(dropped != 0)) count_by_tube(cx.shard, dropped ? tube : -1, C_DROPPED, dropped);
       }
     }
+  }
+  // the unused end of the wave's last block: dead leptons
+  const long long bend = min(rfl64(blk[1]), lroom.L);
+  for (long long sl = rfl64(blk[0]) + lane_id(); sl < bend; sl += WAVE) {
+    const uint32_t s32 = (uint32_t)sl;
+    cx.L.pos[s32] = 0;
+    cx.L.u[s32] = 0.0f;
+    cx.L.w[s32] = 0.0f;
+    cx.L.id[s32] = 0;
+    cx.ltt[s32] = 0;
   }
 }
 
