@@ -749,15 +749,36 @@ void launch_tails(gap_t* g, const Ctx& cx, hipStream_t s) {
   }
 }
 
+void join_photon_side(gap_t* g);
+
+// The photon side of a window step (photon pass, conversion draws), forked
+// onto the second stream once the caller's stream has done the prologue; the
+// caller joins it at the end of the step (join_photon_side), before the next
+// prologue takes the pairs it made.  The two sides touch disjoint data, as in
+// enqueue_step.  Under graph capture everything stays on the caller's stream.
+void fork_photon_side(gap_t* g, const Ctx& cx) {
+  if (g->capturing) {
+    k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
+    launch_conversions(g, cx, g->s);
+    return;
+  }
+  (void)hipEventRecord(g->ev_pre, g->s);
+  (void)hipStreamWaitEvent(g->s2, g->ev_pre, 0);
+  k_photons<<<g->grid_pho, TPB, 0, g->s2>>>(cx);
+  launch_conversions(g, cx, g->s2);
+  (void)hipEventRecord(g->ev_p, g->s2);
+  g->s2_pending = true;
+}
+
 // One step of a window: no merge, no re-sort (slots stay put).
 void enqueue_window_step(gap_t* g) {
   Ctx cx = make_ctx(g);
   k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
+  fork_photon_side(g, cx);
   launch_leptons(g, cx, g->s);
-  k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-  launch_conversions(g, cx, g->s);
   launch_tails(g, cx, g->s);
   field_pass(g, 0);
+  join_photon_side(g);
   ++g->host_step;
 }
 
@@ -940,14 +961,14 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
       k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
       k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + j * M, w.tu + j * M, w.wlast, w.meta + j,
                                       w.M, 0, g->err);
+      fork_photon_side(g, cx);       // (the tape of the leptons is taken; photons are not taped)
       D2D(w.teb + j * (size_t)g->total_nodes, g->ebar, sizeof(float) * g->total_nodes);
       launch_leptons(g, cx, g->s);
-      k_photons<<<g->grid_pho, TPB, 0, g->s>>>(cx);
-      launch_conversions(g, cx, g->s);
       launch_tails(g, cx, g->s);
       field_pass(g, 0);
       ++g->host_step;
       D2D(w.tE + (j + 1) * (size_t)g->total_cells, g->E, sizeof(float) * g->total_cells);
+      join_photon_side(g);
     }
     {
       Ctx cx = make_ctx(g);

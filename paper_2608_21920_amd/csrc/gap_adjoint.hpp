@@ -133,42 +133,40 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_init(double* lamE, const fl
 
 // ------------------------------------------------------------------ reverse
 // Field after step j: E_s receives sum_k lamE_k; suffix sums for the weights;
-// alpha enters E_s as alpha s_co dt.
+// alpha enters E_s as alpha s_co dt.  One workgroup per tube: thread t sums
+// a run of consecutive cells, one block scan gives each run the sum of the
+// runs above it, and each thread then writes its run's suffix sums from the
+// top down (one round of barriers instead of one per ADJ_THREADS cells).
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_field(const double* lamE, double* suf, AdjTube* at) {
   __shared__ double sh[ADJ_THREADS / WAVE];
-  __shared__ double s_carry;
   AdjTube& a = at[blockIdx.x];
   const int N = a.N;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) s += lamE[a.cell_off + k];
-  const double total = block_sum_d(s, sh);
-  if (threadIdx.x == 0) s_carry = 0.0;
-  __syncthreads();
-  // suffix sums from the top cell down, ADJ_THREADS cells at a time
-  for (int top = N; top > 0; top -= ADJ_THREADS) {
-    const int k = top - 1 - (int)threadIdx.x;
-    const double v = k >= 0 ? lamE[a.cell_off + k] : 0.0;
-    double incl = v;
+  const double* lm = lamE + a.cell_off;
+  const int per = (N + ADJ_THREADS - 1) / ADJ_THREADS;
+  const int k0 = min(N, (int)threadIdx.x * per), k1 = min(N, k0 + per);
+  double t = 0.0;
+  for (int k = k0; k < k1; ++k) t += lm[k];
+  // inclusive suffix of the run sums over the wave's lanes, then over waves
+  double incl = t;
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const double o = __shfl_up(incl, d);
-      if (lane_id() >= d) incl += o;
-    }
-    const int wv = threadIdx.x / WAVE;
-    if (lane_id() == WAVE - 1) sh[wv] = incl;
-    __syncthreads();
-    double before = s_carry;
-    for (int q = 0; q < wv; ++q) before += sh[q];
-    if (k >= 0) suf[a.node_off + k] = before + incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int q = 0; q < ADJ_THREADS / WAVE; ++q) t += sh[q];
-      s_carry += t;
-    }
-    __syncthreads();
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const double o = __shfl_down(incl, d);
+    if (lane_id() + d < WAVE) incl += o;
+  }
+  const int wv = threadIdx.x / WAVE;
+  if (lane_id() == 0) sh[wv] = incl;
+  __syncthreads();
+  double after = 0.0;
+  for (int q = ADJ_THREADS / WAVE - 1; q > wv; --q) after += sh[q];
+  // the sum of the runs above this one, then this run's suffix sums
+  const double above = __shfl_down(incl, 1);
+  double s = (lane_id() + 1 < WAVE ? above : 0.0) + after;
+  for (int k = k1 - 1; k >= k0; --k) {
+    s += lm[k];
+    suf[a.node_off + k] = s;
   }
   if (threadIdx.x == 0) {
+    const double total = s;          // thread 0's run starts at cell 0
     suf[a.node_off + N] = 0.0;
     a.lamEs += total;
     a.cw += a.w0 * total;
