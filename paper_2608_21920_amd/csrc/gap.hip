@@ -307,6 +307,7 @@ struct gap_t {
   long long* bq_start = nullptr;
   int pq_groups = 0;                   // entries of pq_count (bounds the photon grid)
   int grid_lep = 2048, grid_pho = 2048, grid_tail = 1024;   // workgroups of the particle passes
+  int round_conv = 2048;                // one resident round of the conversion draws
   int round_lep = 2048, round_pho = 2048, cus = 256;        // one resident round of each pass; CUs
   int rmax = 64;                                            // longest re-sort interval the tile margin allows
   bool any_periodic = false;
@@ -672,7 +673,7 @@ void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, 
   int src = 0;
   for (int pass = 0; pass < 12; ++pass) {
     k_rs_hist<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
-    k_rs_scan<<<1, 1024, 0, g->s>>>(sb);
+    k_rs_scan<<<RS_SCAN_WG, 1024, 0, g->s>>>(sb);
     k_rs_scatter<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
     src ^= 1;
   }
@@ -734,10 +735,15 @@ void launch_leptons(gap_t* g, const Ctx& cx, hipStream_t s) {
     else k_leptons<false, false><<<g->grid_lep, TPB, 0, s>>>(cx);
   }
 }
+// The conversion draws: at least one resident round of workgroups, each
+// with CONV_SEGS queue parts (a photon grid that large keeps one part per
+// segment).
 void launch_conversions(gap_t* g, const Ctx& cx, hipStream_t s) {
-  const int grid = (g->grid_pho + CONV_SEGS - 1) / CONV_SEGS;
-  if (g->any_quantum) k_conversions<true><<<grid, TPB, 0, s>>>(cx, g->grid_pho);
-  else k_conversions<false><<<grid, TPB, 0, s>>>(cx, g->grid_pho);
+  const int target = CONV_SEGS * g->round_conv;
+  const int split = std::max(1, (target + g->grid_pho - 1) / g->grid_pho);
+  const int grid = (g->grid_pho * split + CONV_SEGS - 1) / CONV_SEGS;
+  if (g->any_quantum) k_conversions<true><<<grid, TPB, 0, s>>>(cx, g->grid_pho, split);
+  else k_conversions<false><<<grid, TPB, 0, s>>>(cx, g->grid_pho, split);
 }
 void launch_tails(gap_t* g, const Ctx& cx, hipStream_t s) {
   if (g->any_quantum) {
@@ -1267,6 +1273,9 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
     HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nl, k_leptons<false, false>, TPB, 0));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&np, k_photons, TPB, 0));
+    int nc = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nc, k_conversions<false>, TPB, 0));
+    g->round_conv = std::max(8, cus * std::max(nc, 1));
     // defaults measured on the production gap (2e7 particles): one resident
     // round for the lepton pass, four for the photon pass (short ranges keep
     // its conversion queue segments small), two workgroups per CU for each
@@ -1369,10 +1378,11 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
         if (!sb.major[b] || !sb.id[b] || !sb.val[b]) return GAP_ENOMEM;
       }
       sb.bhist = (uint32_t*)dalloc(g, (size_t)256 * sb.max_blocks * 4);
+      sb.dtot = (uint32_t*)dalloc(g, 256 * 4);
       sb.flags = (uint32_t*)dalloc(g, (size_t)n_tubes * 4);
       sb.gate = (uint32_t*)dalloc(g, 4);
       sb.n = (long long*)dalloc(g, 8);
-      if (!sb.bhist || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
+      if (!sb.bhist || !sb.dtot || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
     }
     g->merge_start = (uint32_t*)dalloc(g, (size_t)std::max(g->lep.capacity, g->pho.capacity) * 4);
     g->merge_bmax = (uint32_t*)dalloc(g, ((size_t)std::max(g->lep.capacity, g->pho.capacity) / MX_ITEMS + 2) * 4);

@@ -1101,9 +1101,13 @@ __global__ __launch_bounds__(TPB) void k_photons(Ctx cx) {
 // Photon pass, second kernel: the conversion draws of the queued photons and
 // the pairs they create: e- and e+ at the photon's new position, gamma = x/2
 // each, moving along the photon; the converted photon is removed.
-// Workgroup b takes the segments that workgroups CONV_SEGS b .. CONV_SEGS b
-// + CONV_SEGS - 1 of the photon kernel (a grid of nseg) wrote, one entry of
-// each segment per thread and round, with all loads issued before the draws.
+// The queue segment that workgroup k of the photon kernel (a grid of nseg)
+// wrote is cut into `split` parts by rounds of TPB entries (part p takes
+// rounds p, p + split, ...), so that the number of parts can fill the chip
+// whatever the photon grid; workgroup b takes parts CONV_SEGS b .. CONV_SEGS
+// b + CONV_SEGS - 1, one entry of each per thread and round, with all loads
+// issued before the draws.  (With the segment as the unit, a photon grid of
+// 768 left 384 workgroups to walk 4e7 entries, 1.7 ms per step.)
 constexpr int CONV_SEGS = 2;
 //
 // The pairs take lepton tail slots from a block per wave (LDS state, one
@@ -1119,7 +1123,7 @@ constexpr int CONV_SEGS = 2;
 constexpr int PAIR_BLOCK_MAX = 128;
 
 template <bool Q>
-__global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
+__global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg, int split) {
   const Room lroom = load_room(cx.lc);
   const long long nsc = cx.pc->n_sorted_chunks;
   __shared__ long long s_blk[TPB / WAVE][3];    // per wave: next slot, block end, next block size
@@ -1130,17 +1134,22 @@ __global__ __launch_bounds__(TPB) void k_conversions(Ctx cx, int nseg) {
   int nmax = 0;
 #pragma unroll
   for (int j = 0; j < CONV_SEGS; ++j) {
-    const int sg = (int)blockIdx.x * CONV_SEGS + j;
+    const int v = (int)blockIdx.x * CONV_SEGS + j;
+    const int sg = v / split;
     long long c0 = 0, c1 = 0;
     n[j] = 0;
     if (sg < nseg) {
       chunk_range(nsc, nseg, sg, &c0, &c1);
       n[j] = __builtin_amdgcn_readfirstlane(cx.pq_count[sg]);
     }
-    q0[j] = c0 * CHUNK;
+    // rounds part, part + split, ... of the segment
+    const int part = v - sg * split;
+    q0[j] = c0 * CHUNK + (long long)part * TPB;
+    n[j] -= part * TPB;
     nmax = max(nmax, n[j]);
   }
-  for (int i0 = 0; i0 < nmax; i0 += TPB) {
+  const int stride = split * TPB;
+  for (int i0 = 0; i0 < nmax; i0 += stride) {
     const int i = i0 + (int)threadIdx.x;
     uint4 e[CONV_SEGS];
     uint64_t id[CONV_SEGS], seed[CONV_SEGS];

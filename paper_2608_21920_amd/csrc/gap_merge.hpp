@@ -18,6 +18,7 @@ struct SortBuf {
   uint64_t* id[2];      // minor key
   uint32_t* val[2];     // slot of the record
   uint32_t* bhist;      // [256][nblocks] digit counts per block
+  uint32_t* dtot;       // [256] items per digit
   uint32_t* flags;      // per tube: merge this step
   uint32_t* gate;       // 0: no tube of the store can be over its threshold
   long long* n;         // number of items
@@ -120,49 +121,47 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_hist(SortBuf sb, int src, int pas
   }
 }
 
-// Exclusive scan of bhist in digit-major order (one workgroup); bhist then
-// holds each (digit, block)'s first output position.
+// Exclusive scan of each digit's row of bhist, RS_SCAN_WG workgroups taking
+// every RS_SCAN_WG-th digit: bhist[d][b] becomes the number of items with
+// digit d in the blocks before b, and dtot[d] the number of items with digit
+// d.  A thread takes a run of consecutive blocks, so a row is read twice and
+// written once.  (One workgroup over all 256 rows took a quarter of a
+// millisecond per pass at 3e8 items; a workgroup per digit cost a gated
+// merge check, which finds nothing to sort, 3 us per launch.)
+constexpr int RS_SCAN_WG = 64;
 __global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
-  __shared__ long long sh[1024 / WAVE];
+  __shared__ uint32_t sh[1024 / WAVE];
   const long long n = *sb.n;
   const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
-  const long long total = 256LL * nb;
-  long long carry = 0;
-  for (long long base = 0; base < total; base += 1024) {
-    const long long t = base + threadIdx.x;
-    long long v = 0;
-    uint32_t* ptr = nullptr;
-    if (t < total) {
-      const int d = (int)(t / nb), b = (int)(t % nb);
-      ptr = &sb.bhist[(long long)d * sb.max_blocks + b];
-      v = *ptr;
-    }
-    long long incl = v;
+  if (nb == 0) {
+    for (int d = (int)blockIdx.x; d < 256; d += gridDim.x)
+      if (threadIdx.x == 0) sb.dtot[d] = 0;
+    return;
+  }
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+  const int wv = (int)threadIdx.x / WAVE;
+  for (int d = (int)blockIdx.x; d < 256; d += gridDim.x) {
+    uint32_t* row = sb.bhist + (long long)d * sb.max_blocks;
+    uint32_t s = 0;
+    for (int b = b0; b < b1; ++b) s += row[b];
+    uint32_t incl = s;
 #pragma unroll
     for (int k = 1; k < WAVE; k <<= 1) {
-      long long o = __shfl_up(incl, k);
+      const uint32_t o = __shfl_up(incl, k);
       if (lane_id() >= k) incl += o;
     }
-    const int wv = threadIdx.x / WAVE;
     if (lane_id() == WAVE - 1) sh[wv] = incl;
     __syncthreads();
-    if (threadIdx.x < WAVE) {
-      long long sv = threadIdx.x < 1024 / WAVE ? sh[threadIdx.x] : 0;
-      long long iv = sv;
-#pragma unroll
-      for (int k = 1; k < WAVE; k <<= 1) {
-        long long o = __shfl_up(iv, k);
-        if (lane_id() >= k) iv += o;
-      }
-      if (threadIdx.x < 1024 / WAVE) sh[threadIdx.x] = iv - sv;
+    uint32_t before = 0;
+    for (int w = 0; w < wv; ++w) before += sh[w];
+    uint32_t run = before + incl - s;
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t v = row[b];
+      row[b] = run;
+      run += v;
     }
-    __syncthreads();
-    const long long ex = carry + sh[wv] + incl - v;
-    if (ptr) *ptr = (uint32_t)ex;
-    __syncthreads();
-    if (threadIdx.x == 1023) sh[0] = ex + v;
-    __syncthreads();
-    carry = sh[0];
+    if (threadIdx.x == 1023) sb.dtot[d] = run;
     __syncthreads();
   }
 }
@@ -171,15 +170,33 @@ __global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
 // walks its items in 256-item tiles; a lane's rank is the number of earlier
 // items of its block with the same digit.
 __global__ __launch_bounds__(RS_TPB) void k_rs_scatter(SortBuf sb, int src, int pass) {
-  __shared__ uint32_t run[256];          // per digit: items of this block already placed
+  static_assert(RS_TPB == 256, "one thread per digit");
+  __shared__ uint32_t run[256];          // per digit: next output position of this block
   __shared__ uint32_t wcnt[RS_TPB / WAVE][256];
+  __shared__ uint32_t dbase[256];        // per digit: items with smaller digits
   const long long n = *sb.n;
   const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
+  if (nb <= (int)blockIdx.x) return;
   const int dst = src ^ 1;
   const int w = threadIdx.x / WAVE;
   const uint64_t lt = (1ull << lane_id()) - 1ull;
+  {
+    const uint32_t v = sb.dtot[threadIdx.x];
+    uint32_t incl = v;
+#pragma unroll
+    for (int k = 1; k < WAVE; k <<= 1) {
+      const uint32_t o = __shfl_up(incl, k);
+      if (lane_id() >= k) incl += o;
+    }
+    if (lane_id() == WAVE - 1) wcnt[0][w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int ww = 0; ww < w; ++ww) before += wcnt[0][ww];
+    dbase[threadIdx.x] = before + incl - v;
+    __syncthreads();
+  }
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    run[threadIdx.x] = 0;
+    run[threadIdx.x] = dbase[threadIdx.x] + sb.bhist[(long long)threadIdx.x * sb.max_blocks + b];
     __syncthreads();
     const long long i0 = (long long)b * RS_ITEMS;
     for (int tile = 0; tile < RS_TILES; ++tile) {
@@ -205,7 +222,7 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_scatter(SortBuf sb, int src, int 
       if (ok) {
         uint32_t before = run[d] + (uint32_t)__popcll(same & lt);
         for (int ww = 0; ww < w; ++ww) before += wcnt[ww][d];
-        const long long o = (long long)sb.bhist[(long long)d * sb.max_blocks + b] + before;
+        const long long o = (long long)before;
         sb.major[dst][o] = mj;
         sb.id[dst][o] = id;
         sb.val[dst][o] = v;
