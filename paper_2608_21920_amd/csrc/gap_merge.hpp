@@ -60,40 +60,71 @@ __global__ void k_merge_flags(const long long* live, const double* thresh, uint3
 
 // Gather the merge candidates (live particles of flagged tubes) with their
 // keys.  The order of the gathered list does not matter: the sort's full key
-// (group, id) is unique.
+// (group, id) is unique.  A workgroup takes MK_PIECES pieces of TPB slots at
+// a time and reserves their entries with one atomic on the list counter.
+// (One atomic per wave and piece, on the one counter, cost the photon store
+// of the QED-active ensemble 10 ms per merge.)
+constexpr int MK_PIECES = 8;
 template <class B>
 __global__ __launch_bounds__(TPB) void k_merge_keys(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
                                                     const Tile* tiles, const Tube* tubes, SortBuf sb) {
   if (*sb.gate == 0) return;
+  __shared__ int s_w[TPB / WAVE];
+  __shared__ long long s_base;
   const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
   const long long nsq = S / TPB, nq = nsq + (tail + TPB - 1) / TPB;
-  for (long long q = blockIdx.x; q < nq; q += gridDim.x) {
-    uint32_t slot;
-    int tile;
-    piece_slot(q, nsq, S, tail, chunk, tt, &slot, &tile);
-    bool take = false;
-    uint32_t key = 0;
-    if (tile >= 0 && rec_alive<B>(buf, slot)) {
-      const Tile tl = tiles[tile];
-      const Tube& T = tubes[tl.tube];
-      if (sb.flags[tl.tube]) {
-        int cell = tl.base + (int)(buf.pos[slot] >> FRAC);
-        if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
-        const uint32_t gcell = (uint32_t)(T.cell_off + cell);
-        key = rec_group(buf, slot, gcell);
-        take = true;
+  const int wv = (int)threadIdx.x / WAVE;
+  for (long long q0 = (long long)blockIdx.x * MK_PIECES; q0 < nq; q0 += (long long)gridDim.x * MK_PIECES) {
+    bool take[MK_PIECES];
+    uint32_t key[MK_PIECES], slot[MK_PIECES];
+    int before[MK_PIECES];
+    int wtot = 0;
+#pragma unroll
+    for (int u = 0; u < MK_PIECES; ++u) {
+      take[u] = false;
+      key[u] = 0;
+      slot[u] = 0;
+      if (q0 + u < nq) {
+        int tile;
+        piece_slot(q0 + u, nsq, S, tail, chunk, tt, &slot[u], &tile);
+        if (tile >= 0 && rec_alive<B>(buf, slot[u])) {
+          const Tile tl = tiles[tile];
+          const Tube& T = tubes[tl.tube];
+          if (sb.flags[tl.tube]) {
+            int cell = tl.base + (int)(buf.pos[slot[u]] >> FRAC);
+            if (T.flags & F_PERIODIC) cell = wrap_cell(cell, T.N);
+            const uint32_t gcell = (uint32_t)(T.cell_off + cell);
+            key[u] = rec_group(buf, slot[u], gcell);
+            take[u] = true;
+          }
+        }
+      }
+      const uint64_t m = __ballot(take[u]);
+      before[u] = wtot + (int)rank_in(m);
+      wtot += (int)__popcll(m);
+    }
+    if (lane_id() == 0) s_w[wv] = wtot;
+    __syncthreads();
+    int off = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < TPB / WAVE; ++w) {
+      off += w < wv ? s_w[w] : 0;
+      total += s_w[w];
+    }
+    if (threadIdx.x == 0)
+      s_base = total ? (long long)atomicAdd((unsigned long long*)sb.n, (unsigned long long)total) : 0;
+    __syncthreads();
+    const long long base = s_base + off;
+#pragma unroll
+    for (int u = 0; u < MK_PIECES; ++u) {
+      if (take[u]) {
+        const long long i = base + before[u];
+        sb.major[0][i] = key[u];
+        sb.id[0][i] = buf.id[slot[u]];
+        sb.val[0][i] = slot[u];
       }
     }
-    const uint64_t m = __ballot(take);
-    long long base = 0;
-    if (lane_id() == 0 && m) base = (long long)atomicAdd((unsigned long long*)sb.n, (unsigned long long)__popcll(m));
-    base = __shfl(base, 0);
-    if (take) {
-      const long long i = base + rank_in(m);
-      sb.major[0][i] = key;
-      sb.id[0][i] = buf.id[slot];
-      sb.val[0][i] = slot;
-    }
+    __syncthreads();   // (s_w and s_base are rewritten by the next round)
   }
 }
 
@@ -344,18 +375,22 @@ __global__ void k_merge_pairs(B buf, SortBuf sb, int src, const uint32_t* start,
                               const int32_t* chunk, const int32_t* tt, const Ctl* ctl, long long* shard) {
   const long long n = *sb.n;
   const long long nsorted_slots = ctl->n_sorted_chunks * CHUNK;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += (long long)gridDim.x * blockDim.x) {
-    if (sb.major[src][i + 1] != sb.major[src][i]) continue;
-    if (((i - (long long)start[i]) & 1) != 0) continue;
-    const uint32_t sa = sb.val[src][i], sbb = sb.val[src][i + 1];
-    const int tile = sa < nsorted_slots ? chunk[sa / CHUNK] : tt[sa];
-    const int t = tiles[tile].tube;
-    const Tube& T = tubes[t];
-    const u4 r = draw(T.seed, sb.id[src][i], T.step, T_MERGE, 0);
-    const uint32_t keep = (r.a & 1u) ? sbb : sa, drop = (r.a & 1u) ? sa : sbb;
-    buf.w[keep] += buf.w[drop];
-    rec_kill(buf, drop);
-    atomicAdd((unsigned long long*)(shard + ((long long)t * NSHARD + (blockIdx.x % NSHARD)) * C_N + C_MERGED), 1ull);
+  // (the loop bound is uniform over the workgroup, so that the per-tube
+  // count below is taken with every lane of the wave active)
+  for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 + 1 < n; i0 += (long long)gridDim.x * blockDim.x) {
+    const long long i = i0 + threadIdx.x;
+    int t = -1;
+    if (i + 1 < n && sb.major[src][i + 1] == sb.major[src][i] && ((i - (long long)start[i]) & 1) == 0) {
+      const uint32_t sa = sb.val[src][i], sbb = sb.val[src][i + 1];
+      const int tile = sa < nsorted_slots ? chunk[sa / CHUNK] : tt[sa];
+      t = tiles[tile].tube;
+      const Tube& T = tubes[t];
+      const u4 r = draw(T.seed, sb.id[src][i], T.step, T_MERGE, 0);
+      const uint32_t keep = (r.a & 1u) ? sbb : sa, drop = (r.a & 1u) ? sa : sbb;
+      buf.w[keep] += buf.w[drop];
+      rec_kill(buf, drop);
+    }
+    count_by_tube(shard, t, C_MERGED, 1);
   }
 }
 
