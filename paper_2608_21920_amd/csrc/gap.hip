@@ -232,6 +232,7 @@ struct gap_t {
   // ev_p: the photon side of the last enqueued step done.
   hipStream_t s2 = nullptr;
   hipEvent_t ev_l = nullptr, ev_pre = nullptr, ev_p = nullptr;
+  hipEvent_t ev_f = nullptr, ev_j = nullptr;   // fork and join of the two stores' re-sort or merge
   bool ev_l_bound = false;   // ev_l is already the completion of the last field kernel on the caller's stream
   bool s2_pending = false;  // photon-side work not yet joined into the caller's stream
   bool capturing = false;   // graph capture: everything stays on the caller's stream
@@ -275,8 +276,6 @@ struct gap_t {
   bool merge_on = false;
   int merge_every = 64;
   SortBuf sort_l{}, sort_p{};
-  uint32_t* merge_start = nullptr;
-  uint32_t* merge_bmax = nullptr;      // per block of the max-scan: its maximum, then its carry
   double* thresh_l = nullptr;
   double* thresh_p = nullptr;
   double tmin_l = 0.0, tmin_p = 0.0;   // smallest tube threshold of each store
@@ -411,7 +410,7 @@ void release(gap_t* g) {
   drop_graph(g);
   if (g->s) (void)hipStreamSynchronize(g->s);
   if (g->s2) { (void)hipStreamSynchronize(g->s2); (void)hipStreamDestroy(g->s2); g->s2 = nullptr; }
-  for (hipEvent_t* e : {&g->ev_l, &g->ev_pre, &g->ev_p})
+  for (hipEvent_t* e : {&g->ev_l, &g->ev_pre, &g->ev_p, &g->ev_f, &g->ev_j})
     if (*e) { (void)hipEventDestroy(*e); *e = nullptr; }
   win_release(g);
   wf_release(g);
@@ -585,7 +584,7 @@ __global__ void k_fill_i64(long long* p, long long n, long long v) {
 }
 
 template <class B>
-void rebucket_t(gap_t* g, Store& st, B src, B dst) {
+void rebucket_t(gap_t* g, Store& st, B src, B dst, hipStream_t s) {
   RbCtx<B> cx;
   cx.tubes = g->tubes;
   cx.tiles = g->tiles;
@@ -604,14 +603,14 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst) {
   cx.tchunk = st.tchunk;
   cx.n_tiles = g->n_tiles;
   const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
-  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
-  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
-  k_rb_count<B><<<kGrid, TPB, 0, g->s>>>(cx);
-  k_rb_scan<B><<<1, 1024, 0, g->s>>>(cx);
-  k_rb_chunks<B><<<kGrid, 256, 0, g->s>>>(cx);
-  k_rb_scatter<B><<<kGrid, TPB, 0, g->s>>>(cx);
-  k_rb_pad<B><<<kGrid, TPB, 0, g->s>>>(cx);
-  k_rb_finish<B><<<1, 1, 0, g->s>>>(cx);
+  k_fill_i32<<<fgrid, 256, 0, s>>>(st.tcount, g->n_tiles, 0);
+  k_fill_i32<<<fgrid, 256, 0, s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
+  k_rb_count<B><<<kGrid, TPB, 0, s>>>(cx);
+  k_rb_scan<B><<<1, 1024, 0, s>>>(cx);
+  k_rb_chunks<B><<<kGrid, 256, 0, s>>>(cx);
+  k_rb_scatter<B><<<kGrid, TPB, 0, s>>>(cx);
+  k_rb_pad<B><<<kGrid, TPB, 0, s>>>(cx);
+  k_rb_finish<B><<<1, 1, 0, s>>>(cx);
   st.cur ^= 1;
 }
 
@@ -620,14 +619,36 @@ __global__ void k_count_resort(Tube* tubes, int n_tubes) {
   if (t < n_tubes) tubes[t].cnt[C_REBUCKETS] += 1;
 }
 
+void join_photon_side(gap_t* g);
+
+// Work on the two stores side by side: outside graph capture, the photon
+// store's part is forked onto the second stream once the caller's stream has
+// reached this point, and the caller's stream waits for it at the end.  The
+// re-sort and the merge of one store touch only that store and its own
+// buffers (the tubes and tiles they read do not change meanwhile).
+hipStream_t fork_stores(gap_t* g) {
+  join_photon_side(g);
+  if (g->capturing) return g->s;
+  (void)hipEventRecord(g->ev_f, g->s);
+  (void)hipStreamWaitEvent(g->s2, g->ev_f, 0);
+  return g->s2;
+}
+void join_stores(gap_t* g, hipStream_t ps) {
+  if (ps == g->s) return;
+  (void)hipEventRecord(g->ev_j, ps);
+  (void)hipStreamWaitEvent(g->s, g->ev_j, 0);
+}
+
 void rebucket_all(gap_t* g) {
-  rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1));
-  rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1));
+  hipStream_t ps = fork_stores(g);
+  rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1), ps);
+  rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1), g->s);
   k_count_resort<<<(g->n_tubes + 255) / 256, 256, 0, g->s>>>(g->tubes, g->n_tubes);
   if (g->any_protons) {
     k_pro_compact<<<1, PRO_COMPACT_THREADS, 0, g->s>>>(g->pr[g->pr_cur], g->pr[g->pr_cur ^ 1], g->pr_n, g->pr_cap);
     g->pr_cur ^= 1;
   }
+  join_stores(g, ps);
 }
 
 // With `done`, the single-pass kernel's own completion is recorded into that
@@ -661,33 +682,35 @@ void rebuild_field(gap_t* g) {
 }
 
 template <class B>
-void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, double thresh_min) {
+void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, double thresh_min, hipStream_t s) {
   const int t1 = (g->n_tubes + 255) / 256;
-  k_merge_gate<<<1, 64, 0, g->s>>>(st.ctl, thresh_min, sb.gate);
-  k_fill_i64<<<std::max(1, t1), 256, 0, g->s>>>(g->live, g->n_tubes, 0);
-  k_count_live<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->live, g->n_tubes,
+  k_merge_gate<<<1, 64, 0, s>>>(st.ctl, thresh_min, sb.gate);
+  k_fill_i64<<<std::max(1, t1), 256, 0, s>>>(sb.live, g->n_tubes, 0);
+  k_count_live<B><<<kGrid, TPB, 0, s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, sb.live, g->n_tubes,
                                            sb.gate);
-  k_merge_flags<<<t1, 256, 0, g->s>>>(g->live, thresh, sb.flags, g->n_tubes, sb.gate);
-  k_fill_i64<<<1, 64, 0, g->s>>>(sb.n, 1, 0);
-  k_merge_keys<B><<<kGrid, TPB, 0, g->s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->tubes, sb);
+  k_merge_flags<<<t1, 256, 0, s>>>(sb.live, thresh, sb.flags, g->n_tubes, sb.gate);
+  k_fill_i64<<<1, 64, 0, s>>>(sb.n, 1, 0);
+  k_merge_keys<B><<<kGrid, TPB, 0, s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->tubes, sb);
   int src = 0;
   for (int pass = 0; pass < 12; ++pass) {
-    k_rs_hist<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
-    k_rs_scan<<<RS_SCAN_WG, 1024, 0, g->s>>>(sb);
-    k_rs_scatter<<<kGrid, RS_TPB, 0, g->s>>>(sb, src, pass);
+    k_rs_hist<<<kGrid, RS_TPB, 0, s>>>(sb, src, pass);
+    k_rs_scan<<<RS_SCAN_WG, 1024, 0, s>>>(sb);
+    k_rs_scatter<<<kGrid, RS_TPB, 0, s>>>(sb, src, pass);
     src ^= 1;
   }
-  k_merge_bounds<<<kGrid, 256, 0, g->s>>>(sb, src, g->merge_start);
-  k_mx_reduce<<<kGrid, RS_TPB, 0, g->s>>>(sb, g->merge_start, g->merge_bmax);
-  k_mx_carry<<<1, 1024, 0, g->s>>>(sb, g->merge_bmax);
-  k_mx_apply<<<kGrid, RS_TPB, 0, g->s>>>(sb, g->merge_start, g->merge_bmax);
-  k_merge_pairs<B><<<kGrid, 256, 0, g->s>>>(buf, sb, src, g->merge_start, g->tubes, g->tiles, st.chunk[st.cur], st.tt,
+  k_merge_bounds<<<kGrid, 256, 0, s>>>(sb, src, sb.start);
+  k_mx_reduce<<<kGrid, RS_TPB, 0, s>>>(sb, sb.start, sb.bmax);
+  k_mx_carry<<<1, 1024, 0, s>>>(sb, sb.bmax);
+  k_mx_apply<<<kGrid, RS_TPB, 0, s>>>(sb, sb.start, sb.bmax);
+  k_merge_pairs<B><<<kGrid, 256, 0, s>>>(buf, sb, src, sb.start, g->tubes, g->tiles, st.chunk[st.cur], st.tt,
                                             st.ctl, g->shard);
 }
 
 void merge_all(gap_t* g) {
-  merge_store<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->sort_l, g->thresh_l, g->tmin_l);
-  merge_store<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->sort_p, g->thresh_p, g->tmin_p);
+  hipStream_t ps = fork_stores(g);
+  merge_store<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->sort_p, g->thresh_p, g->tmin_p, ps);
+  merge_store<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->sort_l, g->thresh_l, g->tmin_l, g->s);
+  join_stores(g, ps);
   // merged-away records are dead slots until the next scheduled re-sort
 }
 
@@ -1379,16 +1402,17 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
       }
       sb.bhist = (uint32_t*)dalloc(g, (size_t)256 * sb.max_blocks * 4);
       sb.dtot = (uint32_t*)dalloc(g, 256 * 4);
+      sb.live = (long long*)dalloc(g, sizeof(long long) * n_tubes);
+      sb.start = (uint32_t*)dalloc(g, n * 4);
+      sb.bmax = (uint32_t*)dalloc(g, (n / MX_ITEMS + 2) * 4);
       sb.flags = (uint32_t*)dalloc(g, (size_t)n_tubes * 4);
       sb.gate = (uint32_t*)dalloc(g, 4);
       sb.n = (long long*)dalloc(g, 8);
-      if (!sb.bhist || !sb.dtot || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
+      if (!sb.bhist || !sb.dtot || !sb.live || !sb.start || !sb.bmax || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
     }
-    g->merge_start = (uint32_t*)dalloc(g, (size_t)std::max(g->lep.capacity, g->pho.capacity) * 4);
-    g->merge_bmax = (uint32_t*)dalloc(g, ((size_t)std::max(g->lep.capacity, g->pho.capacity) / MX_ITEMS + 2) * 4);
     g->thresh_l = (double*)dalloc(g, sizeof(double) * n_tubes);
     g->thresh_p = (double*)dalloc(g, sizeof(double) * n_tubes);
-    if (!g->merge_start || !g->merge_bmax || !g->thresh_l || !g->thresh_p) return GAP_ENOMEM;
+    if (!g->thresh_l || !g->thresh_p) return GAP_ENOMEM;
     std::vector<double> tl(n_tubes), tp(n_tubes);
     for (int t = 0; t < n_tubes; ++t) {
       const bool on = (g->P[t].flags & GAP_MERGE_ON) != 0;
@@ -1667,7 +1691,9 @@ int gap_init(const gap_params* p, int32_t n_tubes, void* stream, const gap_alloc
   if (hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&g->ev_l, kSyncEvent) != hipSuccess ||
       hipEventCreateWithFlags(&g->ev_pre, kSyncEvent) != hipSuccess ||
-      hipEventCreateWithFlags(&g->ev_p, kSyncEvent) != hipSuccess) {
+      hipEventCreateWithFlags(&g->ev_p, kSyncEvent) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_f, kSyncEvent) != hipSuccess ||
+      hipEventCreateWithFlags(&g->ev_j, kSyncEvent) != hipSuccess) {
     release(g);
     delete g;
     return GAP_EDEVICE;

@@ -19,6 +19,9 @@ struct SortBuf {
   uint32_t* val[2];     // slot of the record
   uint32_t* bhist;      // [256][nblocks] digit counts per block
   uint32_t* dtot;       // [256] items per digit
+  long long* live;      // per tube: live particles of the store
+  uint32_t* start;      // per item: first index of its group
+  uint32_t* bmax;       // per block of the max-scan: its maximum, then its carry
   uint32_t* flags;      // per tube: merge this step
   uint32_t* gate;       // 0: no tube of the store can be over its threshold
   long long* n;         // number of items
