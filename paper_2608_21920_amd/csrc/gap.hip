@@ -742,6 +742,8 @@ void win_release(gap_t* g) {
 
 // Workgroups of the fused tail launch: each role takes the tail workgroup
 // count rounded up to a multiple of eight (the roles alternate in eights).
+// threads of the prologue: a wave per 64 tubes, up to PRE_THREADS
+int pre_threads(const gap_t* g) { return std::min(PRE_THREADS, (g->n_tubes + WAVE - 1) / WAVE * WAVE); }
 int tails_grid(const gap_t* g) { return 2 * ((g->grid_tail + 7) / 8 * 8); }
 // workgroups of the tail launch that write the sorted lepton pass's queued
 // photon births: one per CU
@@ -802,7 +804,7 @@ void fork_photon_side(gap_t* g, const Ctx& cx) {
 // One step of a window: no merge, no re-sort (slots stay put).
 void enqueue_window_step(gap_t* g) {
   Ctx cx = make_ctx(g);
-  k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
+  k_pre<<<1, pre_threads(g), 0, g->s>>>(cx, g->n_tubes);
   fork_photon_side(g, cx);
   launch_leptons(g, cx, g->s);
   launch_tails(g, cx, g->s);
@@ -987,7 +989,7 @@ int backward(gap_t* g, double* dalpha, double* dninj) {
     // recompute the segment, taping the lepton store before each step
     for (int64_t j = 0; j < Ks; ++j) {
       Ctx cx = make_ctx(g);
-      k_pre<<<1, PRE_THREADS, 0, g->s>>>(cx, g->n_tubes);
+      k_pre<<<1, pre_threads(g), 0, g->s>>>(cx, g->n_tubes);
       k_tape<<<fgrid, 256, 0, g->s>>>(cx.L, g->lep.ctl, w.tpos + j * M, w.tu + j * M, w.wlast, w.meta + j,
                                       w.M, 0, g->err);
       fork_photon_side(g, cx);       // (the tape of the leptons is taken; photons are not taped)
@@ -1102,8 +1104,8 @@ void enqueue_step(gap_t* g, bool more) {
   g->ev_l_bound = false;
   {
     Timer t(g, KT_PRE, ps);
-    if (two) hipExtLaunchKernelGGL(k_pre, dim3(1), dim3(PRE_THREADS), 0, ps, nullptr, g->ev_pre, 0, cx, g->n_tubes);
-    else k_pre<<<1, PRE_THREADS, 0, ps>>>(cx, g->n_tubes);
+    if (two) hipExtLaunchKernelGGL(k_pre, dim3(1), dim3(pre_threads(g)), 0, ps, nullptr, g->ev_pre, 0, cx, g->n_tubes);
+    else k_pre<<<1, pre_threads(g), 0, ps>>>(cx, g->n_tubes);
   }
   { Timer t(g, KT_PHOTONS, ps); k_photons<<<g->grid_pho, TPB, 0, ps>>>(cx); }
   { Timer t(g, KT_CONV, ps); launch_conversions(g, cx, ps); }

@@ -300,9 +300,14 @@ __device__ void atmosphere_refill(const Ctx& cx, Tube& T, int t, long long S, lo
   atomic_add_i64(&T.dq, dq);
 }
 
-constexpr int PRE_THREADS = 1024;
+constexpr int PRE_THREADS = 256;
 
-// One workgroup; thread t handles tubes t, t + PRE_THREADS, ...  Each tube's
+// One workgroup of at most PRE_THREADS threads (a wave per 64 tubes);
+// thread t handles tubes t, t + blockDim.x, ...  The launch bound asks for at
+// most 96 registers a lane (5 waves a SIMD), so that the prologue's waves fit
+// beside a SIMD's waves of the lepton pass as soon as one of them ends; with
+// 1024 threads and 121 registers it needed a whole idle CU and waited for the
+// lepton pass to drain before the photon side could start.  Each tube's
 // injected electrons take tail slots through one atomic reservation (the
 // order of tail slots changes no result).  The prologue belongs to the photon
 // side of the step: it runs before the photon passes, while the lepton pass
@@ -310,7 +315,7 @@ constexpr int PRE_THREADS = 1024;
 // except through atomics (the surface charge dq); the photon tail's snapshot
 // is taken by the field scan at the end of the previous step, after every
 // photon birth of that step.
-__global__ __launch_bounds__(PRE_THREADS) void k_pre(Ctx cx, int n_tubes) {
+__global__ __launch_bounds__(PRE_THREADS, 5) void k_pre(Ctx cx, int n_tubes) {
   // (appends never leave the tails past the limit; the passes below stay
   // inside the stores whatever the tails hold)
   if (threadIdx.x == 0) {
