@@ -606,7 +606,7 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst, hipStream_t s) {
   k_fill_i32<<<fgrid, 256, 0, s>>>(st.tcount, g->n_tiles, 0);
   k_fill_i32<<<fgrid, 256, 0, s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
   k_rb_count<B><<<kGrid, TPB, 0, s>>>(cx);
-  k_rb_scan<B><<<1, 1024, 0, s>>>(cx);
+  k_rb_scan<B><<<1, RB_SCAN_T, 0, s>>>(cx);
   k_rb_chunks<B><<<kGrid, 256, 0, s>>>(cx);
   k_rb_scatter<B><<<kGrid, TPB, 0, s>>>(cx);
   k_rb_pad<B><<<kGrid, TPB, 0, s>>>(cx);

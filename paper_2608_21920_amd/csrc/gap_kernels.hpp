@@ -2057,18 +2057,32 @@ __global__ __launch_bounds__(TPB) void k_rb_count(RbCtx<B> cx) {
     if (s_c[j] > 0) atomicAdd(&cx.ccount[(j % (NC - 1)) * cx.n_tiles + dlo + j / (NC - 1)], s_c[j]);
 }
 
+// Exclusive scan of the chunk counts of the tiles (one workgroup of
+// RB_SCAN_T threads, RB_SCAN_V consecutive tiles per thread and round).  A
+// small workgroup starts beside the other store's re-sort kernels, which run
+// at the same time on the second stream; one of 1024 threads waited for a
+// whole idle CU.
+constexpr int RB_SCAN_T = 256;
+constexpr int RB_SCAN_V = 4;
 template <class B>
-__global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
-  __shared__ long long sh[1024 / WAVE];
+__global__ __launch_bounds__(RB_SCAN_T) void k_rb_scan(RbCtx<B> cx) {
+  __shared__ long long sh[RB_SCAN_T / WAVE];
   long long carry = 0;
-  for (int base = 0; base < cx.n_tiles; base += 1024) {
-    const int t = base + threadIdx.x;
-    long long v = 0;
-    if (t < cx.n_tiles) {
-      v = (cx.tcount[t] + CHUNK - 1) / CHUNK;
-      for (int k = 0; k < RbClasses<B>::N; ++k) cx.ccur[k * cx.n_tiles + t] = 0;
+  for (int base = 0; base < cx.n_tiles; base += RB_SCAN_T * RB_SCAN_V) {
+    const int t0 = base + (int)threadIdx.x * RB_SCAN_V;
+    long long v[RB_SCAN_V];
+    long long sum = 0;
+#pragma unroll
+    for (int j = 0; j < RB_SCAN_V; ++j) {
+      const int t = t0 + j;
+      v[j] = 0;
+      if (t < cx.n_tiles) {
+        v[j] = (cx.tcount[t] + CHUNK - 1) / CHUNK;
+        for (int k = 0; k < RbClasses<B>::N; ++k) cx.ccur[k * cx.n_tiles + t] = 0;
+      }
+      sum += v[j];
     }
-    long long incl = v;
+    long long incl = sum;
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) {
       long long o = __shfl_up(incl, d);
@@ -2077,24 +2091,18 @@ __global__ __launch_bounds__(1024) void k_rb_scan(RbCtx<B> cx) {
     const int wv = threadIdx.x / WAVE;
     if (lane_id() == WAVE - 1) sh[wv] = incl;
     __syncthreads();
-    if (threadIdx.x < WAVE) {
-      long long sv = threadIdx.x < 1024 / WAVE ? sh[threadIdx.x] : 0;
-      long long iv = sv;
-#pragma unroll
-      for (int d = 1; d < WAVE; d <<= 1) {
-        long long o = __shfl_up(iv, d);
-        if (lane_id() >= d) iv += o;
-      }
-      if (threadIdx.x < 1024 / WAVE) sh[threadIdx.x] = iv - sv;
+    long long before = carry, tot = carry;
+    for (int w = 0; w < RB_SCAN_T / WAVE; ++w) {
+      if (w < wv) before += sh[w];
+      tot += sh[w];
     }
-    __syncthreads();
-    const long long ex = carry + sh[wv] + incl - v;
-    if (t < cx.n_tiles) cx.tchunk[t] = ex;
-    __syncthreads();
-    // block total
-    if (threadIdx.x == 1023) sh[0] = ex + v;
-    __syncthreads();
-    carry = sh[0];
+    long long ex = before + incl - sum;
+#pragma unroll
+    for (int j = 0; j < RB_SCAN_V; ++j) {
+      if (t0 + j < cx.n_tiles) cx.tchunk[t0 + j] = ex;
+      ex += v[j];
+    }
+    carry = tot;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
