@@ -354,13 +354,13 @@ def cpu_baseline(cfg, state, budget_s=15.0):
                 build="gcc -O2, single-threaded FP64")
 
 
-def bench_full_scale(torch, steps, warmup, grow_to, max_grow):
+def bench_full_scale(torch, steps, warmup, grow_to, max_grow, region=None):
     """The full-scale gap (262144 cells, b = 0.2, caps 2e8), grown by the
     physics to at least grow_to particles, measured like the production gap."""
     from paper_2608_21920_amd import Gap, workloads
     cfg = dict(workloads.FULL)
     g = Gap(cfg)
-    res = measure_gap(g, torch, cfg, steps, warmup, grow_to, max_grow)
+    res = measure_gap(g, torch, cfg, steps, warmup, grow_to, max_grow, region=region)
     g.close()
     c0 = res["counts_before"]
     return dict(value=res["value"], unit="particle-steps/s", ms_per_step=res["ms_per_step"], steps=steps,
@@ -596,6 +596,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable window")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scale gap")
     ap.add_argument("--only-main", action="store_true", help="the production gap only (profiling runs)")
+    ap.add_argument("--only-full", action="store_true",
+                    help="the full-scale gap only, its timed steps inside the profiler region (profiling runs)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % a.gpus,
@@ -606,6 +608,11 @@ def main():
         return
     if a.only_main:
         a.no_cpu = a.no_batched = a.no_adjoint = a.no_full = True
+    if a.only_full:
+        import torch
+        full = bench_full_scale(torch, a.steps, a.warmup, a.grow_to, a.max_grow_steps, region=ProfilerRegion())
+        print(json.dumps({"full_scale": full}))
+        return
 
     import torch
     from paper_2608_21920_amd import Gap, workloads

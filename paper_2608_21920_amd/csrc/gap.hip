@@ -179,6 +179,7 @@ struct Store {
   int nclass = 1;                 // placement classes within a tile at a re-sort
   int32_t* ccount = nullptr;      // [nclass - 1][n_tiles]: particles of the leading classes per tile
   int32_t* ccur = nullptr;        // [nclass][n_tiles]: placement cursors
+  int32_t* wh = nullptr;          // [kGrid][RB_HW][nclass]: window counts of the re-sort's count workgroups
   uint8_t* cls = nullptr;         // class of each slot, decided by the count kernel
   uint16_t* chot = nullptr;       // photons: hot slots at the start of each sorted chunk
   long long* tchunk = nullptr;
@@ -601,6 +602,7 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst, hipStream_t s) {
   cx.chot = st.chot;
   cx.window = g->R;
   cx.tchunk = st.tchunk;
+  cx.wh = st.wh;
   cx.n_tiles = g->n_tiles;
   const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
   k_fill_i32<<<fgrid, 256, 0, s>>>(st.tcount, g->n_tiles, 0);
@@ -1182,8 +1184,9 @@ int alloc_store(gap_t* g, Store& st, int64_t cap, bool photon) {
   st.nclass = photon ? RbClasses<PhoBuf>::N : RbClasses<LepBuf>::N;
   st.ccount = (int32_t*)dalloc(g, (size_t)(st.nclass - 1) * g->n_tiles * 4);
   st.ccur = (int32_t*)dalloc(g, (size_t)st.nclass * g->n_tiles * 4);
+  st.wh = (int32_t*)dalloc(g, (size_t)kGrid * RB_HW * st.nclass * 4);
   st.cls = (uint8_t*)dalloc(g, (size_t)st.capacity);
-  if (!st.ccount || !st.ccur || !st.cls) return GAP_ENOMEM;
+  if (!st.ccount || !st.ccur || !st.cls || !st.wh) return GAP_ENOMEM;
   if (photon) {
     st.chot = (uint16_t*)dalloc(g, (n / CHUNK + 1) * 2);
     if (!st.chot) return GAP_ENOMEM;
