@@ -604,16 +604,24 @@ void rebucket_t(gap_t* g, Store& st, B src, B dst, hipStream_t s) {
   cx.tchunk = st.tchunk;
   cx.wh = st.wh;
   cx.n_tiles = g->n_tiles;
-  const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
-  k_fill_i32<<<fgrid, 256, 0, s>>>(st.tcount, g->n_tiles, 0);
-  k_fill_i32<<<fgrid, 256, 0, s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
+  // (the tile and class counts were cleared by rebucket_clear)
   k_rb_count<B><<<kGrid, TPB, 0, s>>>(cx);
   k_rb_scan<B><<<1, RB_SCAN_T, 0, s>>>(cx);
   k_rb_chunks<B><<<kGrid, 256, 0, s>>>(cx);
   k_rb_scatter<B><<<kGrid, TPB, 0, s>>>(cx);
-  k_rb_pad<B><<<kGrid, TPB, 0, s>>>(cx);
+  k_rb_pad<B><<<std::max(1, std::min(g->n_tiles, kGrid)), TPB, 0, s>>>(cx);
   k_rb_finish<B><<<1, 1, 0, s>>>(cx);
   st.cur ^= 1;
+}
+
+// Clears a store's tile and class counts for its re-sort.  Both stores' are
+// cleared on the caller's stream before the photon store's re-sort is forked
+// onto the second one: a small kernel issued beside the other store's full
+// count grid waited for a free CU for a quarter of a millisecond.
+void rebucket_clear(gap_t* g, Store& st) {
+  const int fgrid = std::max(1, std::min(1024, (g->n_tiles + 255) / 256));
+  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.tcount, g->n_tiles, 0);
+  k_fill_i32<<<fgrid, 256, 0, g->s>>>(st.ccount, (long long)(st.nclass - 1) * g->n_tiles, 0);
 }
 
 __global__ void k_count_resort(Tube* tubes, int n_tubes) {
@@ -642,6 +650,9 @@ void join_stores(gap_t* g, hipStream_t ps) {
 }
 
 void rebucket_all(gap_t* g) {
+  join_photon_side(g);
+  rebucket_clear(g, g->pho);
+  rebucket_clear(g, g->lep);
   hipStream_t ps = fork_stores(g);
   rebucket_t<PhoBuf>(g, g->pho, g->pho.pho(g->pho.cur), g->pho.pho(g->pho.cur ^ 1), ps);
   rebucket_t<LepBuf>(g, g->lep, g->lep.lep(g->lep.cur), g->lep.lep(g->lep.cur ^ 1), g->s);

@@ -2203,13 +2203,15 @@ __global__ __launch_bounds__(TPB) void k_rb_scatter(RbCtx<B> cx) {
   }
 }
 
+// The slots of the new layout past each tile's last particle, up to the end
+// of its last chunk, hold dead records (the scatter writes every other slot).
+// Workgroup b takes tiles b, b + G, ...: the work is the padding alone.
 template <class B>
 __global__ __launch_bounds__(TPB) void k_rb_pad(RbCtx<B> cx) {
-  const long long tot = cx.ctl->total_chunks_new * PPC;
-  for (long long q = blockIdx.x; q < tot; q += gridDim.x) {
-    const int t = cx.chunk_new[q / PPC];
-    const long long slot = q * TPB + threadIdx.x;
-    if (slot >= cx.tchunk[t] * CHUNK + cx.tcount[t]) rec_kill(cx.dst, slot);
+  for (int t = blockIdx.x; t < cx.n_tiles; t += gridDim.x) {
+    const long long hi = cx.tchunk[t + 1] * CHUNK;
+    for (long long slot = cx.tchunk[t] * CHUNK + cx.tcount[t] + threadIdx.x; slot < hi; slot += blockDim.x)
+      rec_kill(cx.dst, slot);
   }
 }
 
