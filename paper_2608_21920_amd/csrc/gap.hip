@@ -1422,7 +1422,7 @@ int build(gap_t* g, const gap_params* p, int n_tubes) {
       sb.start = (uint32_t*)dalloc(g, n * 4);
       sb.bmax = (uint32_t*)dalloc(g, (n / MX_ITEMS + 2) * 4);
       sb.flags = (uint32_t*)dalloc(g, (size_t)n_tubes * 4);
-      sb.gate = (uint32_t*)dalloc(g, 4);
+      sb.gate = (uint32_t*)dalloc(g, 8);
       sb.n = (long long*)dalloc(g, 8);
       if (!sb.bhist || !sb.dtot || !sb.live || !sb.start || !sb.bmax || !sb.flags || !sb.gate || !sb.n) return GAP_ENOMEM;
     }

@@ -23,7 +23,7 @@ struct SortBuf {
   uint32_t* start;      // per item: first index of its group
   uint32_t* bmax;       // per block of the max-scan: its maximum, then its carry
   uint32_t* flags;      // per tube: merge this step
-  uint32_t* gate;       // 0: no tube of the store can be over its threshold
+  uint32_t* gate;       // [0]: 0 when no tube of the store can be over its threshold; [1]: some tube is flagged
   long long* n;         // number of items
   int max_blocks;
 };
@@ -50,20 +50,29 @@ __device__ __forceinline__ uint32_t rec_group(const PhoBuf& b, uint32_t slot, ui
 // its threshold.  The check's counting and gathering kernels then return at
 // once (and the sort passes find nothing to sort).
 __global__ void k_merge_gate(const Ctl* ctl, double thresh_min, uint32_t* gate) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    *gate = (double)(ctl->n_sorted_chunks * CHUNK + ctl->tail) > thresh_min ? 1u : 0u;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    gate[0] = (double)(ctl->n_sorted_chunks * CHUNK + ctl->tail) > thresh_min ? 1u : 0u;
+    gate[1] = 0u;
+  }
 }
 
 // Per-tube decision: merge when the live count exceeds merge_frac * cap.
 __global__ void k_merge_flags(const long long* live, const double* thresh, uint32_t* flags, int n_tubes,
-                              const uint32_t* gate) {
+                              uint32_t* gate) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_tubes) flags[t] = (*gate != 0 && (double)live[t] > thresh[t]) ? 1u : 0u;
+  if (t < n_tubes) {
+    const bool f = gate[0] != 0 && (double)live[t] > thresh[t];
+    flags[t] = f ? 1u : 0u;
+    if (f) atomicOr(&gate[1], 1u);
+  }
 }
 
 // Gather the merge candidates (live particles of flagged tubes) with their
 // keys.  The order of the gathered list does not matter: the sort's full key
-// (group, id) is unique.  A workgroup takes MK_PIECES pieces of TPB slots at
+// (group, id) is unique.  With no tube flagged it returns at once (the store
+// may be over the smallest threshold without any tube over its own; reading
+// every particle for nothing took a millisecond in the QED-active
+// ensemble).  A workgroup takes MK_PIECES pieces of TPB slots at
 // a time and reserves their entries with one atomic on the list counter.
 // (One atomic per wave and piece, on the one counter, cost the photon store
 // of the QED-active ensemble 10 ms per merge.)
@@ -71,7 +80,7 @@ constexpr int MK_PIECES = 8;
 template <class B>
 __global__ __launch_bounds__(TPB) void k_merge_keys(B buf, const Ctl* ctl, const int32_t* chunk, const int32_t* tt,
                                                     const Tile* tiles, const Tube* tubes, SortBuf sb) {
-  if (*sb.gate == 0) return;
+  if (sb.gate[1] == 0) return;
   __shared__ int s_w[TPB / WAVE];
   __shared__ long long s_base;
   const long long nsc = ctl->n_sorted_chunks, S = nsc * CHUNK, tail = ctl->tail;
