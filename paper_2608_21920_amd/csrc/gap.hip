@@ -1086,7 +1086,9 @@ void join_photon_side(gap_t* g) {
 // snapshot, step index), sorted photon pass, conversion draws.  Lepton side
 // (caller's stream): sorted lepton pass, then, once the prologue is done,
 // the lepton and photon tail passes, the field update (which also takes the
-// photon tail snapshot of the next step) and the re-sort when due.
+// photon tail snapshot of the next step) and the re-sort when due.  The
+// re-sort and the merge check join the photon side and then run the two
+// stores side by side (fork_stores).
 //
 // The sides touch disjoint data: each pass reads its own store up to its
 // tail snapshot, births go past the snapshots, only leptons deposit charge,
