@@ -389,7 +389,7 @@ def _batched_totals(g, n_tubes):
     return tot
 
 
-def bench_batched(torch, plain_value, cfgs, label, ignite_steps=0, n_tubes=256, launch=None):
+def bench_batched(torch, plain_value, cfgs, label, ignite_steps=0, n_tubes=256, launch=None, region=None):
     """An ensemble of uneven tubes in one set of launches, autotuned, timed
     over graph replays of twice the re-sort interval (each replay starts from
     the same store layout, so one captured graph serves them all) and over as
@@ -425,11 +425,15 @@ def bench_batched(torch, plain_value, cfgs, label, ignite_steps=0, n_tubes=256, 
         torch.cuda.synchronize()
         ms_graph = e0.elapsed_time(e1)
         c1 = _batched_totals(g, n_tubes)
+        if region is not None:
+            region.resume()
         e0.record(s)
         g.step(2 * steps)
         e1.record(s)
         g.sync()
         torch.cuda.synchronize()
+        if region is not None:
+            region.pause()
         ms_eager = e0.elapsed_time(e1)
         c2 = _batched_totals(g, n_tubes)
         g.close()
@@ -450,6 +454,20 @@ def bench_batched(torch, plain_value, cfgs, label, ignite_steps=0, n_tubes=256, 
                 conv_eval_per_particle_step=round((b["conv"] - a["conv"]) / max(ps, 1), 4),
                 hbm_frac_whole_step=alg / (ms / 1e3) / 1e9 / PEAK_HBM_GBS,
                 vs_plain=value / plain_value if plain_value else None, config=label)
+
+
+def bench_qed_active(torch, plain_value, region=None):
+    """The 256 tubes of the batched recipe with the QED rescaled (the
+    cascade-heavy ensemble), timed after ignition."""
+    from paper_2608_21920_amd import workloads
+    return bench_batched(
+        torch, plain_value, workloads.batched_qed_active(workloads.batched_tubes(256, seed=1)), ignite_steps=400,
+        region=region,
+        label="256 tubes: cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q log-uniform in "
+              "[0.01, 0.3], ppc uniform in [4, 64] per species, seed 1; uniform e+- start, QED rescaled "
+              "(lambda~ x 3e3, R~ x 3e-3) so that emission, photon transport and conversion run, merge check every "
+              "32 steps above 70 % of the cap; "
+              "timed after 400 steps, past ignition, with its own autotuned launch shape")
 
 
 def bench_adjoint(torch, window=2000, ckpt=100):
@@ -596,6 +614,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable window")
     ap.add_argument("--no-full", action="store_true", help="skip the full-scale gap")
     ap.add_argument("--only-main", action="store_true", help="the production gap only (profiling runs)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="the QED-active ensemble only, its eager timed steps inside the profiler region (profiling runs)")
     ap.add_argument("--only-full", action="store_true",
                     help="the full-scale gap only, its timed steps inside the profiler region (profiling runs)")
     a = ap.parse_args()
@@ -608,6 +628,10 @@ def main():
         return
     if a.only_main:
         a.no_cpu = a.no_batched = a.no_adjoint = a.no_full = True
+    if a.only_batched:
+        import torch
+        print(json.dumps({"batched": bench_qed_active(torch, None, region=ProfilerRegion())}))
+        return
     if a.only_full:
         import torch
         full = bench_full_scale(torch, a.steps, a.warmup, a.grow_to, a.max_grow_steps, region=ProfilerRegion())
@@ -672,13 +696,7 @@ def main():
             label="256 tubes of the batched recipe with physical QED (R_curv 1e7 cm): no emission in the timed "
                   "window")
         torch.cuda.empty_cache()
-        out["batched"] = bench_batched(
-            torch, res["value"], workloads.batched_qed_active(recipe), ignite_steps=400,
-            label="256 tubes: cells uniform in [2048, 16384], alpha uniform in [-1, 2], B/B_Q log-uniform in "
-                  "[0.01, 0.3], ppc uniform in [4, 64] per species, seed 1; uniform e+- start, QED rescaled "
-                  "(lambda~ x 3e3, R~ x 3e-3) so that emission, photon transport and conversion run, merge check every "
-                  "32 steps above 70 % of the cap; "
-                  "timed after 400 steps, past ignition, with its own autotuned launch shape")
+        out["batched"] = bench_qed_active(torch, res["value"])
         out["batched_physical_qed"] = phys
         torch.cuda.empty_cache()
     if not a.no_adjoint:
