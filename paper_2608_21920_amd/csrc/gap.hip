@@ -701,13 +701,14 @@ void merge_store(gap_t* g, Store& st, B buf, SortBuf& sb, const double* thresh, 
   k_fill_i64<<<std::max(1, t1), 256, 0, s>>>(sb.live, g->n_tubes, 0);
   k_count_live<B><<<kGrid, TPB, 0, s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, sb.live, g->n_tubes,
                                            sb.gate);
-  k_merge_flags<<<t1, 256, 0, s>>>(sb.live, thresh, sb.flags, g->n_tubes, sb.gate);
+  // (one-wave workgroups: they start beside the other store's kernels)
+  k_merge_flags<<<(g->n_tubes + WAVE - 1) / WAVE, WAVE, 0, s>>>(sb.live, thresh, sb.flags, g->n_tubes, sb.gate);
   k_fill_i64<<<1, 64, 0, s>>>(sb.n, 1, 0);
   k_merge_keys<B><<<kGrid, TPB, 0, s>>>(buf, st.ctl, st.chunk[st.cur], st.tt, g->tiles, g->tubes, sb);
   int src = 0;
   for (int pass = 0; pass < 12; ++pass) {
     k_rs_hist<<<kGrid, RS_TPB, 0, s>>>(sb, src, pass);
-    k_rs_scan<<<RS_SCAN_WG, 1024, 0, s>>>(sb);
+    k_rs_scan<<<RS_SCAN_WG, RS_SCAN_T, 0, s>>>(sb);
     k_rs_scatter<<<kGrid, RS_TPB, 0, s>>>(sb, src, pass);
     src ^= 1;
   }

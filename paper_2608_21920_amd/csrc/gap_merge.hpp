@@ -170,10 +170,14 @@ __global__ __launch_bounds__(RS_TPB) void k_rs_hist(SortBuf sb, int src, int pas
 // d.  A thread takes a run of consecutive blocks, so a row is read twice and
 // written once.  (One workgroup over all 256 rows took a quarter of a
 // millisecond per pass at 3e8 items; a workgroup per digit cost a gated
-// merge check, which finds nothing to sort, 3 us per launch.)
+// merge check, which finds nothing to sort, 3 us per launch.)  Workgroups
+// of RS_SCAN_T threads start beside the other store's sort kernels, which
+// run at the same time on the second stream; 1024-thread ones waited up to
+// 0.8 ms for an idle CU in the QED-active ensemble.
 constexpr int RS_SCAN_WG = 64;
-__global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
-  __shared__ uint32_t sh[1024 / WAVE];
+constexpr int RS_SCAN_T = 256;
+__global__ __launch_bounds__(RS_SCAN_T) void k_rs_scan(SortBuf sb) {
+  __shared__ uint32_t sh[RS_SCAN_T / WAVE];
   const long long n = *sb.n;
   const int nb = (int)((n + RS_ITEMS - 1) / RS_ITEMS);
   if (nb == 0) {
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
       if (threadIdx.x == 0) sb.dtot[d] = 0;
     return;
   }
-  const int per = (nb + 1023) / 1024;
+  const int per = (nb + RS_SCAN_T - 1) / RS_SCAN_T;
   const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
   const int wv = (int)threadIdx.x / WAVE;
   for (int d = (int)blockIdx.x; d < 256; d += gridDim.x) {
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_rs_scan(SortBuf sb) {
       row[b] = run;
       run += v;
     }
-    if (threadIdx.x == 1023) sb.dtot[d] = run;
+    if (threadIdx.x == RS_SCAN_T - 1) sb.dtot[d] = run;
     __syncthreads();
   }
 }
